@@ -1,0 +1,155 @@
+"""Python access to the CPU oracle (``oracle/liboracle.so``).
+
+Test infrastructure only: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it.  The product package never imports this module.
+
+Each function takes the arrays of one layout (any numeric dtype for the
+coordinates; they are passed as float64 holding integers) and returns Python
+numbers.  The library is built on first use if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_i64 = C.c_int64
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_u64p = C.POINTER(C.c_uint64)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.oracle_node_occlusion.argtypes = [_dp, _dp, _i64, C.c_double, _u64p]
+        L.oracle_edge_crossing.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _u64p, _u64p]
+        L.oracle_crossing_angle.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, C.c_double,
+                                            _dp, _u64p, _dp]
+        L.oracle_crossings_of_edges.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, C.c_double,
+                                                _i64p, _i64, _u64p, _dp]
+        L.oracle_min_angle.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _dp, _dp, _u64p]
+        L.oracle_edge_length_variation.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _dp, _dp]
+        L.oracle_segment_pair.argtypes = [_dp, C.c_double, C.POINTER(C.c_int), _dp]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise OracleError(f"{what} failed with status {rc}")
+
+
+def _unpack(L):
+    x, y, s, d = _f64(L.x), _f64(L.y), _i32(L.src), _i32(L.dst)
+    return x, y, s, d
+
+
+def node_occlusion(x, y, diameter: float) -> int:
+    x, y = _f64(x), _f64(y)
+    out = C.c_uint64()
+    _check(lib().oracle_node_occlusion(_p(x, _dp), _p(y, _dp), x.shape[0],
+                                       float(diameter), C.byref(out)), "node_occlusion")
+    return int(out.value)
+
+
+def edge_crossing(x, y, src, dst) -> tuple[int, int]:
+    """(closed crossing count, proper crossing count)."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    c, p = C.c_uint64(), C.c_uint64()
+    _check(lib().oracle_edge_crossing(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                      _p(d, _i32p), s.shape[0], C.byref(c), C.byref(p)),
+           "edge_crossing")
+    return int(c.value), int(p.value)
+
+
+def crossing_angle(x, y, src, dst, ideal_angle: float) -> tuple[float, int, float]:
+    """(metric E_ca, crossing count, sum of |ideal - a| / ideal)."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    met, cnt, sm = C.c_double(), C.c_uint64(), C.c_double()
+    _check(lib().oracle_crossing_angle(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                       _p(d, _i32p), s.shape[0], float(ideal_angle),
+                                       C.byref(met), C.byref(cnt), C.byref(sm)),
+           "crossing_angle")
+    return float(met.value), int(cnt.value), float(sm.value)
+
+
+def crossings_of_edges(x, y, src, dst, ideal_angle: float, which):
+    """Per listed edge: (number of crossing edges, sum of |ideal - a|)."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    w = np.ascontiguousarray(np.asarray(which, dtype=np.int64))
+    cnt = np.zeros(w.shape[0], dtype=np.uint64)
+    dev = np.zeros(w.shape[0], dtype=np.float64)
+    _check(lib().oracle_crossings_of_edges(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                           _p(d, _i32p), s.shape[0], float(ideal_angle),
+                                           _p(w, _i64p), w.shape[0], _p(cnt, _u64p),
+                                           _p(dev, _dp)), "crossings_of_edges")
+    return cnt, dev
+
+
+def min_angle(x, y, src, dst) -> tuple[float, float, int]:
+    """(metric M_a, sum of d_v, number of vertices with degree >= 1)."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    met, sdv, used = C.c_double(), C.c_double(), C.c_uint64()
+    _check(lib().oracle_min_angle(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                  _p(d, _i32p), s.shape[0], C.byref(met), C.byref(sdv),
+                                  C.byref(used)), "min_angle")
+    return float(met.value), float(sdv.value), int(used.value)
+
+
+def edge_length_variation(x, y, src, dst) -> tuple[float, float]:
+    """(metric M_l, mean edge length)."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    met, mu = C.c_double(), C.c_double()
+    _check(lib().oracle_edge_length_variation(_p(x, _dp), _p(y, _dp), x.shape[0],
+                                              _p(s, _i32p), _p(d, _i32p), s.shape[0],
+                                              C.byref(met), C.byref(mu)),
+           "edge_length_variation")
+    return float(met.value), float(mu.value)
+
+
+def segment_pair(p, ideal_angle: float = 1.2217304763960306) -> tuple[int, float]:
+    """Crossing kind (0 none, 1 touching/overlapping, 2 proper) and the acute
+    line angle of two segments p = (x0,y0,x1,y1, x2,y2,x3,y3)."""
+    a = _f64(p)
+    kind, ang = C.c_int(), C.c_double()
+    _check(lib().oracle_segment_pair(_p(a, _dp), float(ideal_angle), C.byref(kind),
+                                     C.byref(ang)), "segment_pair")
+    return int(kind.value), float(ang.value)
+
+
+def all_metrics(L) -> dict:
+    """The five metrics of one layout (``paper_2411_09809_amd.gen.Layout``)."""
+    x, y, s, d = _unpack(L)
+    closed, proper = edge_crossing(x, y, s, d)
+    eca, cnt, devsum = crossing_angle(x, y, s, d, L.ideal_angle)
+    ma, sdv, used = min_angle(x, y, s, d)
+    ml, mu = edge_length_variation(x, y, s, d)
+    return dict(node_occlusion=node_occlusion(x, y, L.diameter), edge_crossing=closed,
+                proper_crossing=proper, crossing_angle=eca, crossing_dev_sum=devsum,
+                min_angle=ma, min_angle_sum_dv=sdv, min_angle_n_used=used,
+                edge_length_variation=ml, mean_edge_length=mu)

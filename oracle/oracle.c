@@ -1,0 +1,378 @@
+/*
+ * CPU oracle for the five readability metrics of "Scalable Readability
+ * Evaluation for Graph Layouts" (arXiv 2411.09809).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  The product library
+ * never links, loads or calls it, and the two share no source.
+ *
+ * Everything here is the plain definition, written out as nested loops:
+ *   - integer predicates in int64 (coordinates are integers with |c| <= 2^20,
+ *     so every difference is below 2^21 and every 2x2 determinant below 2^43);
+ *   - floating-point metrics in double, with compensated (Neumaier) sums;
+ *   - OpenMP only splits the outer loop into independent rows; per-row
+ *     results are combined afterwards in row order, so results do not depend
+ *     on the thread count.
+ *
+ * Readings taken where the paper is silent or ambiguous (each one is listed
+ * with its reason in the design notes):
+ *   R1 occlusion compares the squared distance with the squared diameter
+ *      d = 2r, strictly (Algorithm 1), each unordered pair once;
+ *   R2 edge pairs that share an endpoint id are not crossings;
+ *   R3 closed segments: the paper's two CCW products <= 0, and when both
+ *      products are zero the bounding boxes must also meet (collinear pieces
+ *      that do not touch are not crossings);
+ *   R5 the crossing angle is the acute angle between the two lines,
+ *      atan2(|cross|, |dot|), in [0, pi/2];
+ *   R6 the deviation is |ideal - a| / ideal (Algorithm 5's absolute value);
+ *   R7 with no crossing the crossing-angle metric is 1;
+ *   R9 the minimum-angle metric averages d_v over vertices of degree >= 1;
+ *   R10 the angle at v is that of the direction v -> u, in [0, 2 pi);
+ *   R11 N_e = |E|; with |E| < 2 or zero mean length the variation is 0.
+ *
+ * Status codes: 0 ok, 1 bad argument, 2 coordinate not an integer in range,
+ * 3 edge end out of range.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+#define COORD_LIMIT 1048576.0 /* 2^20 */
+
+/* ------------------------------------------------------------ helpers */
+
+typedef struct { double s, c; } nsum;   /* Neumaier compensated sum */
+
+static void nsum_add(nsum *a, double v) {
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+static double nsum_get(const nsum *a) { return a->s + a->c; }
+
+static int to_int_coords(const double *x, const double *y, int64_t n,
+                         int64_t **ix, int64_t **iy) {
+    *ix = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    *iy = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        double a = x[i], b = y[i];
+        if (!(a == floor(a)) || !(b == floor(b)) || fabs(a) > COORD_LIMIT ||
+            fabs(b) > COORD_LIMIT) {
+            free(*ix); free(*iy);
+            return 2;
+        }
+        (*ix)[i] = (int64_t)a;
+        (*iy)[i] = (int64_t)b;
+    }
+    return 0;
+}
+
+static int check_edges(const int32_t *src, const int32_t *dst, int64_t m, int64_t n) {
+    for (int64_t e = 0; e < m; ++e)
+        if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return 3;
+    return 0;
+}
+
+/* ------------------------------------------- Algorithm 1: node occlusion */
+
+/* Exact test  dist2 < d*d  for an integer dist2 >= 0 and a double d >= 0.
+ * d = M * 2^k with M a 53-bit integer, so d^2 = M^2 * 2^(2k) is compared
+ * with dist2 in 128-bit integer arithmetic. */
+static int less_than_square(int64_t dist2, double d) {
+    if (d <= 0.0) return 0;
+    int e;
+    double f = frexp(d, &e);                      /* d = f 2^e, f in [0.5,1) */
+    unsigned __int128 M = (unsigned __int128)(uint64_t)ldexp(f, 53);
+    int k2 = 2 * (e - 53);                        /* d^2 = M^2 2^k2 */
+    unsigned __int128 M2 = M * M;                 /* < 2^106 */
+    unsigned __int128 D = (unsigned __int128)(uint64_t)dist2;
+    if (k2 >= 0) return 1;        /* d >= 2^52: d^2 exceeds every squared distance */
+    int s = -k2;
+    if (s >= 127) return D == 0 && M2 != 0;
+    unsigned __int128 q = M2 >> s;
+    unsigned __int128 r = M2 - (q << s);
+    return D < q || (D == q && r != 0);
+}
+
+int oracle_node_occlusion(const double *x, const double *y, int64_t n,
+                          double diameter, uint64_t *out_count) {
+    if (n < 0 || !out_count || !(diameter >= 0.0) || isinf(diameter)) return 1;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    uint64_t total = 0;
+    #pragma omp parallel for schedule(dynamic, 64) reduction(+:total)
+    for (int64_t v = 0; v < n; ++v) {
+        for (int64_t u = v + 1; u < n; ++u) {             /* v < u */
+            int64_t dx = ix[v] - ix[u], dy = iy[v] - iy[u];
+            if (less_than_square(dx * dx + dy * dy, diameter)) total += 1;
+        }
+    }
+    free(ix); free(iy);
+    *out_count = total;
+    return 0;
+}
+
+/* --------------------------------------------- Algorithm 4: edge crossing */
+
+/* CCW(A,B,C): sign of the cross product CA x AB (the procedure of
+ * Algorithm 4). */
+static int ccw(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t cx, int64_t cy) {
+    int64_t cax = ax - cx, cay = ay - cy;
+    int64_t abx = bx - ax, aby = by - ay;
+    int64_t c = cax * aby - cay * abx;
+    return (c > 0) - (c < 0);
+}
+
+static int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+static int64_t max64(int64_t a, int64_t b) { return a > b ? a : b; }
+
+/* Crossing test of two edges (v1,u1) and (v2,u2) given by node ids.
+ * Returns 0 (no crossing), 1 (crossing, segments touch or overlap),
+ * 2 (proper crossing: each segment strictly separates the other's ends). */
+static int edge_pair_crossing(const int64_t *ix, const int64_t *iy,
+                              int32_t v1, int32_t u1, int32_t v2, int32_t u2) {
+    /* R2: pairs sharing an endpoint id are incident, not crossing */
+    if (v1 == v2 || v1 == u2 || u1 == v2 || u1 == u2) return 0;
+    int c1 = ccw(ix[v1], iy[v1], ix[u1], iy[u1], ix[v2], iy[v2]);
+    int c2 = ccw(ix[v1], iy[v1], ix[u1], iy[u1], ix[u2], iy[u2]);
+    int c3 = ccw(ix[v2], iy[v2], ix[u2], iy[u2], ix[v1], iy[v1]);
+    int c4 = ccw(ix[v2], iy[v2], ix[u2], iy[u2], ix[u1], iy[u1]);
+    int p12 = c1 * c2, p34 = c3 * c4;
+    if (p12 > 0 || p34 > 0) return 0;              /* Algorithm 4's <= 0 test */
+    if (p12 < 0 && p34 < 0) return 2;
+    if (p12 == 0 && p34 == 0) {                    /* R3: boxes must meet */
+        int64_t ax0 = min64(ix[v1], ix[u1]), ax1 = max64(ix[v1], ix[u1]);
+        int64_t ay0 = min64(iy[v1], iy[u1]), ay1 = max64(iy[v1], iy[u1]);
+        int64_t bx0 = min64(ix[v2], ix[u2]), bx1 = max64(ix[v2], ix[u2]);
+        int64_t by0 = min64(iy[v2], iy[u2]), by1 = max64(iy[v2], iy[u2]);
+        if (max64(ax0, bx0) > min64(ax1, bx1)) return 0;
+        if (max64(ay0, by0) > min64(ay1, by1)) return 0;
+    }
+    return 1;
+}
+
+int oracle_edge_crossing(const double *x, const double *y, int64_t n,
+                         const int32_t *src, const int32_t *dst, int64_t m,
+                         uint64_t *out_count, uint64_t *out_proper) {
+    if (n < 0 || m < 0 || !out_count) return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    uint64_t closed = 0, proper = 0;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+:closed, proper)
+    for (int64_t e = 0; e < m; ++e) {
+        for (int64_t f = e + 1; f < m; ++f) {          /* each unordered pair once */
+            int r = edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f]);
+            closed += (r != 0);
+            proper += (r == 2);
+        }
+    }
+    free(ix); free(iy);
+    *out_count = closed;
+    if (out_proper) *out_proper = proper;
+    return 0;
+}
+
+/* ------------------------------------ Algorithm 5: edge crossing angle */
+
+/* Acute angle between the lines of two edges, from exact integer cross and
+ * dot products of their direction vectors (R5). */
+static double crossing_angle(const int64_t *ix, const int64_t *iy,
+                             int32_t v1, int32_t u1, int32_t v2, int32_t u2) {
+    int64_t ax = ix[u1] - ix[v1], ay = iy[u1] - iy[v1];
+    int64_t bx = ix[u2] - ix[v2], by = iy[u2] - iy[v2];
+    int64_t cr = ax * by - ay * bx;
+    int64_t dt = ax * bx + ay * by;
+    return atan2(fabs((double)cr), fabs((double)dt));
+}
+
+int oracle_crossing_angle(const double *x, const double *y, int64_t n,
+                          const int32_t *src, const int32_t *dst, int64_t m,
+                          double ideal_angle, double *out_metric,
+                          uint64_t *out_count, double *out_dev_sum) {
+    if (n < 0 || m < 0 || !out_metric || !(ideal_angle > 0.0)) return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    double *row_sum = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
+    uint64_t count = 0;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+:count)
+    for (int64_t e = 0; e < m; ++e) {
+        nsum acc = {0.0, 0.0};
+        for (int64_t f = e + 1; f < m; ++f) {
+            if (!edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) continue;
+            double a = crossing_angle(ix, iy, src[e], dst[e], src[f], dst[f]);
+            nsum_add(&acc, fabs(ideal_angle - a) / ideal_angle);      /* R6 */
+            count += 1;
+        }
+        row_sum[e] = nsum_get(&acc);
+    }
+    nsum tot = {0.0, 0.0};
+    for (int64_t e = 0; e < m; ++e) nsum_add(&tot, row_sum[e]);
+    double s = nsum_get(&tot);
+    free(row_sum); free(ix); free(iy);
+    *out_metric = count ? 1.0 - s / (double)count : 1.0;               /* R7 */
+    if (out_count) *out_count = count;
+    if (out_dev_sum) *out_dev_sum = s;
+    return 0;
+}
+
+/* Per-edge view of Algorithms 4 and 5: for each listed edge e, the number of
+ * edges crossing it and the sum of |ideal - a| over those crossings (without
+ * the division by the ideal angle).  O(|E|) per listed edge. */
+int oracle_crossings_of_edges(const double *x, const double *y, int64_t n,
+                              const int32_t *src, const int32_t *dst, int64_t m,
+                              double ideal_angle, const int64_t *which, int64_t k,
+                              uint64_t *out_count, double *out_dev) {
+    if (n < 0 || m < 0 || k < 0 || !which || !out_count) return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    for (int64_t i = 0; i < k; ++i)
+        if (which[i] < 0 || which[i] >= m) return 1;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < k; ++i) {
+        int64_t e = which[i];
+        uint64_t c = 0;
+        nsum acc = {0.0, 0.0};
+        for (int64_t f = 0; f < m; ++f) {
+            if (f == e) continue;
+            if (!edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) continue;
+            c += 1;
+            nsum_add(&acc, fabs(ideal_angle - crossing_angle(ix, iy, src[e], dst[e], src[f], dst[f])));
+        }
+        out_count[i] = c;
+        if (out_dev) out_dev[i] = nsum_get(&acc);
+    }
+    free(ix); free(iy);
+    return 0;
+}
+
+/* ------------------------------------------ Algorithm 2: minimum angle */
+
+static int cmp_double(const void *a, const void *b) {
+    double p = *(const double *)a, q = *(const double *)b;
+    return (p > q) - (p < q);
+}
+
+/* GetMinAngle: sort, then the smallest gap between neighbours, the wrap-around
+ * gap 2 pi - a_n + a_1 included. */
+static double get_min_angle(double *a, int64_t k) {
+    const double two_pi = 2.0 * M_PI;
+    qsort(a, (size_t)k, sizeof(double), cmp_double);
+    double best = two_pi - a[k - 1] + a[0];
+    for (int64_t i = 1; i < k; ++i) {
+        double g = a[i] - a[i - 1];
+        if (g < best) best = g;
+    }
+    return best;
+}
+
+int oracle_min_angle(const double *x, const double *y, int64_t n,
+                     const int32_t *src, const int32_t *dst, int64_t m,
+                     double *out_metric, double *out_sum_dv, uint64_t *out_n_used) {
+    if (n < 0 || m < 0 || !out_metric) return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    /* the incident edges of every vertex (what aggregateMessages collects) */
+    int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < m; ++e) { deg[src[e]]++; deg[dst[e]]++; }
+    int64_t *start = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t v = 0; v < n; ++v) start[v + 1] = start[v] + deg[v];
+    int64_t *fill = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+    for (int64_t e = 0; e < m; ++e) {
+        int32_t a = src[e], b = dst[e];
+        nbr[start[a] + fill[a]++] = b;
+        nbr[start[b] + fill[b]++] = a;
+    }
+    double *dv = (double *)calloc((size_t)n + 1, sizeof(double));
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t k = deg[v];
+        if (k == 0) continue;
+        double *ang = (double *)malloc(sizeof(double) * (size_t)k);
+        for (int64_t i = 0; i < k; ++i) {
+            int32_t u = nbr[start[v] + i];
+            double a = atan2((double)(iy[u] - iy[v]), (double)(ix[u] - ix[v]));
+            if (a < 0.0) a += 2.0 * M_PI;                             /* R10 */
+            ang[i] = a;
+        }
+        double ideal = 2.0 * M_PI / (double)k;                        /* phi(v) */
+        dv[v] = (ideal - get_min_angle(ang, k)) / ideal;
+        free(ang);
+    }
+    nsum tot = {0.0, 0.0};
+    uint64_t used = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (deg[v] > 0) { nsum_add(&tot, dv[v]); used++; }
+    double s = nsum_get(&tot);
+    *out_metric = used ? 1.0 - s / (double)used : 1.0;                /* R9 */
+    if (out_sum_dv) *out_sum_dv = s;
+    if (out_n_used) *out_n_used = used;
+    free(deg); free(start); free(fill); free(nbr); free(dv); free(ix); free(iy);
+    return 0;
+}
+
+/* ----------------------------------- Algorithm 3: edge length variation */
+
+int oracle_edge_length_variation(const double *x, const double *y, int64_t n,
+                                 const int32_t *src, const int32_t *dst, int64_t m,
+                                 double *out_metric, double *out_mean) {
+    if (n < 0 || m < 0 || !out_metric) return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    double *len = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    nsum s1 = {0.0, 0.0};
+    for (int64_t e = 0; e < m; ++e) {
+        int64_t dx = ix[dst[e]] - ix[src[e]], dy = iy[dst[e]] - iy[src[e]];
+        len[e] = sqrt((double)(dx * dx + dy * dy));
+        nsum_add(&s1, len[e]);
+    }
+    double Ne = (double)m;                                            /* R11 */
+    double mu = m ? nsum_get(&s1) / Ne : 0.0;
+    nsum s2 = {0.0, 0.0};
+    for (int64_t e = 0; e < m; ++e) {
+        double d = len[e] - mu;
+        nsum_add(&s2, d * d);
+    }
+    double metric = 0.0;
+    if (m >= 2 && mu > 0.0) {
+        double la = sqrt(nsum_get(&s2) / (Ne * mu * mu));
+        metric = la / sqrt(Ne - 1.0);
+    }
+    *out_metric = metric;
+    if (out_mean) *out_mean = mu;
+    free(len); free(ix); free(iy);
+    return 0;
+}
+
+/* ------------------------------------------------ pairwise test helpers */
+
+/* The crossing and angle tests of one pair of segments with four distinct
+ * endpoints (used by the tests to pin the predicate on exhaustive lattices). */
+int oracle_segment_pair(const double *p, double ideal_angle, int *out_kind,
+                        double *out_angle) {
+    double x[4] = {p[0], p[2], p[4], p[6]};
+    double y[4] = {p[1], p[3], p[5], p[7]};
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, 4, &ix, &iy);
+    if (st) return st;
+    *out_kind = edge_pair_crossing(ix, iy, 0, 1, 2, 3);
+    if (out_angle) *out_angle = crossing_angle(ix, iy, 0, 1, 2, 3);
+    (void)ideal_angle;
+    free(ix); free(iy);
+    return 0;
+}

@@ -1,0 +1,29 @@
+/* CPU oracle of the readability metrics -- test infrastructure only.
+ * Coordinates are passed as doubles holding integers with |c| <= 2^20.
+ * All functions return 0 on success (see oracle.c for the other codes). */
+#ifndef RB_ORACLE_H
+#define RB_ORACLE_H
+#include <stdint.h>
+
+int oracle_node_occlusion(const double *x, const double *y, int64_t n,
+                          double diameter, uint64_t *out_count);
+int oracle_edge_crossing(const double *x, const double *y, int64_t n,
+                         const int32_t *src, const int32_t *dst, int64_t m,
+                         uint64_t *out_count, uint64_t *out_proper);
+int oracle_crossing_angle(const double *x, const double *y, int64_t n,
+                          const int32_t *src, const int32_t *dst, int64_t m,
+                          double ideal_angle, double *out_metric,
+                          uint64_t *out_count, double *out_dev_sum);
+int oracle_crossings_of_edges(const double *x, const double *y, int64_t n,
+                              const int32_t *src, const int32_t *dst, int64_t m,
+                              double ideal_angle, const int64_t *which, int64_t k,
+                              uint64_t *out_count, double *out_dev);
+int oracle_min_angle(const double *x, const double *y, int64_t n,
+                     const int32_t *src, const int32_t *dst, int64_t m,
+                     double *out_metric, double *out_sum_dv, uint64_t *out_n_used);
+int oracle_edge_length_variation(const double *x, const double *y, int64_t n,
+                                 const int32_t *src, const int32_t *dst, int64_t m,
+                                 double *out_metric, double *out_mean);
+int oracle_segment_pair(const double *p, double ideal_angle, int *out_kind,
+                        double *out_angle);
+#endif

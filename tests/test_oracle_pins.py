@@ -1,0 +1,433 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+* exact rational geometry (Python ``fractions``) on exhaustive lattices;
+* closed forms (K_n in convex position, two-row K_{m,n}, lattice occlusion);
+* hand-worked cases stored in ``tests/golden/hand_cases.json``;
+* Eq. (1)'s eight angle categories (Section 3.2.3) as a second route to the
+  per-edge crossing-angle sums;
+* invariants under integer similarity maps, relabelling and reordering;
+* the classical 25/108 crossing probability of random segments.
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2411_09809_amd import gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")
+IDEAL = 70.0 * math.pi / 180.0
+
+
+# ---------------------------------------------------------------- exact geometry
+
+def _cross(ax, ay, bx, by):
+    return ax * by - ay * bx
+
+
+def rational_segment_relation(P0, P1, Q0, Q1):
+    """0: disjoint, 1: closed segments meet, 2: they cross at one interior
+    point of both.  Parametric intersection in exact rationals."""
+    rx, ry = P1[0] - P0[0], P1[1] - P0[1]
+    qx, qy = Q1[0] - Q0[0], Q1[1] - Q0[1]
+    wx, wy = Q0[0] - P0[0], Q0[1] - P0[1]
+    den = _cross(rx, ry, qx, qy)
+    if den != 0:
+        s = Fraction(_cross(wx, wy, qx, qy), den)
+        t = Fraction(_cross(wx, wy, rx, ry), den)
+        if 0 < s < 1 and 0 < t < 1:
+            return 2
+        return 1 if (0 <= s <= 1 and 0 <= t <= 1) else 0
+    # parallel, or at least one segment is a single point
+
+    def on_segment(A, B, X):
+        ux, uy = B[0] - A[0], B[1] - A[1]
+        vx, vy = X[0] - A[0], X[1] - A[1]
+        if _cross(ux, uy, vx, vy) != 0:
+            return False
+        if ux == 0 and uy == 0:
+            return vx == 0 and vy == 0
+        d = ux * vx + uy * vy
+        return 0 <= d <= ux * ux + uy * uy
+
+    if rx == 0 and ry == 0:
+        return int(on_segment(Q0, Q1, P0))
+    if qx == 0 and qy == 0:
+        return int(on_segment(P0, P1, Q0))
+    if _cross(rx, ry, wx, wy) != 0:
+        return 0                                        # parallel, distinct lines
+    rr = rx * rx + ry * ry
+    t0 = Fraction(wx * rx + wy * ry, rr)
+    t1 = Fraction((Q1[0] - P0[0]) * rx + (Q1[1] - P0[1]) * ry, rr)
+    lo, hi = min(t0, t1), max(t0, t1)
+    return int(hi >= 0 and lo <= 1)
+
+
+def acos_angle(P0, P1, Q0, Q1):
+    """Acute angle between two lines via arccos of the normalised |dot|."""
+    rx, ry = P1[0] - P0[0], P1[1] - P0[1]
+    qx, qy = Q1[0] - Q0[0], Q1[1] - Q0[1]
+    nr, nq = math.hypot(rx, ry), math.hypot(qx, qy)
+    if nr == 0 or nq == 0:
+        return 0.0
+    c = min(1.0, abs(rx * qx + ry * qy) / (nr * nq))
+    return math.acos(c)
+
+
+def brute_layout(x, y, src, dst, ideal=IDEAL):
+    """Exact rational evaluation of closed/proper counts and the crossing
+    angle metric of a (small) layout."""
+    pts = [(int(a), int(b)) for a, b in zip(x, y)]
+    closed = proper = 0
+    dev = 0.0
+    for e, f in itertools.combinations(range(len(src)), 2):
+        ids = {int(src[e]), int(dst[e])} & {int(src[f]), int(dst[f])}
+        if ids:
+            continue
+        r = rational_segment_relation(pts[src[e]], pts[dst[e]], pts[src[f]], pts[dst[f]])
+        if r:
+            closed += 1
+            proper += r == 2
+            dev += abs(ideal - acos_angle(pts[src[e]], pts[dst[e]], pts[src[f]], pts[dst[f]])) / ideal
+    eca = 1.0 - dev / closed if closed else 1.0
+    return closed, proper, eca
+
+
+# ---------------------------------------------------------------- predicate pins
+
+def test_segment_predicate_exhaustive_4x4_lattice(orc):
+    """All 65,536 ordered pairs of segments with ends on a 4x4 lattice,
+    degenerate and collinear ones included."""
+    pts = [(i, j) for i in range(4) for j in range(4)]
+    segs = [(a, b) for a in pts for b in pts]
+    mism = 0
+    kinds = [0, 0, 0]
+    for (P0, P1) in segs:
+        for (Q0, Q1) in segs:
+            k, _ = orc.segment_pair([*P0, *P1, *Q0, *Q1])
+            r = rational_segment_relation(P0, P1, Q0, Q1)
+            kinds[r] += 1
+            mism += k != r
+    assert mism == 0
+    assert min(kinds) > 1000          # every outcome is well represented
+
+
+def test_segment_predicate_random_wide_coords(orc):
+    """Random segments near the coordinate limit (|c| <= 2^20) with forced
+    collinear and touching configurations."""
+    rng = np.random.default_rng(7)
+    lim = 1 << 20
+    for trial in range(3000):
+        P0 = rng.integers(-lim, lim + 1, size=2)
+        P1 = rng.integers(-lim, lim + 1, size=2)
+        mode = trial % 4
+        if mode == 0:
+            Q0, Q1 = rng.integers(-lim, lim + 1, size=2), rng.integers(-lim, lim + 1, size=2)
+        else:
+            # points on the line through P0, P1 (collinear or touching cases)
+            d = P1 - P0
+            g = math.gcd(int(d[0]), int(d[1])) or 1
+            step = d // g
+            t = rng.integers(-g, 2 * g + 1, size=2)
+            Q0 = P0 + t[0] * step
+            Q1 = P0 + t[1] * step if mode == 1 else rng.integers(-lim, lim + 1, size=2)
+            if np.abs(Q0).max() > lim or np.abs(Q1).max() > lim:
+                continue
+        k, a = orc.segment_pair([*P0, *P1, *Q0, *Q1])
+        r = rational_segment_relation(tuple(map(int, P0)), tuple(map(int, P1)),
+                                      tuple(map(int, Q0)), tuple(map(int, Q1)))
+        assert k == r, (P0, P1, Q0, Q1)
+        ref = acos_angle(tuple(map(int, P0)), tuple(map(int, P1)), tuple(map(int, Q0)), tuple(map(int, Q1)))
+        assert abs(a - ref) < 2e-7
+
+
+def test_oracle_matches_rational_brute_force_on_small_layouts(orc):
+    """Whole-layout counts and E_ca against the rational evaluation, on
+    crowded layouts (tiny coordinate range, many degeneracies)."""
+    rng = np.random.default_rng(11)
+    for trial in range(25):
+        n = int(rng.integers(5, 14))
+        m = int(rng.integers(2, min(30, n * (n - 1) // 2)))
+        x = rng.integers(0, 5, size=n)
+        y = rng.integers(0, 5, size=n)
+        s, d = gen.distinct_random_edges(rng, n, m)
+        c, p = orc.edge_crossing(x, y, s, d)
+        eca, cnt, _ = orc.crossing_angle(x, y, s, d, IDEAL)
+        bc, bp, beca = brute_layout(x, y, s, d)
+        assert (c, p) == (bc, bp)
+        assert cnt == bc
+        assert abs(eca - beca) < 1e-7
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", range(4, 11))
+def test_complete_graph_convex_position(orc, n):
+    L = gen.complete_convex(n)
+    c, p = orc.edge_crossing(L.x, L.y, L.src, L.dst)
+    assert c == p == math.comb(n, 4)
+
+
+@pytest.mark.parametrize("m,n", [(2, 2), (3, 4), (5, 5), (6, 3), (7, 8)])
+def test_two_row_bipartite(orc, m, n):
+    L = gen.two_row_bipartite(m, n)
+    c, p = orc.edge_crossing(L.x, L.y, L.src, L.dst)
+    assert c == p == math.comb(m, 2) * math.comb(n, 2)
+
+
+def test_star_and_grid_have_no_crossings(orc):
+    for L in (gen.star(12), gen.grid(6, 7), gen.grid(1, 9)):
+        assert orc.edge_crossing(L.x, L.y, L.src, L.dst) == (0, 0)
+        eca, cnt, _ = orc.crossing_angle(L.x, L.y, L.src, L.dst, IDEAL)
+        assert cnt == 0 and eca == 1.0
+
+
+def lattice_occlusion_closed_form(k, s, d):
+    """Count pairs of a k x k lattice (spacing s) closer than d, by offsets."""
+    tot = 0
+    r = int(d // s) + 1
+    for a in range(-r, r + 1):
+        for b in range(-r, r + 1):
+            if (a, b) == (0, 0) or abs(a) >= k or abs(b) >= k:
+                continue
+            if Fraction(s * s * (a * a + b * b)) < Fraction(d) ** 2:
+                tot += (k - abs(a)) * (k - abs(b))
+    return tot // 2
+
+
+@pytest.mark.parametrize("k,s,d", [(7, 4, 8), (7, 8, 8), (9, 3, 10), (12, 5, 11.5),
+                                   (10, 2, 2.0000000000000004), (6, 1, 100), (8, 3, 0.5)])
+def test_lattice_occlusion_closed_form(orc, k, s, d):
+    L = gen.square_lattice(k, s, d)
+    assert orc.node_occlusion(L.x, L.y, d) == lattice_occlusion_closed_form(k, s, d)
+
+
+def test_coincident_nodes_all_occlude(orc):
+    x = np.full(9, 17.0)
+    y = np.full(9, -3.0)
+    assert orc.node_occlusion(x, y, 1e-300) == math.comb(9, 2)
+    assert orc.node_occlusion(x, y, 0.0) == 0
+
+
+@pytest.mark.parametrize("d", [0.1, 1.0, 1.5, 2.0, math.sqrt(2), math.sqrt(5), 3.0000000000000004,
+                               7.999999999999999, 8.0, 8.000000000000002, 1e-300, 1e30])
+def test_occlusion_threshold_is_exact(orc, d):
+    """Squared distances on both sides of d^2, against exact rationals."""
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 12, size=60)
+    y = rng.integers(0, 12, size=60)
+    want = 0
+    D2 = Fraction(d) ** 2
+    for i in range(60):
+        for j in range(i + 1, 60):
+            want += Fraction(int((x[i] - x[j]) ** 2 + (y[i] - y[j]) ** 2)) < D2
+    assert orc.node_occlusion(x, y, d) == want
+
+
+# ---------------------------------------------------------------- hand cases
+
+def _cases():
+    with open(GOLDEN) as fh:
+        return json.load(fh)["cases"]
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
+def test_hand_cases(orc, case):
+    if "lattice" in case:
+        L = gen.square_lattice(case["lattice"]["k"], case["lattice"]["spacing"], case["diameter"])
+        x, y, s, d = L.x, L.y, L.src, L.dst
+    else:
+        x = np.array(case["x"], dtype=np.float64)
+        y = np.array(case["y"], dtype=np.float64)
+        e = np.array(case["edges"], dtype=np.int32).reshape(-1, 2)
+        s, d = e[:, 0], e[:, 1]
+    ex = case["expect"]
+    if "node_occlusion" in ex:
+        assert orc.node_occlusion(x, y, case["diameter"]) == ex["node_occlusion"]
+    if "edge_crossing" in ex or "proper_crossing" in ex:
+        c, p = orc.edge_crossing(x, y, s, d)
+        if "edge_crossing" in ex:
+            assert c == ex["edge_crossing"]
+        if "proper_crossing" in ex:
+            assert p == ex["proper_crossing"]
+    if "crossing_angle" in ex:
+        assert orc.crossing_angle(x, y, s, d, IDEAL)[0] == pytest.approx(ex["crossing_angle"], abs=1e-14)
+    if "min_angle" in ex:
+        assert orc.min_angle(x, y, s, d)[0] == pytest.approx(ex["min_angle"], abs=1e-14)
+    if "edge_length_variation" in ex:
+        assert orc.edge_length_variation(x, y, s, d)[0] == pytest.approx(ex["edge_length_variation"], abs=1e-14)
+
+
+def test_isolated_vertices_do_not_count_for_min_angle(orc):
+    x = np.array([1, 0, 0, 50, 60], dtype=np.float64)
+    y = np.array([0, 0, 1, 50, 60], dtype=np.float64)
+    ma, sdv, used = orc.min_angle(x, y, [0, 1], [1, 2])
+    assert used == 3 and sdv == pytest.approx(0.5) and ma == pytest.approx(5 / 6)
+
+
+# ------------------------------------------------- Eq. (1) angle categories
+
+def category_sum(theta_i, thetas_j, ideal):
+    """Sum over crossing partners of |ideal - a| by the eight categories of
+    Section 3.2.3 / Eq. (1) (its right-hand side, which omits the /ideal)."""
+    pi = math.pi
+    tot = 0.0
+    for tj in thetas_j:
+        if theta_i <= tj < theta_i + ideal:                    # LIL
+            tot += ideal - (tj - theta_i)
+        elif theta_i + ideal <= tj < theta_i + pi / 2:         # LIG
+            tot += (tj - theta_i) - ideal
+        elif theta_i + pi / 2 <= tj < theta_i + pi - ideal:    # LOG
+            tot += (theta_i - (tj - pi)) - ideal
+        elif theta_i + pi - ideal <= tj < theta_i + pi:        # LOL
+            tot += ideal - (theta_i - (tj - pi))
+        elif theta_i - ideal <= tj < theta_i:                  # RIL
+            tot += ideal - (theta_i - tj)
+        elif theta_i - pi / 2 <= tj < theta_i - ideal:         # RIG
+            tot += (theta_i - tj) - ideal
+        elif theta_i - pi + ideal <= tj < theta_i - pi / 2:    # ROG
+            tot += ((tj + pi) - theta_i) - ideal
+        elif theta_i - pi <= tj < theta_i - pi + ideal:        # ROL
+            tot += ideal - ((tj + pi) - theta_i)
+        else:
+            raise AssertionError("angle outside every category")
+    return tot
+
+
+def test_per_edge_angle_sums_match_eq1_categories(orc):
+    rng = np.random.default_rng(5)
+    n, m = 40, 90
+    x = rng.integers(0, 200, size=n)
+    y = rng.integers(0, 200, size=n)
+    s, d = gen.distinct_random_edges(rng, n, m)
+    pts = [(int(a), int(b)) for a, b in zip(x, y)]
+
+    def theta(e):  # line angle with the x-axis, in [0, pi)
+        t = math.atan2(pts[d[e]][1] - pts[s[e]][1], pts[d[e]][0] - pts[s[e]][0])
+        return t + math.pi if t < 0 else (0.0 if t >= math.pi else t)
+
+    cnt, dev = orc.crossings_of_edges(x, y, s, d, IDEAL, np.arange(m))
+    for e in range(m):
+        partners = [f for f in range(m) if f != e
+                    and not ({int(s[e]), int(d[e])} & {int(s[f]), int(d[f])})
+                    and rational_segment_relation(pts[s[e]], pts[d[e]], pts[s[f]], pts[d[f]])]
+        assert cnt[e] == len(partners)
+        want = category_sum(theta(e), [theta(f) for f in partners], IDEAL)
+        assert dev[e] == pytest.approx(want, abs=1e-9)
+    # summing per-edge values counts every crossing twice
+    eca, c, devsum = orc.crossing_angle(x, y, s, d, IDEAL)
+    assert int(cnt.sum()) == 2 * c
+    assert dev.sum() / IDEAL == pytest.approx(2 * devsum, rel=1e-12)
+
+
+# ---------------------------------------------------------------- invariants
+
+def _transform(L, kind, rng):
+    x, y = L.x.astype(np.int64), L.y.astype(np.int64)
+    s, d = L.src.copy(), L.dst.copy()
+    if kind == "translate":
+        x, y = x + 12345, y - 777
+    elif kind == "rot90":
+        x, y = -y, x
+    elif kind == "reflect":
+        x = -x
+    elif kind == "swap_ends":
+        s, d = d, s
+    elif kind == "permute_edges":
+        p = rng.permutation(s.shape[0])
+        s, d = s[p], d[p]
+    elif kind == "relabel":
+        p = rng.permutation(x.shape[0])
+        inv = np.empty_like(p)
+        inv[p] = np.arange(p.shape[0])
+        x, y = x[p], y[p]              # new node i is old node p[i]
+        s, d = inv[s], inv[d]
+    elif kind == "scale3":
+        x, y = 3 * x, 3 * y
+    return x.astype(np.float64), y.astype(np.float64), s, d
+
+
+@pytest.mark.parametrize("kind", ["translate", "rot90", "reflect", "swap_ends", "permute_edges",
+                                  "relabel", "scale3"])
+def test_invariants(orc, kind):
+    rng = np.random.default_rng(2)
+    L = gen.uniform_layout(300, 700, extent=64, seed=1)      # crowded: many degeneracies
+    base = orc.all_metrics(L)
+    x, y, s, d = _transform(L, kind, rng)
+    diam = L.diameter * (3 if kind == "scale3" else 1)
+    assert orc.node_occlusion(x, y, diam) == base["node_occlusion"]
+    assert orc.edge_crossing(x, y, s, d) == (base["edge_crossing"], base["proper_crossing"])
+    eca = orc.crossing_angle(x, y, s, d, IDEAL)[0]
+    assert eca == pytest.approx(base["crossing_angle"], rel=1e-12)
+    assert orc.min_angle(x, y, s, d)[0] == pytest.approx(base["min_angle"], rel=1e-12)
+    assert orc.edge_length_variation(x, y, s, d)[0] == pytest.approx(base["edge_length_variation"], rel=1e-12)
+
+
+# ---------------------------------------------------------------- min angle / ELV routes
+
+def test_min_angle_matches_circular_pairwise_distance(orc):
+    """The sorted-gap minimum (Algorithm 2) equals the smallest circular
+    distance over all pairs of incident directions."""
+    rng = np.random.default_rng(9)
+    n = 60
+    x = rng.integers(0, 30, size=n)
+    y = rng.integers(0, 30, size=n)
+    s, d = gen.distinct_random_edges(rng, n, 200)
+    nbrs = [[] for _ in range(n)]
+    for a, b in zip(s, d):
+        nbrs[a].append(b)
+        nbrs[b].append(a)
+    dvs = []
+    for v in range(n):
+        if not nbrs[v]:
+            continue
+        ang = [math.atan2(y[u] - y[v], x[u] - x[v]) % (2 * math.pi) for u in nbrs[v]]
+        best = 2 * math.pi
+        for i in range(len(ang)):
+            for j in range(i + 1, len(ang)):
+                g = abs(ang[i] - ang[j])
+                best = min(best, g, 2 * math.pi - g)
+        ideal = 2 * math.pi / len(ang)
+        dvs.append((ideal - best) / ideal)
+    ma, sdv, used = orc.min_angle(x, y, s, d)
+    assert used == len(dvs)
+    assert sdv == pytest.approx(sum(dvs), rel=1e-12, abs=1e-12)
+    assert ma == pytest.approx(1 - sum(dvs) / len(dvs), rel=1e-12)
+
+
+def test_edge_length_variation_is_coefficient_of_variation(orc):
+    """M_l = (population std / mean) / sqrt(|E|-1), via numpy.std."""
+    L = gen.uniform_layout(500, 1500, seed=4)
+    ln = np.hypot(L.x[L.dst].astype(np.float64) - L.x[L.src], L.y[L.dst].astype(np.float64) - L.y[L.src])
+    want = ln.std() / ln.mean() / math.sqrt(ln.shape[0] - 1)
+    assert orc.edge_length_variation(L.x, L.y, L.src, L.dst)[0] == pytest.approx(want, rel=1e-12)
+
+
+# ---------------------------------------------------------------- statistics
+
+def test_random_segments_cross_with_probability_25_over_108(orc):
+    """Four independent uniform points in a square are in convex position
+    with probability 25/36 (Sylvester); one of the three pairings then
+    crosses, so random non-incident segments cross with probability 25/108.
+    With |E| = 20,000 random segments the sample fraction has a standard
+    deviation of about 0.0017 (a U-statistic: 2 sigma_1 / sqrt(|E|) with
+    sigma_1 ~ 0.12 the spread of the per-segment crossing probability)."""
+    L = gen.uniform_layout(40_000, 20_000, extent=1 << 20, seed=0)
+    c, p = orc.edge_crossing(L.x, L.y, L.src, L.dst)
+    deg = np.bincount(np.concatenate([L.src, L.dst]), minlength=L.n_nodes)
+    non_incident = math.comb(L.n_edges, 2) - int((deg * (deg - 1) // 2).sum())
+    assert abs(c / non_incident - 25 / 108) < 0.007
+    assert c - p < 10                  # touching pairs are rare on a 2^20 grid
+
+
+def test_bad_inputs_are_rejected(orc):
+    with pytest.raises(orc.OracleError):
+        orc.node_occlusion([0.5, 1.0], [0.0, 0.0], 1.0)
+    with pytest.raises(orc.OracleError):
+        orc.edge_crossing([0, 1, 2], [0, 1, 2], [0], [3])
+    with pytest.raises(orc.OracleError):
+        orc.node_occlusion([2.0 ** 21, 0.0], [0.0, 0.0], 1.0)
