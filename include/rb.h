@@ -1,0 +1,154 @@
+/*
+ * rb.h -- exact readability metrics of straight-line graph layouts on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Implements the five metrics of Section 2.1 of "Scalable Readability
+ * Evaluation for Graph Layouts: 2D Geometric Distributed Algorithms"
+ * (arXiv 2411.09809) by the exact procedures of Section 3.1 (Algorithms 1-5):
+ * node occlusion N_c, minimum angle M_a, edge length variation M_l, edge
+ * crossing E_c and crossing angle E_ca.
+ *
+ * ------------------------------------------------------------------ layout
+ * A layout is given as structure-of-arrays in DEVICE memory:
+ *   x, y      float[n_nodes]   node coordinates.  Every value must be an
+ *                              integer with |value| <= 2^20 (so the geometric
+ *                              predicates are evaluated exactly);
+ *   src, dst  int32[n_edges]   the two end node ids of each undirected edge,
+ *                              0 <= id < n_nodes, src != dst, and no edge
+ *                              listed twice (in either orientation).
+ * These preconditions are not checked by the metric calls (their results are
+ * only defined for valid input); rb_validate_layout checks all of them.
+ * Limits: 0 <= n_nodes <= 2^31-1, 0 <= n_edges <= 2^30.
+ *
+ * ------------------------------------------------------------------ calls
+ * Every metric call only ENQUEUES work on `stream` (a hipStream_t passed as
+ * void*; NULL means the null stream) and returns.  It does not synchronise,
+ * does not allocate and keeps no pointer after returning, so a sequence of
+ * calls can be captured into a hipGraph.  Results are written to DEVICE
+ * memory (out_* pointers are device pointers; the ones documented as
+ * optional may be NULL) when the enqueued work completes.
+ *
+ * Scratch memory is supplied by the caller: `ws` is a device buffer of
+ * `ws_bytes` bytes, at least rb_workspace_size(n_nodes, n_edges), 256-byte
+ * aligned.  One workspace serves every call on the same layout size; calls
+ * that run concurrently need separate workspaces.  All buffers stay owned by
+ * the caller.
+ *
+ * ------------------------------------------------------------------ errors
+ * Argument errors (NULL required pointer, negative or too large size, a bad
+ * parameter, a workspace too small or misaligned) return RB_EINVAL or
+ * RB_EWORKSPACE before anything is enqueued.  A failing HIP runtime call
+ * returns RB_EHIP.  rb_last_error() then describes the failure (per host
+ * thread; valid until the next call on that thread).
+ */
+#ifndef RB_H
+#define RB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rb_status {
+    RB_OK = 0,
+    RB_EINVAL = 1,      /* bad argument                                     */
+    RB_EWORKSPACE = 2,  /* workspace NULL, misaligned or too small          */
+    RB_EDOMAIN = 3,     /* layout violates the preconditions (validation)   */
+    RB_EHIP = 4         /* a HIP runtime call or kernel launch failed       */
+} rb_status;
+
+/* Library version string, e.g. "rb 1.0.0 gfx950". */
+const char *rb_version(void);
+
+/* Text of the last error on the calling host thread ("" if none). */
+const char *rb_last_error(void);
+
+/* Bytes of workspace needed by every call below for a layout of this size
+ * (a multiple of 256).  Returns 0 for negative or too large sizes. */
+size_t rb_workspace_size(int64_t n_nodes, int64_t n_edges);
+
+/* Node occlusion N_c (Section 2.1; Algorithm 1, Section 3.1.1): the number
+ * of unordered node pairs {v,u}, v != u, whose Euclidean distance is
+ * strictly less than `diameter` (the paper's 2r), evaluated exactly on the
+ * integer coordinates.  diameter must be finite and >= 0.
+ * out_count: device uint64[1]. */
+rb_status rb_node_occlusion(const float *x, const float *y, int64_t n_nodes,
+                            double diameter, uint64_t *out_count,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* Edge crossing E_c (Section 2.1; Algorithm 4, Section 3.1.4): the number
+ * of unordered pairs of edges that do not share an end node and whose
+ * closed segments intersect.  This is Algorithm 4's test -- both products
+ * of CCW orientations <= 0 -- where, when both products are zero
+ * (collinear or touching ends), the two bounding boxes must also overlap.
+ * out_count:  device uint64[1] -- E_c.
+ * out_proper: device uint64[1] or NULL -- pairs whose segments cross at a
+ *             single point interior to both (both products < 0).         */
+rb_status rb_edge_crossing(const float *x, const float *y, int64_t n_nodes,
+                           const int32_t *src, const int32_t *dst, int64_t n_edges,
+                           uint64_t *out_count, uint64_t *out_proper,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* Crossing angle E_ca (Section 2.1; Algorithm 5, Section 3.1.5): over the
+ * crossing pairs of rb_edge_crossing, a = the acute angle between the two
+ * edge lines (in [0, pi/2]; 0 for parallel lines and zero-length edges),
+ * E_ca = 1 - mean(|ideal_angle - a| / ideal_angle); 1 when nothing
+ * crosses.  ideal_angle in radians, 0 < ideal_angle <= pi/2 (the paper
+ * uses 70 degrees).
+ * out_metric:  device double[1] -- E_ca.
+ * out_count:   device uint64[1] or NULL -- the crossing count E_c.
+ * out_dev_sum: device double[1] or NULL -- sum of |ideal - a| / ideal.    */
+rb_status rb_crossing_angle(const float *x, const float *y, int64_t n_nodes,
+                            const int32_t *src, const int32_t *dst, int64_t n_edges,
+                            double ideal_angle, double *out_metric,
+                            uint64_t *out_count, double *out_dev_sum,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* Minimum angle M_a (Section 2.1; Algorithm 2, Section 3.1.2): for each
+ * node v of degree deg(v) >= 1, the directions v->u of its incident edges
+ * as angles in [0, 2 pi), phi_min(v) = the smallest gap between
+ * circularly consecutive angles (the wrap-around gap included),
+ * d_v = (2 pi/deg - phi_min) / (2 pi/deg); M_a = 1 - mean of d_v over the
+ * nodes of degree >= 1 (1 when there are none).
+ * out_metric: device double[1];  out_sum_dv: device double[1] or NULL;
+ * out_n_used: device uint64[1] or NULL (number of nodes of degree >= 1).  */
+rb_status rb_min_angle(const float *x, const float *y, int64_t n_nodes,
+                       const int32_t *src, const int32_t *dst, int64_t n_edges,
+                       double *out_metric, double *out_sum_dv, uint64_t *out_n_used,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Edge length variation M_l (Section 2.1; Algorithm 3, Section 3.1.3):
+ * l_e the Euclidean edge lengths, N = n_edges, mu = mean(l),
+ * M_l = sqrt(sum (l_e - mu)^2 / (N mu^2)) / sqrt(N - 1); 0 when N < 2 or
+ * mu = 0.  out_metric: device double[1]; out_mean: device double[1] or NULL. */
+rb_status rb_edge_length_variation(const float *x, const float *y, int64_t n_nodes,
+                                   const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                   double *out_metric, double *out_mean,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+/* Checks the layout preconditions listed above on the GPU and waits for the
+ * result (this call synchronises `stream`).  Returns RB_OK or RB_EDOMAIN;
+ * *out_flags (host int32, may be NULL) receives a bit set:
+ *   1 a coordinate is not an integer, 2 a coordinate exceeds 2^20 in
+ *   magnitude, 4 an edge end id is out of range, 8 a self-loop,
+ *   16 an edge listed twice.                                              */
+rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes,
+                             const int32_t *src, const int32_t *dst, int64_t n_edges,
+                             int32_t *out_flags, void *ws, size_t ws_bytes, void *stream);
+
+/* Kernel timing for measurement.  While enabled, the library records a HIP
+ * event pair on the caller's stream around each launch of its all-pairs
+ * sweep kernels.  rb_timing_read waits for the recorded events and returns
+ * the summed duration in milliseconds and the number of launches of one
+ * kernel: 0 = edge-pair sweep (crossing / crossing angle), 1 = node-pair
+ * sweep (occlusion).  rb_timing_reset clears the sums.                    */
+rb_status rb_timing_enable(int enable);
+rb_status rb_timing_reset(void);
+rb_status rb_timing_read(int kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RB_H */

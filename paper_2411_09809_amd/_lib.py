@@ -1,0 +1,75 @@
+"""ctypes loader for ``librb.so`` (the C-ABI of include/rb.h).
+
+Argument marshalling only.  The library must have been built with
+``python -m paper_2411_09809_amd.build`` (or ``__graft_entry__.build()``);
+there is no fallback: a missing library raises ``RBError``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librb.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rb.h")
+
+RB_OK, RB_EINVAL, RB_EWORKSPACE, RB_EDOMAIN, RB_EHIP = range(5)
+STATUS_NAMES = {0: "RB_OK", 1: "RB_EINVAL", 2: "RB_EWORKSPACE", 3: "RB_EDOMAIN", 4: "RB_EHIP"}
+
+
+class RBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_vp, _i64, _f64, _sz = C.c_void_p, C.c_int64, C.c_double, C.c_size_t
+
+_SIGS = {
+    "rb_version": ([], C.c_char_p),
+    "rb_last_error": ([], C.c_char_p),
+    "rb_workspace_size": ([_i64, _i64], _sz),
+    "rb_node_occlusion": ([_vp, _vp, _i64, _f64, _vp, _vp, _sz, _vp], C.c_int),
+    "rb_edge_crossing": ([_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp], C.c_int),
+    "rb_crossing_angle": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _vp, _vp, _vp, _vp, _sz, _vp],
+                          C.c_int),
+    "rb_min_angle": ([_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
+    "rb_edge_length_variation": ([_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp],
+                                 C.c_int),
+    "rb_validate_layout": ([_vp, _vp, _i64, _vp, _vp, _i64, C.POINTER(C.c_int32), _vp, _sz, _vp],
+                           C.c_int),
+    "rb_timing_enable": ([C.c_int], C.c_int),
+    "rb_timing_reset": ([], C.c_int),
+    "rb_timing_read": ([C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+}
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions declared in include/rb.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rb_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib():
+    """Load librb.so once; raise RBError when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RBError(RB_EHIP, f"{LIB_PATH} is missing: build it with "
+                                   "`python -m paper_2411_09809_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str):
+    if status != RB_OK:
+        raise RBError(status, f"{what}: {lib().rb_last_error().decode()}")

@@ -1,0 +1,355 @@
+// C-ABI entry points of librb (declared in include/rb.h): argument checks,
+// workspace carving and the launch sequence of each metric.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "rb.h"
+#include "rb_internal.h"
+
+namespace rb {
+namespace {
+
+thread_local std::string g_err;
+
+rb_status fail(rb_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+rb_status fail(rb_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+rb_status hip_fail(hipError_t e, const char *what) {
+    return fail(RB_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int64_t kMaxNodes = 2147483647LL;
+constexpr int64_t kMaxEdges = 1LL << 30;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Timing of the sweep kernels (rb_timing_*).
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
+    double ms[2] = {0.0, 0.0};
+    int64_t n[2] = {0, 0};
+} g_timing;
+
+struct TimedLaunch {
+    int kind;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(int k, hipStream_t s) : kind(k), st(s) {
+        std::lock_guard<std::mutex> g(g_timing.mu);
+        if (!g_timing.on) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, st);
+    }
+    void done() {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        std::lock_guard<std::mutex> g(g_timing.mu);
+        g_timing.ev[kind].emplace_back(a, b);
+        a = b = nullptr;
+    }
+};
+
+// Largest integer T with T < d^2 (d finite, >= 0).  fma(d, d, -n) carries the
+// exact sign of d^2 - n.  Squared distances are below 2^43, so T is capped.
+double occlusion_threshold(double d) {
+    if (d <= 0.0) return -1.0;
+    if (d < 1.0) return 0.0;
+    if (d >= 4194304.0) return 17592186044416.0;   // d >= 2^22: T = 2^44 covers all
+    double t = std::ceil(d * d) - 1.0;
+    while (std::fma(d, d, -(t + 1.0)) > 0.0) t += 1.0;
+    while (std::fma(d, d, -t) <= 0.0) t -= 1.0;
+    return t;
+}
+
+rb_status check_sizes(int64_t n_nodes, int64_t n_edges) {
+    if (n_nodes < 0 || n_nodes > kMaxNodes)
+        return fail(RB_EINVAL, "n_nodes = %lld out of range [0, 2^31-1]", (long long)n_nodes);
+    if (n_edges < 0 || n_edges > kMaxEdges)
+        return fail(RB_EINVAL, "n_edges = %lld out of range [0, 2^30]", (long long)n_edges);
+    return RB_OK;
+}
+
+rb_status check_layout(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                       const int32_t *dst, int64_t n_edges) {
+    rb_status s = check_sizes(n_nodes, n_edges);
+    if (s) return s;
+    if (n_nodes > 0 && (!x || !y)) return fail(RB_EINVAL, "x or y is NULL");
+    if (n_edges > 0 && (!src || !dst)) return fail(RB_EINVAL, "src or dst is NULL");
+    if (n_edges > 0 && n_nodes < 2) return fail(RB_EINVAL, "edges need at least two nodes");
+    return RB_OK;
+}
+
+rb_status check_ws(void *ws, size_t ws_bytes, int64_t n_nodes, int64_t n_edges, WsLayout *L) {
+    if (!ws_layout(n_nodes, n_edges, L)) return fail(RB_EINVAL, "layout too large");
+    if (!ws) return fail(RB_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(RB_EWORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < L->total)
+        return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, L->total);
+    return RB_OK;
+}
+
+int g_cu_count[64];
+
+}  // namespace
+
+int device_cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (g_cu_count[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        g_cu_count[dev] = n;
+    }
+    return g_cu_count[dev];
+}
+
+bool ws_layout(int64_t n_nodes, int64_t n_edges, WsLayout *L) {
+    if (n_nodes < 0 || n_nodes > kMaxNodes || n_edges < 0 || n_edges > kMaxEdges) return false;
+    const int64_t V = n_nodes > 0 ? n_nodes : 1;
+    const int64_t E = n_edges > 0 ? n_edges : 1;
+    L->n_edge_pad = (int64_t)round_up((size_t)E, kEdgePad);
+    L->n_node_pad = (int64_t)round_up((size_t)V, kNodePad);
+    int64_t h = 1024;
+    while (h < 2 * E) h <<= 1;
+    L->hash_size = h;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = round_up(off + bytes, 256);
+        return o;
+    };
+    L->edge_rec = take(sizeof(EdgeRec) * (size_t)L->n_edge_pad);
+    L->node_rec = take(sizeof(NodeRec) * (size_t)L->n_node_pad);
+    L->partial = take(sizeof(CrossPartial) * (size_t)kMaxPartials);
+    L->scalars = take(sizeof(Scalars));
+    L->deg = take(sizeof(uint32_t) * (size_t)V);
+    L->cursor = take(sizeof(uint32_t) * (size_t)V);
+    L->offs = take(sizeof(uint32_t) * (size_t)(V + 1));
+    L->angles = take(sizeof(double) * (size_t)(2 * E));
+    L->dv = take(sizeof(double) * (size_t)V);
+    L->big_list = take(sizeof(int32_t) * (size_t)V);
+    L->hash = take(sizeof(unsigned long long) * (size_t)h);
+    L->total = off;
+    return true;
+}
+
+}  // namespace rb
+
+using namespace rb;
+
+extern "C" {
+
+const char *rb_version(void) { return "rb 1.0.0 gfx950"; }
+
+const char *rb_last_error(void) { return g_err.c_str(); }
+
+size_t rb_workspace_size(int64_t n_nodes, int64_t n_edges) {
+    WsLayout L;
+    if (!ws_layout(n_nodes, n_edges, &L)) return 0;
+    return L.total;
+}
+
+rb_status rb_node_occlusion(const float *x, const float *y, int64_t n_nodes, double diameter,
+                            uint64_t *out_count, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_sizes(n_nodes, 0);
+    if (s) return s;
+    if (n_nodes > 0 && (!x || !y)) return fail(RB_EINVAL, "x or y is NULL");
+    if (!out_count) return fail(RB_EINVAL, "out_count is NULL");
+    if (!(diameter >= 0.0) || !std::isfinite(diameter))
+        return fail(RB_EINVAL, "diameter must be finite and >= 0");
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, 0, &L))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    NodeRec *rec = (NodeRec *)(w + L.node_rec);
+    OcclPartial *part = (OcclPartial *)(w + L.partial);
+    SweepPlan p = plan_occl(n_nodes);
+    hipError_t e = launch_node_prep(x, y, n_nodes, L.n_node_pad, occlusion_threshold(diameter),
+                                    rec, st);
+    if (e != hipSuccess) return hip_fail(e, "node_prep launch");
+    TimedLaunch tl(1, st);
+    e = launch_occl_sweep(rec, p, part, st);
+    tl.done();
+    if (e != hipSuccess) return hip_fail(e, "occlusion sweep launch");
+    e = launch_occl_finalize(part, p.grid, (unsigned long long *)out_count, st);
+    if (e != hipSuccess) return hip_fail(e, "occlusion finalize launch");
+    return RB_OK;
+}
+
+static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes,
+                                 const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                 bool angle, double ideal, uint64_t *out_count,
+                                 uint64_t *out_proper, double *out_metric, double *out_dev_sum,
+                                 void *ws, size_t ws_bytes, void *stream) {
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    EdgeRec *rec = (EdgeRec *)(w + L.edge_rec);
+    CrossPartial *part = (CrossPartial *)(w + L.partial);
+    SweepPlan p = plan_cross(n_edges, angle);
+    hipError_t e = launch_edge_prep(x, y, src, dst, n_nodes, n_edges, L.n_edge_pad, rec, st);
+    if (e != hipSuccess) return hip_fail(e, "edge_prep launch");
+    TimedLaunch tl(0, st);
+    e = launch_cross_sweep(rec, p, angle, ideal, part, st);
+    tl.done();
+    if (e != hipSuccess) return hip_fail(e, "crossing sweep launch");
+    e = launch_cross_finalize(part, p.grid, ideal, (unsigned long long *)out_count,
+                              (unsigned long long *)out_proper, out_metric, out_dev_sum, st);
+    if (e != hipSuccess) return hip_fail(e, "crossing finalize launch");
+    return RB_OK;
+}
+
+rb_status rb_edge_crossing(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                           const int32_t *dst, int64_t n_edges, uint64_t *out_count,
+                           uint64_t *out_proper, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!out_count) return fail(RB_EINVAL, "out_count is NULL");
+    return crossing_common(x, y, n_nodes, src, dst, n_edges, false, 1.0, out_count, out_proper,
+                           nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+rb_status rb_crossing_angle(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                            const int32_t *dst, int64_t n_edges, double ideal_angle,
+                            double *out_metric, uint64_t *out_count, double *out_dev_sum,
+                            void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
+    if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
+        return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
+    return crossing_common(x, y, n_nodes, src, dst, n_edges, true, ideal_angle, out_count,
+                           nullptr, out_metric, out_dev_sum, ws, ws_bytes, stream);
+}
+
+rb_status rb_min_angle(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                       const int32_t *dst, int64_t n_edges, double *out_metric,
+                       double *out_sum_dv, uint64_t *out_n_used, void *ws, size_t ws_bytes,
+                       void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    hipError_t e = launch_min_angle(x, y, n_nodes, src, dst, n_edges, L, (char *)ws, out_metric,
+                                    out_sum_dv, (unsigned long long *)out_n_used,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "min_angle launch");
+    return RB_OK;
+}
+
+rb_status rb_edge_length_variation(const float *x, const float *y, int64_t n_nodes,
+                                   const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                   double *out_metric, double *out_mean, void *ws,
+                                   size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    char *w = (char *)ws;
+    hipError_t e = launch_elv(x, y, src, dst, n_nodes, n_edges, (double *)(w + L.partial),
+                              (Scalars *)(w + L.scalars), out_metric, out_mean,
+                              (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "edge_length_variation launch");
+    return RB_OK;
+}
+
+rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                             const int32_t *dst, int64_t n_edges, int32_t *out_flags, void *ws,
+                             size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    hipError_t e = launch_validate(x, y, n_nodes, src, dst, n_edges, L, w, st);
+    if (e != hipSuccess) return hip_fail(e, "validate launch");
+    Scalars sc;
+    e = hipMemcpyAsync(&sc, w + L.scalars, sizeof sc, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "validate copy");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "validate synchronize");
+    if (out_flags) *out_flags = sc.flags;
+    if (sc.flags) {
+        std::string msg = "invalid layout:";
+        if (sc.flags & 1) msg += " non-integer coordinate;";
+        if (sc.flags & 2) msg += " coordinate beyond 2^20;";
+        if (sc.flags & 4) msg += " edge end out of range;";
+        if (sc.flags & 8) msg += " self-loop;";
+        if (sc.flags & 16) msg += " duplicate edge;";
+        g_err = msg;
+        return RB_EDOMAIN;
+    }
+    return RB_OK;
+}
+
+rb_status rb_timing_enable(int enable) {
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    g_timing.on = enable != 0;
+    return RB_OK;
+}
+
+rb_status rb_timing_reset(void) {
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    for (int k = 0; k < 2; ++k) {
+        for (auto &p : g_timing.ev[k]) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+        g_timing.ev[k].clear();
+        g_timing.ms[k] = 0.0;
+        g_timing.n[k] = 0;
+    }
+    return RB_OK;
+}
+
+rb_status rb_timing_read(int kernel, double *total_ms, int64_t *launches) {
+    g_err.clear();
+    if (kernel < 0 || kernel > 1) return fail(RB_EINVAL, "kernel must be 0 or 1");
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    for (auto &p : g_timing.ev[kernel]) {
+        hipError_t e = hipEventSynchronize(p.second);
+        if (e != hipSuccess) return hip_fail(e, "timing event");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p.first, p.second);
+        if (e != hipSuccess) return hip_fail(e, "timing elapsed");
+        g_timing.ms[kernel] += ms;
+        g_timing.n[kernel] += 1;
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    g_timing.ev[kernel].clear();
+    if (total_ms) *total_ms = g_timing.ms[kernel];
+    if (launches) *launches = g_timing.n[kernel];
+    return RB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,563 @@
+// The O(|E|) and O(sum deg log deg) metrics and the layout validator:
+//   edge length variation (Algorithm 3), minimum angle (Algorithm 2),
+//   precondition checks.
+// Every floating-point reduction runs over a fixed grid and combines block
+// partials in a fixed order, so results are bit-reproducible.
+#include "rb_internal.h"
+
+namespace rb {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925;
+constexpr int kRedGrid = 1024;       // blocks of the fixed-grid reductions
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ids out of range violate the preconditions; such edges are skipped so that
+// no kernel reads or writes outside its buffers
+__device__ __forceinline__ bool valid_ids(int32_t s, int32_t t, int64_t n_nodes) {
+    return s >= 0 && t >= 0 && s < n_nodes && t < n_nodes;
+}
+
+__device__ __forceinline__ double edge_length(const float *x, const float *y, int32_t s,
+                                              int32_t t) {
+    const double dx = (double)x[t] - (double)x[s];
+    const double dy = (double)y[t] - (double)y[s];
+    return sqrt(fma(dx, dx, dy * dy));      // dx^2 + dy^2 < 2^44 is exact
+}
+
+// ---------------------------------------------------- edge length variation
+
+__global__ __launch_bounds__(256) void elv_pass_kernel(const float *__restrict__ x,
+                                                       const float *__restrict__ y,
+                                                       const int32_t *__restrict__ src,
+                                                       const int32_t *__restrict__ dst,
+                                                       int64_t n_nodes, int64_t n_edges,
+                                                       const Scalars *sc, int second,
+                                                       double *__restrict__ partial) {
+    __shared__ double sh[256];
+    const double mu = second ? sc->mean : 0.0;
+    double acc = 0.0;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n_edges; e += (int64_t)gridDim.x * 256) {
+        const int32_t s = src[e], t = dst[e];
+        if (!valid_ids(s, t, n_nodes)) continue;
+        const double l = edge_length(x, y, s, t);
+        if (second) {
+            const double d = l - mu;
+            acc = fma(d, d, acc);
+        } else {
+            acc += l;
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void elv_reduce_kernel(const double *__restrict__ partial,
+                                                         int n_part, int64_t n_edges, int second,
+                                                         Scalars *sc, double *out_metric,
+                                                         double *out_mean) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n_part; i += 256) acc += partial[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    const double N = (double)n_edges;
+    if (!second) {
+        const double mu = n_edges > 0 ? s / N : 0.0;
+        sc->mean = mu;
+        if (out_mean) *out_mean = mu;
+    } else {
+        const double mu = sc->mean;
+        double m = 0.0;
+        if (n_edges >= 2 && mu > 0.0) m = sqrt(s / (N * mu * mu)) / sqrt(N - 1.0);
+        *out_metric = m;
+    }
+}
+
+// ------------------------------------------------------------ minimum angle
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void zero_scalars_kernel(Scalars *sc) {
+    if (threadIdx.x == 0) {
+        sc->mean = 0.0;
+        sc->sum_dv = 0.0;
+        sc->n_used = 0;
+        sc->big_count = 0;
+        sc->flags = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void degree_kernel(const int32_t *__restrict__ src,
+                                                     const int32_t *__restrict__ dst,
+                                                     int64_t n_nodes, int64_t n_edges,
+                                                     uint32_t *deg) {
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n_edges; e += (int64_t)gridDim.x * 256) {
+        const int32_t s = src[e], t = dst[e];
+        if (!valid_ids(s, t, n_nodes)) continue;
+        atomicAdd(&deg[s], 1u);
+        atomicAdd(&deg[t], 1u);
+    }
+}
+
+// exclusive scan of deg[0..n) into offs[0..n], in tiles of 2048 elements
+constexpr int kScanTile = 2048;
+
+__global__ __launch_bounds__(256) void scan_tile_sums_kernel(const uint32_t *__restrict__ deg,
+                                                             int64_t n,
+                                                             unsigned long long *tile_sum) {
+    __shared__ unsigned long long sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    unsigned long long s = 0;
+    for (int k = 0; k < kScanTile / 256; ++k) {
+        const int64_t i = base + (int64_t)k * 256 + threadIdx.x;
+        if (i < n) s += deg[i];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void scan_tile_offsets_kernel(unsigned long long *tile_sum,
+                                                                int64_t n_tiles) {
+    // one block: exclusive scan, 256 tiles at a time with a running carry
+    __shared__ unsigned long long sh[256];
+    unsigned long long carry = 0;
+    for (int64_t base = 0; base < n_tiles; base += 256) {
+        const int64_t i = base + threadIdx.x;
+        const unsigned long long v = i < n_tiles ? tile_sum[i] : 0ull;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int k = 1; k < 256; k <<= 1) {
+            unsigned long long t = threadIdx.x >= k ? sh[threadIdx.x - k] : 0ull;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < n_tiles) tile_sum[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_tile_apply_kernel(const uint32_t *__restrict__ deg,
+                                                              int64_t n,
+                                                              const unsigned long long *tile_off,
+                                                              uint32_t *__restrict__ offs) {
+    __shared__ unsigned long long sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    constexpr int per = kScanTile / 256;
+    // each thread scans `per` consecutive elements
+    unsigned long long loc[per];
+    unsigned long long s = 0;
+    for (int k = 0; k < per; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * per + k;
+        loc[k] = s;
+        s += (i < n) ? deg[i] : 0u;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 1; k < 256; k <<= 1) {
+        unsigned long long t = threadIdx.x >= k ? sh[threadIdx.x - k] : 0ull;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const unsigned long long before = tile_off[blockIdx.x] + sh[threadIdx.x] - s;
+    for (int k = 0; k < per; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * per + k;
+        if (i < n) offs[i] = (uint32_t)(before + loc[k]);
+        if (i == n - 1) offs[n] = (uint32_t)(before + loc[k] + deg[i]);
+    }
+}
+
+__device__ __forceinline__ double direction_angle(double dx, double dy) {
+    double a = atan2(dy, dx);
+    return a < 0.0 ? a + kTwoPi : a;               // [0, 2 pi)
+}
+
+__global__ __launch_bounds__(256) void fill_angles_kernel(const float *__restrict__ x,
+                                                          const float *__restrict__ y,
+                                                          const int32_t *__restrict__ src,
+                                                          const int32_t *__restrict__ dst,
+                                                          int64_t n_nodes, int64_t n_edges,
+                                                          const uint32_t *__restrict__ offs,
+                                                          uint32_t *cursor,
+                                                          double *__restrict__ ang) {
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n_edges; e += (int64_t)gridDim.x * 256) {
+        const int32_t s = src[e], t = dst[e];
+        if (!valid_ids(s, t, n_nodes)) continue;
+        const double dx = (double)x[t] - (double)x[s];
+        const double dy = (double)y[t] - (double)y[s];
+        const uint32_t ps = offs[s] + atomicAdd(&cursor[s], 1u);
+        const uint32_t pt = offs[t] + atomicAdd(&cursor[t], 1u);
+        // the reverse difference is taken from the coordinates, not negated:
+        // a zero-length edge must give +0 (angle 0), never -0 (atan2 -> -pi)
+        const double rdx = (double)x[s] - (double)x[t];
+        const double rdy = (double)y[s] - (double)y[t];
+        ang[ps] = direction_angle(dx, dy);       // at s, towards t
+        ang[pt] = direction_angle(rdx, rdy);     // at t, towards s
+    }
+}
+
+// d_v = (2 pi/deg - phi_min) / (2 pi/deg)
+__device__ __forceinline__ double dv_of(double phi_min, uint32_t deg) {
+    const double ideal = kTwoPi / (double)deg;
+    return (ideal - phi_min) / ideal;
+}
+
+// Nodes of degree <= kSmallDeg: one thread each.  The smallest gap between
+// circularly consecutive angles equals the smallest circular distance
+// min(|a_i - a_j|, 2 pi - |a_i - a_j|) over all pairs, so no sort is needed.
+__global__ __launch_bounds__(256) void min_angle_small_kernel(
+    const uint32_t *__restrict__ deg, const uint32_t *__restrict__ offs,
+    const double *__restrict__ ang, int64_t n_nodes, double *__restrict__ dv,
+    int32_t *__restrict__ big_list, Scalars *sc) {
+    for (int64_t v = blockIdx.x * 256 + threadIdx.x; v < n_nodes; v += (int64_t)gridDim.x * 256) {
+        const uint32_t d = deg[v];
+        if (d == 0) {
+            dv[v] = 0.0;
+            continue;
+        }
+        if (d > (uint32_t)kSmallDeg) {
+            const unsigned long long slot = atomicAdd(&sc->big_count, 1ull);
+            big_list[slot] = (int32_t)v;
+            continue;
+        }
+        const uint32_t o = offs[v];
+        double a[kSmallDeg];
+#pragma unroll
+        for (int i = 0; i < kSmallDeg; ++i) a[i] = (uint32_t)i < d ? ang[o + i] : 0.0;
+        double best = kTwoPi;
+#pragma unroll
+        for (int i = 0; i < kSmallDeg; ++i) {
+#pragma unroll
+            for (int j = i + 1; j < kSmallDeg; ++j) {
+                if ((uint32_t)j < d) {
+                    const double g = fabs(a[i] - a[j]);
+                    best = fmin(best, fmin(g, kTwoPi - g));
+                }
+            }
+        }
+        dv[v] = dv_of(best, d);
+    }
+}
+
+// Ascending sort of a[0..n) by a bitonic network in which every comparator
+// puts the minimum at the lower index; indices >= n act as +infinity and are
+// never touched, so n need not be a power of two.
+__device__ void block_sort(double *a, uint32_t n) {
+    uint32_t P = 1;
+    while (P < n) P <<= 1;
+    const uint32_t half = P >> 1;
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        const uint32_t hk = k >> 1;
+        for (uint32_t q = threadIdx.x; q < half; q += blockDim.x) {
+            const uint32_t i = (q / hk) * k + (q % hk);
+            const uint32_t j = i ^ (k - 1);
+            if (j < n) {
+                const double u = a[i], w = a[j];
+                if (w < u) { a[i] = w; a[j] = u; }
+            }
+        }
+        __syncthreads();
+        for (uint32_t s = hk >> 1; s > 0; s >>= 1) {
+            for (uint32_t q = threadIdx.x; q < half; q += blockDim.x) {
+                const uint32_t i = (q / s) * (2 * s) + (q % s);
+                const uint32_t j = i + s;
+                if (j < n) {
+                    const double u = a[i], w = a[j];
+                    if (w < u) { a[i] = w; a[j] = u; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Nodes of larger degree: one block each; sort (in LDS, or in place in the
+// angle array for the largest degrees), then the smallest consecutive gap,
+// the wrap-around gap included (GetMinAngle of Algorithm 2).
+__global__ __launch_bounds__(256) void min_angle_big_kernel(
+    const uint32_t *__restrict__ deg, const uint32_t *__restrict__ offs, double *ang,
+    const int32_t *__restrict__ big_list, const Scalars *sc, double *__restrict__ dv) {
+    __shared__ double buf[kLdsDeg];
+    __shared__ double red[256];
+    const unsigned long long n_big = sc->big_count;
+    for (unsigned long long k = blockIdx.x; k < n_big; k += gridDim.x) {
+        const int32_t v = big_list[k];
+        const uint32_t d = deg[v];
+        double *seg = ang + offs[v];
+        double *a = seg;
+        if (d <= (uint32_t)kLdsDeg) {
+            for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) buf[i] = seg[i];
+            a = buf;
+        }
+        __syncthreads();
+        block_sort(a, d);
+        double best = kTwoPi;
+        for (uint32_t i = threadIdx.x + 1; i < d; i += blockDim.x) best = fmin(best, a[i] - a[i - 1]);
+        if (threadIdx.x == 0) best = fmin(best, (kTwoPi - a[d - 1]) + a[0]);
+        red[threadIdx.x] = best;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) dv[v] = dv_of(red[0], d);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void dv_sum_kernel(const uint32_t *__restrict__ deg,
+                                                     const double *__restrict__ dv,
+                                                     int64_t n_nodes, double *__restrict__ partial,
+                                                     unsigned long long *__restrict__ used) {
+    __shared__ double sh[256];
+    __shared__ unsigned long long su[256];
+    double acc = 0.0;
+    unsigned long long u = 0;
+    for (int64_t v = blockIdx.x * 256 + threadIdx.x; v < n_nodes; v += (int64_t)gridDim.x * 256) {
+        if (deg[v] > 0) {
+            acc += dv[v];
+            ++u;
+        }
+    }
+    su[threadIdx.x] = u;
+    const double s = block_sum(acc, sh);
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) su[threadIdx.x] += su[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = s;
+        used[blockIdx.x] = su[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void dv_final_kernel(const double *__restrict__ partial,
+                                                       const unsigned long long *__restrict__ used,
+                                                       int n_part, double *out_metric,
+                                                       double *out_sum_dv,
+                                                       unsigned long long *out_n_used) {
+    __shared__ double sh[256];
+    __shared__ unsigned long long su[256];
+    double acc = 0.0;
+    unsigned long long u = 0;
+    for (int i = threadIdx.x; i < n_part; i += 256) {
+        acc += partial[i];
+        u += used[i];
+    }
+    su[threadIdx.x] = u;
+    const double s = block_sum(acc, sh);
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) su[threadIdx.x] += su[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long n = su[0];
+        *out_metric = n ? 1.0 - s / (double)n : 1.0;
+        if (out_sum_dv) *out_sum_dv = s;
+        if (out_n_used) *out_n_used = n;
+    }
+}
+
+// ---------------------------------------------------------------- validation
+
+__global__ __launch_bounds__(256) void validate_nodes_kernel(const float *__restrict__ x,
+                                                             const float *__restrict__ y,
+                                                             int64_t n, Scalars *sc) {
+    int f = 0;
+    for (int64_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        const float a = x[v], b = y[v];
+        if (!(a == floorf(a)) || !(b == floorf(b))) f |= 1;
+        else if (fabsf(a) > 1048576.0f || fabsf(b) > 1048576.0f) f |= 2;
+    }
+    if (f) atomicOr(&sc->flags, f);
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+__global__ __launch_bounds__(256) void validate_edges_kernel(const int32_t *__restrict__ src,
+                                                             const int32_t *__restrict__ dst,
+                                                             int64_t n_edges, int64_t n_nodes,
+                                                             unsigned long long *table,
+                                                             int64_t table_size, Scalars *sc) {
+    const unsigned long long kEmpty = ~0ull;
+    int f = 0;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n_edges; e += (int64_t)gridDim.x * 256) {
+        const int32_t s = src[e], t = dst[e];
+        if (s < 0 || t < 0 || s >= n_nodes || t >= n_nodes) {
+            f |= 4;
+            continue;
+        }
+        if (s == t) {
+            f |= 8;
+            continue;
+        }
+        const unsigned long long lo = (unsigned long long)(s < t ? s : t);
+        const unsigned long long hi = (unsigned long long)(s < t ? t : s);
+        const unsigned long long key = (lo << 32) | hi;
+        unsigned long long h = mix64(key) & (unsigned long long)(table_size - 1);
+        // the table has at least twice as many slots as edges: the probe ends
+        for (int64_t probe = 0; probe < table_size; ++probe) {
+            const unsigned long long prev = atomicCAS(&table[h], kEmpty, key);
+            if (prev == kEmpty) break;
+            if (prev == key) {
+                f |= 16;
+                break;
+            }
+            h = (h + 1) & (unsigned long long)(table_size - 1);
+        }
+    }
+    if (f) atomicOr(&sc->flags, f);
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int grid_for(int64_t n, int cap = 65536) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+#define RB_TRY(expr)                          \
+    do {                                      \
+        hipError_t _e = (expr);               \
+        if (_e != hipSuccess) return _e;      \
+    } while (0)
+#define RB_LAUNCHED() RB_TRY(hipGetLastError())
+
+}  // namespace
+
+hipError_t launch_elv(const float *x, const float *y, const int32_t *src, const int32_t *dst,
+                      int64_t n_nodes, int64_t n_edges, double *partial, Scalars *sc, double *out_metric,
+                      double *out_mean, hipStream_t st) {
+    const int g = grid_for(n_edges, kRedGrid);
+    hipLaunchKernelGGL(elv_pass_kernel, dim3(g), dim3(256), 0, st, x, y, src, dst, n_nodes, n_edges, sc, 0,
+                       partial);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(elv_reduce_kernel, dim3(1), dim3(256), 0, st, partial, g, n_edges, 0, sc,
+                       out_metric, out_mean);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(elv_pass_kernel, dim3(g), dim3(256), 0, st, x, y, src, dst, n_nodes, n_edges, sc, 1,
+                       partial);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(elv_reduce_kernel, dim3(1), dim3(256), 0, st, partial, g, n_edges, 1, sc,
+                       out_metric, out_mean);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_angle(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                            const int32_t *dst, int64_t n_edges, const WsLayout &L, char *ws,
+                            double *out_metric, double *out_sum_dv,
+                            unsigned long long *out_n_used, hipStream_t st) {
+    uint32_t *deg = (uint32_t *)(ws + L.deg);
+    uint32_t *cursor = (uint32_t *)(ws + L.cursor);
+    uint32_t *offs = (uint32_t *)(ws + L.offs);
+    double *ang = (double *)(ws + L.angles);
+    double *dv = (double *)(ws + L.dv);
+    int32_t *big = (int32_t *)(ws + L.big_list);
+    Scalars *sc = (Scalars *)(ws + L.scalars);
+    double *partial = (double *)(ws + L.partial);
+    unsigned long long *used = (unsigned long long *)(ws + L.partial) + kRedGrid;
+    unsigned long long *tile = (unsigned long long *)dv;   // dv is written only later
+
+    const int64_t V = n_nodes > 0 ? n_nodes : 1;
+    hipLaunchKernelGGL(zero_scalars_kernel, dim3(1), dim3(64), 0, st, sc);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(V)), dim3(256), 0, st, deg, V, 0u);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(V)), dim3(256), 0, st, cursor, V, 0u);
+    RB_LAUNCHED();
+    if (n_edges > 0) {
+        hipLaunchKernelGGL(degree_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, src, dst,
+                           n_nodes, n_edges, deg);
+        RB_LAUNCHED();
+    }
+    const int64_t n_tiles = (V + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, deg, V,
+                       tile);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(scan_tile_offsets_kernel, dim3(1), dim3(256), 0, st, tile, n_tiles);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(scan_tile_apply_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, deg, V,
+                       tile, offs);
+    RB_LAUNCHED();
+    if (n_edges > 0) {
+        hipLaunchKernelGGL(fill_angles_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, x, y,
+                           src, dst, n_nodes, n_edges, offs, cursor, ang);
+        RB_LAUNCHED();
+    }
+    if (n_nodes > 0) {
+        hipLaunchKernelGGL(min_angle_small_kernel, dim3(grid_for(n_nodes)), dim3(256), 0, st, deg,
+                           offs, ang, n_nodes, dv, big, sc);
+        RB_LAUNCHED();
+        hipLaunchKernelGGL(min_angle_big_kernel, dim3(1024), dim3(256), 0, st, deg, offs, ang, big,
+                           sc, dv);
+        RB_LAUNCHED();
+    }
+    const int g = grid_for(n_nodes, kRedGrid);
+    hipLaunchKernelGGL(dv_sum_kernel, dim3(g), dim3(256), 0, st, deg, dv, n_nodes, partial, used);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(dv_final_kernel, dim3(1), dim3(256), 0, st, partial, used, g, out_metric,
+                       out_sum_dv, out_n_used);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                           const int32_t *dst, int64_t n_edges, const WsLayout &L, char *ws,
+                           hipStream_t st) {
+    Scalars *sc = (Scalars *)(ws + L.scalars);
+    unsigned long long *table = (unsigned long long *)(ws + L.hash);
+    hipLaunchKernelGGL(zero_scalars_kernel, dim3(1), dim3(64), 0, st, sc);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(L.hash_size)), dim3(256), 0, st, table,
+                       L.hash_size, ~0ull);
+    RB_LAUNCHED();
+    if (n_nodes > 0) {
+        hipLaunchKernelGGL(validate_nodes_kernel, dim3(grid_for(n_nodes)), dim3(256), 0, st, x, y,
+                           n_nodes, sc);
+        RB_LAUNCHED();
+    }
+    if (n_edges > 0) {
+        hipLaunchKernelGGL(validate_edges_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, src,
+                           dst, n_edges, n_nodes, table, L.hash_size, sc);
+        RB_LAUNCHED();
+    }
+    return hipSuccess;
+}
+
+}  // namespace rb

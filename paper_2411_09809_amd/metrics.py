@@ -1,0 +1,196 @@
+"""Python entry points with the names of the C-ABI (include/rb.h).
+
+Each function takes a layout as torch tensors on one AMD GPU -- ``x``, ``y``
+float32 (integer-valued, |c| <= 2^20) and ``src``, ``dst`` int32 -- enqueues
+the HIP kernels of librb on the current stream and returns Python numbers
+(which waits for the stream), or device tensors with ``async_=True``.
+PyTorch only provides device memory and the stream; all metric arithmetic
+runs in librb's kernels.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import torch
+
+from ._lib import check, lib
+
+IDEAL_ANGLE = 70.0 * math.pi / 180.0
+
+_ws_cache: dict[int, torch.Tensor] = {}
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
+    """A cached device workspace large enough for this layout size."""
+    need = int(lib().rb_workspace_size(int(n_nodes), int(n_edges)))
+    if need == 0:
+        raise ValueError(f"layout size out of range: {n_nodes} nodes, {n_edges} edges")
+    dev = torch.device(device)
+    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < need:
+        _ws_cache.pop(key, None)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        _ws_cache[key] = ws
+    return ws
+
+
+def _ws_args(ws: torch.Tensor):
+    p = ws.data_ptr()
+    aligned = (p + 255) & ~255
+    return aligned, ws.numel() - (aligned - p)
+
+
+def _check_coords(x, y):
+    for name, t in (("x", x), ("y", y)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+                and t.dim() == 1 and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous 1-D float32 GPU tensor")
+    if x.shape != y.shape or x.device != y.device:
+        raise ValueError("x and y must have the same shape and device")
+
+
+def _check_edges(x, src, dst):
+    for name, t in (("src", src), ("dst", dst)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32
+                and t.dim() == 1 and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous 1-D int32 GPU tensor")
+    if src.shape != dst.shape or src.device != x.device or dst.device != x.device:
+        raise ValueError("src and dst must have the same shape and the device of x")
+
+
+def _out(n, dtype, dev):
+    return torch.zeros(n, dtype=dtype, device=dev)
+
+
+def node_occlusion(x, y, diameter: float, *, async_: bool = False):
+    """N_c: node pairs closer than ``diameter`` (Algorithm 1)."""
+    _check_coords(x, y)
+    out = _out(1, torch.int64, x.device)
+    ws = workspace(x.numel(), 0, x.device)
+    w, wb = _ws_args(ws)
+    check(lib().rb_node_occlusion(_ptr(x), _ptr(y), x.numel(), float(diameter), _ptr(out), w, wb,
+                                  _stream(x.device)), "rb_node_occlusion")
+    return out if async_ else int(out.item())
+
+
+def edge_crossing(x, y, src, dst, *, async_: bool = False):
+    """(E_c, proper crossings) (Algorithm 4)."""
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    out = _out(2, torch.int64, x.device)
+    ws = workspace(x.numel(), src.numel(), x.device)
+    w, wb = _ws_args(ws)
+    check(lib().rb_edge_crossing(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst), src.numel(),
+                                 _ptr(out), _ptr(out) + 8, w, wb, _stream(x.device)),
+          "rb_edge_crossing")
+    if async_:
+        return out
+    c, p = out.tolist()
+    return int(c), int(p)
+
+
+def crossing_angle(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, *, async_: bool = False):
+    """(E_ca, E_c, sum of |ideal - a|/ideal) (Algorithm 5)."""
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    out = _out(3, torch.float64, x.device)        # metric, count (int64 bits), dev sum
+    ws = workspace(x.numel(), src.numel(), x.device)
+    w, wb = _ws_args(ws)
+    p = _ptr(out)
+    check(lib().rb_crossing_angle(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst), src.numel(),
+                                  float(ideal_angle), p, p + 8, p + 16, w, wb, _stream(x.device)),
+          "rb_crossing_angle")
+    if async_:
+        return out
+    vals = out.cpu()
+    return float(vals[0]), int(vals.view(torch.int64)[1]), float(vals[2])
+
+
+def min_angle(x, y, src, dst, *, async_: bool = False):
+    """(M_a, sum of d_v, nodes of degree >= 1) (Algorithm 2)."""
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    out = _out(3, torch.float64, x.device)
+    ws = workspace(x.numel(), src.numel(), x.device)
+    w, wb = _ws_args(ws)
+    p = _ptr(out)
+    check(lib().rb_min_angle(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst), src.numel(),
+                             p, p + 8, p + 16, w, wb, _stream(x.device)), "rb_min_angle")
+    if async_:
+        return out
+    vals = out.cpu()
+    return float(vals[0]), float(vals[1]), int(vals.view(torch.int64)[2])
+
+
+def edge_length_variation(x, y, src, dst, *, async_: bool = False):
+    """(M_l, mean edge length) (Algorithm 3)."""
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    out = _out(2, torch.float64, x.device)
+    ws = workspace(x.numel(), src.numel(), x.device)
+    w, wb = _ws_args(ws)
+    p = _ptr(out)
+    check(lib().rb_edge_length_variation(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst),
+                                         src.numel(), p, p + 8, w, wb, _stream(x.device)),
+          "rb_edge_length_variation")
+    if async_:
+        return out
+    m, mu = out.tolist()
+    return float(m), float(mu)
+
+
+def validate_layout(x, y, src, dst) -> int:
+    """Bit set of violated preconditions (0 when the layout is valid)."""
+    import ctypes as C
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    ws = workspace(x.numel(), src.numel(), x.device)
+    w, wb = _ws_args(ws)
+    flags = C.c_int32(0)
+    rc = lib().rb_validate_layout(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst), src.numel(),
+                                  C.byref(flags), w, wb, _stream(x.device))
+    if rc not in (0, 3):
+        check(rc, "rb_validate_layout")
+    return int(flags.value)
+
+
+@dataclass
+class DeviceLayout:
+    """A layout resident in GPU memory."""
+    x: torch.Tensor
+    y: torch.Tensor
+    src: torch.Tensor
+    dst: torch.Tensor
+    diameter: float = 8.0
+    ideal_angle: float = IDEAL_ANGLE
+
+    @classmethod
+    def from_host(cls, L, device="cuda"):
+        """Copy a ``gen.Layout`` (numpy arrays) to the GPU."""
+        t = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
+        return cls(t(L.x, torch.float32), t(L.y, torch.float32), t(L.src, torch.int32),
+                   t(L.dst, torch.int32), float(L.diameter), float(L.ideal_angle))
+
+
+def evaluate(D: DeviceLayout) -> dict:
+    """All five metrics of one device layout (one pass of the hot path)."""
+    occ = node_occlusion(D.x, D.y, D.diameter, async_=True)
+    ang = crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True)
+    ma = min_angle(D.x, D.y, D.src, D.dst, async_=True)
+    ml = edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)
+    occ, ang, ma, ml = occ.cpu(), ang.cpu(), ma.cpu(), ml.cpu()
+    return dict(node_occlusion=int(occ[0]), crossing_angle=float(ang[0]),
+                edge_crossing=int(ang.view(torch.int64)[1]), crossing_dev_sum=float(ang[2]),
+                min_angle=float(ma[0]), min_angle_sum_dv=float(ma[1]),
+                min_angle_n_used=int(ma.view(torch.int64)[2]), edge_length_variation=float(ml[0]),
+                mean_edge_length=float(ml[1]))

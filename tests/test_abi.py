@@ -1,0 +1,91 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/rb.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+from paper_2411_09809_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _lib.header_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(names) <= exported
+
+
+def test_header_compiles_as_c():
+    src = '#include "rb.h"\nint main(void){return (int)rb_workspace_size(1,1) < 0;}\n'
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c",
+                        "-I", os.path.join(ROOT, "include"), "-"], input=src, text=True,
+                       capture_output=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_version_and_workspace(L):
+    assert L.rb_version().decode().startswith("rb ")
+    a = L.rb_workspace_size(1000, 2000)
+    b = L.rb_workspace_size(50000, 149994)
+    assert a > 0 and b > a and a % 256 == 0 and b % 256 == 0
+    assert L.rb_workspace_size(0, 0) > 0
+    assert L.rb_workspace_size(-1, 5) == 0
+    assert L.rb_workspace_size(10, 1 << 31) == 0
+
+
+def _err(L):
+    return L.rb_last_error().decode()
+
+
+def test_argument_errors_need_no_gpu(L):
+    fake = 0x1000                     # never dereferenced: checks fail first
+    ws_need = L.rb_workspace_size(10, 5)
+    # NULL out pointer
+    assert L.rb_edge_crossing(fake, fake, 10, fake, fake, 5, None, None, fake * 256, ws_need,
+                              None) == _lib.RB_EINVAL
+    assert "out_count" in _err(L)
+    # NULL coordinates
+    assert L.rb_node_occlusion(None, None, 10, 8.0, fake, fake * 256, ws_need,
+                               None) == _lib.RB_EINVAL
+    # bad diameter and ideal angle
+    assert L.rb_node_occlusion(fake, fake, 10, -1.0, fake, fake * 256, ws_need,
+                               None) == _lib.RB_EINVAL
+    assert L.rb_node_occlusion(fake, fake, 10, float("inf"), fake, fake * 256, ws_need,
+                               None) == _lib.RB_EINVAL
+    assert L.rb_crossing_angle(fake, fake, 10, fake, fake, 5, 2.0, fake, None, None, fake * 256,
+                               ws_need, None) == _lib.RB_EINVAL
+    assert "ideal_angle" in _err(L)
+    # negative sizes
+    assert L.rb_min_angle(fake, fake, -3, fake, fake, 5, fake, None, None, fake * 256, ws_need,
+                          None) == _lib.RB_EINVAL
+    # edges without nodes
+    assert L.rb_edge_length_variation(fake, fake, 1, fake, fake, 5, fake, None, fake * 256,
+                                      ws_need, None) == _lib.RB_EINVAL
+    # workspace: NULL, misaligned, too small
+    assert L.rb_edge_crossing(fake, fake, 10, fake, fake, 5, fake, None, None, ws_need,
+                              None) == _lib.RB_EWORKSPACE
+    assert L.rb_edge_crossing(fake, fake, 10, fake, fake, 5, fake, None, fake * 256 + 8, ws_need,
+                              None) == _lib.RB_EWORKSPACE
+    assert L.rb_edge_crossing(fake, fake, 10, fake, fake, 5, fake, None, fake * 256, ws_need - 1,
+                              None) == _lib.RB_EWORKSPACE
+    assert "needed" in _err(L)
+    assert L.rb_timing_read(7, None, None) == _lib.RB_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "librb.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(_lib.RBError):
+        _lib.lib()

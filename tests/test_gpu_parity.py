@@ -1,0 +1,243 @@
+"""Parity of the HIP path (librb through its C-ABI) with the CPU oracle.
+
+Counts must match bit for bit; floating-point metrics within 1e-5 relative
+of the oracle's double-precision value (the kernels accumulate in double, so
+the observed error is ~1e-13).  Inputs are the seeded generators of
+``paper_2411_09809_amd.gen``; full-size workloads compare with oracle values
+stored by ``tests/golden/make_golden.py``.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_09809_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+IDEAL = gen.IDEAL_ANGLE
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def rb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2411_09809_amd import metrics
+    return metrics
+
+
+def dev(L):
+    from paper_2411_09809_amd.metrics import DeviceLayout
+    return DeviceLayout.from_host(L)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_ok(a, b, rtol=RTOL, atol=1e-12):
+    return abs(a - b) <= max(rtol * abs(b), atol)
+
+
+def compare_all(rb, L, want=None):
+    """Every metric of layout L on the GPU against the oracle."""
+    say(f"[parity] {L.name or 'layout'} V={L.n_nodes} E={L.n_edges} d={L.diameter}")
+    D = dev(L)
+    if want is None:
+        want = oracle.all_metrics(L)
+    occ = rb.node_occlusion(D.x, D.y, L.diameter)
+    c, p = rb.edge_crossing(D.x, D.y, D.src, D.dst)
+    eca, cnt, devsum = rb.crossing_angle(D.x, D.y, D.src, D.dst, L.ideal_angle)
+    ma, sdv, used = rb.min_angle(D.x, D.y, D.src, D.dst)
+    ml, mu = rb.edge_length_variation(D.x, D.y, D.src, D.dst)
+    assert occ == want["node_occlusion"]
+    assert c == want["edge_crossing"]
+    assert p == want["proper_crossing"]
+    assert cnt == want["edge_crossing"]
+    assert rel_ok(eca, want["crossing_angle"]), (eca, want["crossing_angle"])
+    assert rel_ok(devsum, want["crossing_dev_sum"]), (devsum, want["crossing_dev_sum"])
+    assert used == want["min_angle_n_used"]
+    assert rel_ok(ma, want["min_angle"]), (ma, want["min_angle"])
+    assert rel_ok(sdv, want["min_angle_sum_dv"], atol=1e-9), (sdv, want["min_angle_sum_dv"])
+    assert rel_ok(ml, want["edge_length_variation"]), (ml, want["edge_length_variation"])
+    assert rel_ok(mu, want["mean_edge_length"])
+    return dict(occ=occ, c=c, p=p, eca=eca, ma=ma, ml=ml)
+
+
+# ---------------------------------------------------------------- hand cases
+
+def _cases():
+    with open(os.path.join(GOLDEN, "hand_cases.json")) as fh:
+        return json.load(fh)["cases"]
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
+def test_hand_cases(rb, case):
+    import torch
+    say(f"[hand] {case['name']}")
+    if "lattice" in case:
+        L = gen.square_lattice(case["lattice"]["k"], case["lattice"]["spacing"], case["diameter"])
+    else:
+        e = np.array(case["edges"], dtype=np.int32).reshape(-1, 2)
+        L = gen._finish(case["x"], case["y"], e[:, 0], e[:, 1])
+    D = dev(L)
+    ex = case["expect"]
+    if "node_occlusion" in ex:
+        assert rb.node_occlusion(D.x, D.y, case["diameter"]) == ex["node_occlusion"]
+    if "edge_crossing" in ex:
+        assert rb.edge_crossing(D.x, D.y, D.src, D.dst)[0] == ex["edge_crossing"]
+    if "proper_crossing" in ex:
+        assert rb.edge_crossing(D.x, D.y, D.src, D.dst)[1] == ex["proper_crossing"]
+    if "crossing_angle" in ex:
+        assert rb.crossing_angle(D.x, D.y, D.src, D.dst, IDEAL)[0] == pytest.approx(
+            ex["crossing_angle"], abs=1e-12)
+    if "min_angle" in ex:
+        assert rb.min_angle(D.x, D.y, D.src, D.dst)[0] == pytest.approx(ex["min_angle"], abs=1e-12)
+    if "edge_length_variation" in ex:
+        assert rb.edge_length_variation(D.x, D.y, D.src, D.dst)[0] == pytest.approx(
+            ex["edge_length_variation"], abs=1e-12)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [4, 7, 10, 40])
+def test_complete_convex(rb, n):
+    L = gen.complete_convex(n)
+    D = dev(L)
+    assert rb.edge_crossing(D.x, D.y, D.src, D.dst) == (math.comb(n, 4), math.comb(n, 4))
+
+
+def test_two_rows_star_grid(rb):
+    for m, n in [(3, 4), (30, 41)]:
+        L = gen.two_row_bipartite(m, n)
+        D = dev(L)
+        want = math.comb(m, 2) * math.comb(n, 2)
+        assert rb.edge_crossing(D.x, D.y, D.src, D.dst) == (want, want)
+    for L in (gen.star(300), gen.grid(40, 50)):
+        D = dev(L)
+        assert rb.edge_crossing(D.x, D.y, D.src, D.dst) == (0, 0)
+        assert rb.crossing_angle(D.x, D.y, D.src, D.dst)[:2] == (1.0, 0)
+
+
+# ---------------------------------------------------------------- workloads
+
+def test_uniform_1000_2000(rb):
+    compare_all(rb, gen.uniform_layout(seed=0))
+
+
+@pytest.mark.parametrize("V,E,extent,seed", [
+    (2, 1, 16, 1), (3, 2, 16, 2), (40, 255, 32, 3), (60, 256, 32, 4), (70, 257, 64, 5),
+    (300, 1023, 100, 6), (300, 1024, 100, 7), (301, 1025, 100, 8), (800, 2047, 512, 9),
+    (900, 3001, 8, 10), (4095, 4097, 4096, 11), (5000, 9000, 1 << 20, 12),
+])
+def test_ragged_sizes(rb, V, E, extent, seed):
+    """Sizes around the tile edges (256-edge chunks, 1024-edge and 4096-node
+    row tiles); small extents force collinear, touching and coincident cases
+    and zero-length edges."""
+    L = gen.uniform_layout(V, E, extent=extent, diameter=3.5 if extent < 64 else 40.0, seed=seed)
+    compare_all(rb, L)
+
+
+def test_negative_and_extreme_coordinates(rb):
+    rng = np.random.default_rng(21)
+    V, E = 1500, 4000
+    lim = 1 << 20
+    x = rng.integers(-lim, lim + 1, size=V)
+    y = rng.integers(-lim, lim + 1, size=V)
+    x[:50] = lim
+    y[50:100] = -lim
+    s, d = gen.distinct_random_edges(rng, V, E)
+    L = gen._finish(x, y, s, d, diameter=300000.0, name="extreme")
+    compare_all(rb, L)
+
+
+def test_empty_layouts(rb):
+    import torch
+    say("[empty]")
+    z = torch.zeros(0, dtype=torch.float32, device="cuda")
+    zi = torch.zeros(0, dtype=torch.int32, device="cuda")
+    assert rb.node_occlusion(z, z, 8.0) == 0
+    assert rb.edge_crossing(z, z, zi, zi) == (0, 0)
+    assert rb.crossing_angle(z, z, zi, zi) == (1.0, 0, 0.0)
+    assert rb.min_angle(z, z, zi, zi) == (1.0, 0.0, 0)
+    assert rb.edge_length_variation(z, z, zi, zi)[0] == 0.0
+    one = torch.ones(1, dtype=torch.float32, device="cuda")
+    assert rb.node_occlusion(one, one, 8.0) == 0
+    assert rb.min_angle(one, one, zi, zi) == (1.0, 0.0, 0)
+
+
+@pytest.mark.parametrize("d", [0.0, 1e-300, 0.5, 1.0, 2.0, math.sqrt(2), 7.999999999999999, 8.0,
+                               8.000000000000002, 100.5, 5000.0, 1e7])
+def test_occlusion_diameters(rb, d):
+    L = gen.uniform_layout(3000, 1, extent=300, seed=5)
+    D = dev(L)
+    assert rb.node_occlusion(D.x, D.y, d) == oracle.node_occlusion(L.x, L.y, d)
+
+
+def test_high_degree_min_angle(rb):
+    """Stars of every min-angle path: per-thread (deg <= 16), LDS sort
+    (<= 2048) and in-place global sort (larger)."""
+    rng = np.random.default_rng(8)
+    for leaves in (3, 16, 17, 300, 2048, 2049, 9000):
+        V = leaves + 1 + 50
+        x = rng.integers(0, 4096, size=V)
+        y = rng.integers(0, 4096, size=V)
+        s = np.zeros(leaves, dtype=np.int64)
+        d = np.arange(1, leaves + 1)
+        extra_s, extra_d = gen.distinct_random_edges(rng, 50, 60)
+        s = np.concatenate([s, extra_s + leaves + 1])
+        d = np.concatenate([d, extra_d + leaves + 1])
+        L = gen._finish(x, y, s, d, name=f"star{leaves}")
+        say(f"[min_angle] star {leaves}")
+        D = dev(L)
+        ma, sdv, used = rb.min_angle(D.x, D.y, D.src, D.dst)
+        wm, ws, wu = oracle.min_angle(L.x, L.y, L.src, L.dst)
+        assert used == wu
+        assert rel_ok(ma, wm) and rel_ok(sdv, ws, atol=1e-9)
+
+
+def test_deterministic_repeats(rb):
+    L = gen.uniform_layout(3000, 9000, extent=2048, seed=3)
+    D = dev(L)
+    a = [rb.crossing_angle(D.x, D.y, D.src, D.dst) for _ in range(3)]
+    b = [rb.min_angle(D.x, D.y, D.src, D.dst) for _ in range(3)]
+    assert a[0] == a[1] == a[2]
+    assert b[0] == b[1] == b[2]
+
+
+def test_validation_flags(rb):
+    import torch
+    say("[validate]")
+    L = gen.uniform_layout(100, 200, seed=1)
+    D = dev(L)
+    assert rb.validate_layout(D.x, D.y, D.src, D.dst) == 0
+    x = D.x.clone(); x[3] = 0.5
+    assert rb.validate_layout(x, D.y, D.src, D.dst) & 1
+    y = D.y.clone(); y[7] = 2.0 ** 21
+    assert rb.validate_layout(D.x, y, D.src, D.dst) & 2
+    s = D.src.clone(); s[5] = 100
+    assert rb.validate_layout(D.x, D.y, s, D.dst) & 4
+    s = D.src.clone(); s[5] = D.dst[5]
+    assert rb.validate_layout(D.x, D.y, s, D.dst) & 8
+    s = torch.cat([D.src, D.dst[:1]]); d = torch.cat([D.dst, D.src[:1]])
+    assert rb.validate_layout(D.x, D.y, s, d) & 16
+
+
+@pytest.mark.parametrize("name", ["uniform_V1000_E2000_s0", "ba_cluster_V50000_s0",
+                                  "rgg_V20000_s0"])
+def test_full_size_workloads(rb, name):
+    with open(os.path.join(GOLDEN, "workloads.json")) as fh:
+        want = json.load(fh)[name]
+    build = {"uniform_V1000_E2000_s0": lambda: gen.uniform_layout(seed=0),
+             "ba_cluster_V50000_s0": lambda: gen.ba_cluster_layout(seed=0),
+             "rgg_V20000_s0": lambda: gen.geometric_layout(seed=0)}[name]
+    L = build()
+    assert L.digest() == want["digest"], "generator output changed; rerun make_golden.py"
+    compare_all(rb, L, want)
