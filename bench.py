@@ -52,6 +52,57 @@ def cpu_baseline(L, budget_pairs: float):
                       f"({math.comb(S, 2):.3e} pairs) of the same layout, {dt:.1f} s"}
 
 
+def bench_batch(torch, steps: int):
+    """512 layouts of uneven size: one captured hipGraph replay per
+    evaluation against 512 plain single-layout launch sets."""
+    from paper_2411_09809_amd import gen, metrics
+    from paper_2411_09809_amd.batch import Batch
+
+    layouts = gen.batch_layouts(512, seed=0)
+    B = Batch(layouts)
+    pairs = sum(math.comb(L.n_edges, 2) for L in layouts)
+    tuned_ms = B.autotune(repeats=2)
+    B.capture()
+    B.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.replay()
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / steps
+    B.evaluate()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.evaluate()
+    torch.cuda.synchronize()
+    eager_s = (time.perf_counter() - t0) / steps
+    views = [B.layout_views(i) for i in range(B.n)]
+
+    def plain():
+        for x, y, s, d, diam in views:
+            metrics.node_occlusion(x, y, diam, async_=True)
+            metrics.crossing_angle(x, y, s, d, async_=True)
+            metrics.min_angle(x, y, s, d, async_=True)
+            metrics.edge_length_variation(x, y, s, d, async_=True)
+
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_steps = max(1, steps // 2)
+    for _ in range(plain_steps):
+        plain()
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / plain_steps
+    return {"workload": "512 layouts, |V| log-uniform in [200, 20000], |E| = U[1.5,4]|V|, "
+                        "coords in [0,2^16)^2, diameter 8",
+            "edge_pairs": pairs, "graph_ms": graph_s * 1e3, "eager_ms": eager_s * 1e3,
+            "plain_512_launch_sets_ms": plain_s * 1e3,
+            "graph_pairs_per_s": pairs / graph_s, "plain_pairs_per_s": pairs / plain_s,
+            "speedup_vs_plain": plain_s / graph_s, "autotuned_sweeps_ms": tuned_ms,
+            "variants": B.variants()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +112,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=float, default=5e9,
                     help="edge pairs in the CPU-baseline sample")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-layout comparison")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -96,6 +148,21 @@ def main():
     node_pairs = math.comb(L.n_nodes, 2)
     log(f"[bench] workload V={L.n_nodes} E={L.n_edges} pairs={pairs:.3e}")
 
+    # pick the fastest sweep variants for this layout's size classes (untimed)
+    import ctypes as C
+    ws = metrics.workspace(L.n_nodes, L.n_edges, dev)
+    w, wb = metrics._ws_args(ws)
+    tuned = C.c_double()
+    _lib.check(_lib.lib().rb_autotune(D.x.data_ptr(), D.y.data_ptr(), L.n_nodes, D.src.data_ptr(),
+                                      D.dst.data_ptr(), L.n_edges, D.diameter, D.ideal_angle, 2,
+                                      C.byref(tuned), w, wb, metrics._stream(dev)), "rb_autotune")
+    variant = {}
+    for kind, name in ((1, "cross_angle"), (2, "occlusion")):
+        rows, waves = C.c_int(), C.c_int()
+        n_items = L.n_nodes if kind == 2 else L.n_edges
+        _lib.check(_lib.lib().rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves)), "q")
+        variant[name] = {"rows_per_thread": rows.value, "waves_per_simd": waves.value}
+
     def step():
         return [metrics.node_occlusion(D.x, D.y, D.diameter, async_=True),
                 metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True),
@@ -115,7 +182,6 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     R.rb_timing_enable(0)
-    import ctypes as C
     ms, n = C.c_double(), C.c_int64()
     _lib.check(R.rb_timing_read(0, C.byref(ms), C.byref(n)), "rb_timing_read")
     cross_ms = ms.value / max(n.value, 1)
@@ -146,8 +212,9 @@ def main():
                    "n_nodes": L.n_nodes, "n_edges": L.n_edges, "seed": args.seed},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                     "kernel": "cross_sweep_kernel<4,true>",
-                     "ops_per_pair": OPS_PER_EDGE_PAIR, "kernel_ms": cross_ms},
+                     "kernel": "cross_sweep_kernel (crossing + angle)",
+                     "ops_per_pair": OPS_PER_EDGE_PAIR, "kernel_ms": cross_ms,
+                     "variant": variant["cross_angle"]},
         "kernels": {"edge_pair_sweep_ms": cross_ms,
                     "edge_pair_sweep_pairs_per_s": pairs / (cross_ms * 1e-3),
                     "node_pair_sweep_ms": occl_ms,
@@ -155,6 +222,9 @@ def main():
                     "node_pair_sweep_valu_frac":
                         OPS_PER_NODE_PAIR * node_pairs / (occl_ms * 1e-3) / VALU_PEAK_OPS},
     }
+    if not args.no_batch:
+        log("[bench] batched 512 layouts ...")
+        rec["batched"] = bench_batch(torch, max(3, args.steps // 4))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(L, args.cpu_pairs)

@@ -138,6 +138,78 @@ rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes,
                              const int32_t *src, const int32_t *dst, int64_t n_edges,
                              int32_t *out_flags, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ batches
+ * Many layouts of uneven size in one evaluation.  The layouts are
+ * concatenated: x, y hold the nodes of layout 0, then layout 1, ...;
+ * src, dst the edges likewise, with end ids LOCAL to their layout
+ * (0 <= id < nodes of that layout).  node_off / edge_off (host int64,
+ * n_layouts + 1 entries, starting at 0, nondecreasing) give each layout's
+ * range.  Each all-pairs sweep runs as ONE persistent launch over the unit
+ * lists of all layouts; per-layout results are combined in a fixed order.
+ *
+ * rb_batch_create builds the host plan (diameters: host double[n_layouts]).
+ * rb_batch_upload writes the plan's tables into the workspace (at least
+ * rb_batch_workspace_size bytes, 256-byte aligned) and synchronises
+ * `stream`; evaluations must use that same workspace.
+ * rb_batch_evaluate only enqueues kernels (capturable): outputs are device
+ * arrays of n_layouts entries, each may be NULL to skip that metric --
+ * node occlusion N_c, crossing count E_c, crossing angle E_ca, minimum
+ * angle M_a, edge length variation M_l, with the per-layout definitions of
+ * the single-layout calls.
+ * rb_batch_autotune times the sweep variants on this batch, keeps the
+ * fastest in the plan and the tuning table, re-uploads; it synchronises.
+ * rb_batch_graph_create captures rb_batch_evaluate with these arguments into
+ * a hipGraph (on a private stream); rb_graph_launch replays it on `stream`.
+ * The graph reuses the given pointers: keep them valid while it is used. */
+typedef struct rb_batch rb_batch;
+typedef struct rb_graph rb_graph;
+rb_status rb_batch_create(int64_t n_layouts, const int64_t *node_off, const int64_t *edge_off,
+                          const double *diameters, rb_batch **out);
+size_t rb_batch_workspace_size(const rb_batch *batch);
+rb_status rb_batch_upload(rb_batch *batch, void *ws, size_t ws_bytes, void *stream);
+rb_status rb_batch_evaluate(const rb_batch *batch, const float *x, const float *y,
+                            const int32_t *src, const int32_t *dst, double ideal_angle,
+                            uint64_t *out_occlusion, uint64_t *out_crossings,
+                            double *out_crossing_angle, double *out_min_angle, double *out_elv,
+                            void *ws, size_t ws_bytes, void *stream);
+rb_status rb_batch_autotune(rb_batch *batch, const float *x, const float *y, const int32_t *src,
+                            const int32_t *dst, double ideal_angle, int repeats,
+                            double *out_best_ms, void *ws, size_t ws_bytes, void *stream);
+rb_status rb_batch_variants(const rb_batch *batch, int *cross_rows, int *cross_waves,
+                            int *occl_rows, int *occl_waves);
+void rb_batch_destroy(rb_batch *batch);
+rb_status rb_batch_graph_create(const rb_batch *batch, const float *x, const float *y,
+                                const int32_t *src, const int32_t *dst, double ideal_angle,
+                                uint64_t *out_occlusion, uint64_t *out_crossings,
+                                double *out_crossing_angle, double *out_min_angle,
+                                double *out_elv, void *ws, size_t ws_bytes, rb_graph **out);
+rb_status rb_graph_launch(rb_graph *graph, void *stream);
+void rb_graph_destroy(rb_graph *graph);
+
+/* Autotuning of the all-pairs sweeps.  The sweeps come in variants (rows
+ * of the pair matrix held per thread, waves per SIMD); all variants give
+ * identical results.  Each call above picks the variant recorded for the
+ * layout's size class (floor(log2) of its edge count, node count for the
+ * occlusion sweep); built-in defaults apply until tuned.
+ *   kind: 0 = edge crossing, 1 = crossing angle, 2 = node occlusion;
+ *   batch: 0 = single-layout calls, 1 = rb_batch_* calls.
+ * rb_autotune times every variant of the three sweeps on the given layout
+ * (`repeats` timed launches each, after one untimed launch), records the
+ * fastest for its size classes and returns the sum of the three best mean
+ * launch times in *out_best_ms (host, may be NULL).  It synchronises
+ * `stream`.  rb_tune_set forces a variant index (0 .. variants-1) for a size
+ * class; rb_tune_query reports the rows and waves of the variant in use.
+ * rb_tune_save / rb_tune_load write and read the table as text; the file
+ * named by the environment variable RB_TUNE_CACHE is loaded on first use. */
+rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes,
+                      const int32_t *src, const int32_t *dst, int64_t n_edges,
+                      double diameter, double ideal_angle, int repeats, double *out_best_ms,
+                      void *ws, size_t ws_bytes, void *stream);
+rb_status rb_tune_set(int kind, int batch, int64_t n_items, int variant);
+rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *waves);
+rb_status rb_tune_save(const char *path);
+rb_status rb_tune_load(const char *path);
+
 /* Kernel timing for measurement.  While enabled, the library records a HIP
  * event pair on the caller's stream around each launch of its all-pairs
  * sweep kernels.  rb_timing_read waits for the recorded events and returns

@@ -40,6 +40,25 @@ _SIGS = {
                                  C.c_int),
     "rb_validate_layout": ([_vp, _vp, _i64, _vp, _vp, _i64, C.POINTER(C.c_int32), _vp, _sz, _vp],
                            C.c_int),
+    "rb_autotune": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, C.c_int, C.POINTER(C.c_double),
+                     _vp, _sz, _vp], C.c_int),
+    "rb_tune_set": ([C.c_int, C.c_int, _i64, C.c_int], C.c_int),
+    "rb_tune_query": ([C.c_int, C.c_int, _i64, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+    "rb_tune_save": ([C.c_char_p], C.c_int),
+    "rb_tune_load": ([C.c_char_p], C.c_int),
+    "rb_batch_create": ([_i64, _vp, _vp, _vp, C.POINTER(C.c_void_p)], C.c_int),
+    "rb_batch_workspace_size": ([_vp], _sz),
+    "rb_batch_upload": ([_vp, _vp, _sz, _vp], C.c_int),
+    "rb_batch_evaluate": ([_vp, _vp, _vp, _vp, _vp, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+                          C.c_int),
+    "rb_batch_autotune": ([_vp, _vp, _vp, _vp, _vp, _f64, C.c_int, C.POINTER(C.c_double), _vp,
+                           _sz, _vp], C.c_int),
+    "rb_batch_variants": ([_vp] + [C.POINTER(C.c_int)] * 4, C.c_int),
+    "rb_batch_destroy": ([_vp], None),
+    "rb_batch_graph_create": ([_vp, _vp, _vp, _vp, _vp, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                               C.POINTER(C.c_void_p)], C.c_int),
+    "rb_graph_launch": ([_vp, _vp], C.c_int),
+    "rb_graph_destroy": ([_vp], None),
     "rb_timing_enable": ([C.c_int], C.c_int),
     "rb_timing_reset": ([], C.c_int),
     "rb_timing_read": ([C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),

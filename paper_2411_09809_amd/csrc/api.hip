@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -68,18 +69,6 @@ struct TimedLaunch {
     }
 };
 
-// Largest integer T with T < d^2 (d finite, >= 0).  fma(d, d, -n) carries the
-// exact sign of d^2 - n.  Squared distances are below 2^43, so T is capped.
-double occlusion_threshold(double d) {
-    if (d <= 0.0) return -1.0;
-    if (d < 1.0) return 0.0;
-    if (d >= 4194304.0) return 17592186044416.0;   // d >= 2^22: T = 2^44 covers all
-    double t = std::ceil(d * d) - 1.0;
-    while (std::fma(d, d, -(t + 1.0)) > 0.0) t += 1.0;
-    while (std::fma(d, d, -t) <= 0.0) t -= 1.0;
-    return t;
-}
-
 rb_status check_sizes(int64_t n_nodes, int64_t n_edges) {
     if (n_nodes < 0 || n_nodes > kMaxNodes)
         return fail(RB_EINVAL, "n_nodes = %lld out of range [0, 2^31-1]", (long long)n_nodes);
@@ -111,6 +100,30 @@ int g_cu_count[64];
 
 }  // namespace
 
+int set_error(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return status;
+}
+
+int hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+
+void clear_error() { g_err.clear(); }
+
+double occlusion_threshold(double d) {
+    if (d <= 0.0) return -1.0;
+    if (d < 1.0) return 0.0;
+    if (d >= 4194304.0) return 17592186044416.0;   // d >= 2^22: T = 2^44 covers all
+    double t = std::ceil(d * d) - 1.0;
+    while (std::fma(d, d, -(t + 1.0)) > 0.0) t += 1.0;
+    while (std::fma(d, d, -t) <= 0.0) t -= 1.0;
+    return t;
+}
+
 int device_cu_count() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
@@ -128,8 +141,8 @@ bool ws_layout(int64_t n_nodes, int64_t n_edges, WsLayout *L) {
     if (n_nodes < 0 || n_nodes > kMaxNodes || n_edges < 0 || n_edges > kMaxEdges) return false;
     const int64_t V = n_nodes > 0 ? n_nodes : 1;
     const int64_t E = n_edges > 0 ? n_edges : 1;
-    L->n_edge_pad = (int64_t)round_up((size_t)E, kEdgePad);
-    L->n_node_pad = (int64_t)round_up((size_t)V, kNodePad);
+    L->n_edge_pad = (int64_t)round_up((size_t)E, kRecPad);
+    L->n_node_pad = (int64_t)round_up((size_t)V, kRecPad);
     int64_t h = 1024;
     while (h < 2 * E) h <<= 1;
     L->hash_size = h;
@@ -185,15 +198,22 @@ rb_status rb_node_occlusion(const float *x, const float *y, int64_t n_nodes, dou
     char *w = (char *)ws;
     NodeRec *rec = (NodeRec *)(w + L.node_rec);
     OcclPartial *part = (OcclPartial *)(w + L.partial);
-    SweepPlan p = plan_occl(n_nodes);
+    const int v = tuned_variant(2, false, n_nodes);
+    const int rows = occl_variant(v).rows;
+    SweepArgs a;
+    a.table = nullptr;
+    a.single = sweep_layout(n_nodes, rows, 0, 0);
+    a.n_layouts = 1;
+    a.n_units = sweep_units(n_nodes, rows);
+    const int grid = (int)std::min<int64_t>(a.n_units, occl_grid(v));
     hipError_t e = launch_node_prep(x, y, n_nodes, L.n_node_pad, occlusion_threshold(diameter),
                                     rec, st);
     if (e != hipSuccess) return hip_fail(e, "node_prep launch");
     TimedLaunch tl(1, st);
-    e = launch_occl_sweep(rec, p, part, st);
+    e = launch_occl_sweep(v, rec, a, grid, part, st);
     tl.done();
     if (e != hipSuccess) return hip_fail(e, "occlusion sweep launch");
-    e = launch_occl_finalize(part, p.grid, (unsigned long long *)out_count, st);
+    e = launch_occl_finalize(part, grid, (unsigned long long *)out_count, st);
     if (e != hipSuccess) return hip_fail(e, "occlusion finalize launch");
     return RB_OK;
 }
@@ -211,14 +231,21 @@ static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes
     char *w = (char *)ws;
     EdgeRec *rec = (EdgeRec *)(w + L.edge_rec);
     CrossPartial *part = (CrossPartial *)(w + L.partial);
-    SweepPlan p = plan_cross(n_edges, angle);
+    const int v = tuned_variant(angle ? 1 : 0, false, n_edges);
+    const int rows = cross_variant(v).rows;
+    SweepArgs a;
+    a.table = nullptr;
+    a.single = sweep_layout(n_edges, rows, 0, 0);
+    a.n_layouts = 1;
+    a.n_units = sweep_units(n_edges, rows);
+    const int grid = (int)std::min<int64_t>(a.n_units, cross_grid(v, angle));
     hipError_t e = launch_edge_prep(x, y, src, dst, n_nodes, n_edges, L.n_edge_pad, rec, st);
     if (e != hipSuccess) return hip_fail(e, "edge_prep launch");
     TimedLaunch tl(0, st);
-    e = launch_cross_sweep(rec, p, angle, ideal, part, st);
+    e = launch_cross_sweep(v, angle, rec, a, grid, ideal, part, st);
     tl.done();
     if (e != hipSuccess) return hip_fail(e, "crossing sweep launch");
-    e = launch_cross_finalize(part, p.grid, ideal, (unsigned long long *)out_count,
+    e = launch_cross_finalize(part, grid, ideal, (unsigned long long *)out_count,
                               (unsigned long long *)out_proper, out_metric, out_dev_sum, st);
     if (e != hipSuccess) return hip_fail(e, "crossing finalize launch");
     return RB_OK;
@@ -308,6 +335,119 @@ rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes, co
         g_err = msg;
         return RB_EDOMAIN;
     }
+    return RB_OK;
+}
+
+// Times every sweep variant on this layout (after one untimed launch each)
+// and records the fastest for the layout's size class.  Synchronises.
+rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                      const int32_t *dst, int64_t n_edges, double diameter, double ideal_angle,
+                      int repeats, double *out_best_ms, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (!(diameter >= 0.0) || !std::isfinite(diameter))
+        return fail(RB_EINVAL, "diameter must be finite and >= 0");
+    if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
+        return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
+    if (repeats < 1 || repeats > 1000) return fail(RB_EINVAL, "repeats must be in [1, 1000]");
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    EdgeRec *erec = (EdgeRec *)(w + L.edge_rec);
+    NodeRec *nrec = (NodeRec *)(w + L.node_rec);
+    hipError_t e = launch_edge_prep(x, y, src, dst, n_nodes, n_edges, L.n_edge_pad, erec, st);
+    if (e == hipSuccess)
+        e = launch_node_prep(x, y, n_nodes, L.n_node_pad, occlusion_threshold(diameter), nrec, st);
+    if (e != hipSuccess) return hip_fail(e, "autotune prep");
+    hipEvent_t ea, eb;
+    if ((e = hipEventCreate(&ea)) != hipSuccess) return hip_fail(e, "autotune event");
+    if ((e = hipEventCreate(&eb)) != hipSuccess) {
+        (void)hipEventDestroy(ea);
+        return hip_fail(e, "autotune event");
+    }
+    auto timed = [&](auto &&launch, float *ms) -> hipError_t {
+        hipError_t r = launch();                    // untimed: first-launch costs
+        if (r != hipSuccess) return r;
+        if ((r = hipEventRecord(ea, st)) != hipSuccess) return r;
+        for (int k = 0; k < repeats && r == hipSuccess; ++k) r = launch();
+        if (r != hipSuccess) return r;
+        if ((r = hipEventRecord(eb, st)) != hipSuccess) return r;
+        if ((r = hipEventSynchronize(eb)) != hipSuccess) return r;
+        if ((r = hipEventElapsedTime(ms, ea, eb)) != hipSuccess) return r;
+        *ms /= repeats;
+        return hipSuccess;
+    };
+    double best_total = 0.0;
+    for (int kind = 0; kind < 3 && e == hipSuccess; ++kind) {
+        const bool occl = kind == 2, angle = kind == 1;
+        const int nv = occl ? kOcclVariants : kCrossVariants;
+        const int64_t n = occl ? n_nodes : n_edges;
+        int best = -1;
+        float best_ms = 0.f;
+        for (int v = 0; v < nv && e == hipSuccess; ++v) {
+            const int rows = occl ? occl_variant(v).rows : cross_variant(v).rows;
+            SweepArgs a;
+            a.table = nullptr;
+            a.single = sweep_layout(n, rows, 0, 0);
+            a.n_layouts = 1;
+            a.n_units = sweep_units(n, rows);
+            const int grid = (int)std::min<int64_t>(a.n_units, occl ? occl_grid(v) : cross_grid(v, angle));
+            float ms = 0.f;
+            if (occl)
+                e = timed([&] { return launch_occl_sweep(v, nrec, a, grid, (OcclPartial *)(w + L.partial), st); }, &ms);
+            else
+                e = timed([&] { return launch_cross_sweep(v, angle, erec, a, grid, ideal_angle, (CrossPartial *)(w + L.partial), st); }, &ms);
+            if (e == hipSuccess && (best < 0 || ms < best_ms)) {
+                best = v;
+                best_ms = ms;
+            }
+        }
+        if (e == hipSuccess) {
+            set_tuned_variant(kind, false, n, best);
+            best_total += best_ms;
+        }
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (out_best_ms) *out_best_ms = best_total;
+    return RB_OK;
+}
+
+rb_status rb_tune_set(int kind, int batch, int64_t n_items, int variant) {
+    g_err.clear();
+    if (kind < 0 || kind > 2) return fail(RB_EINVAL, "kind must be 0, 1 or 2");
+    if (n_items < 0) return fail(RB_EINVAL, "n_items must be >= 0");
+    const int nv = kind == 2 ? kOcclVariants : kCrossVariants;
+    if (variant < 0 || variant >= nv) return fail(RB_EINVAL, "variant must be in [0, %d)", nv);
+    set_tuned_variant(kind, batch != 0, n_items, variant);
+    return RB_OK;
+}
+
+rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *waves) {
+    g_err.clear();
+    if (kind < 0 || kind > 2) return fail(RB_EINVAL, "kind must be 0, 1 or 2");
+    if (n_items < 0) return fail(RB_EINVAL, "n_items must be >= 0");
+    const int v = tuned_variant(kind, batch != 0, n_items);
+    const SweepVariant sv = kind == 2 ? occl_variant(v) : cross_variant(v);
+    if (rows) *rows = sv.rows;
+    if (waves) *waves = sv.waves;
+    return RB_OK;
+}
+
+rb_status rb_tune_save(const char *path) {
+    g_err.clear();
+    if (!path) return fail(RB_EINVAL, "path is NULL");
+    if (!save_tuning(path)) return fail(RB_EINVAL, "cannot write %s", path);
+    return RB_OK;
+}
+
+rb_status rb_tune_load(const char *path) {
+    g_err.clear();
+    if (!path) return fail(RB_EINVAL, "path is NULL");
+    if (!load_tuning(path)) return fail(RB_EINVAL, "cannot read %s", path);
     return RB_OK;
 }
 

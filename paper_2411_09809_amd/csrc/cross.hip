@@ -1,14 +1,16 @@
 // All-pairs edge-crossing sweep (Algorithm 4) with the crossing-angle term
 // of Algorithm 5 fused in.
 //
-// Work decomposition.  The upper triangle of the |E| x |E| pair matrix is cut
-// into units: a row tile of R = 256*K edges (each of the 256 threads of a
-// block keeps K edge records in registers) against a chunk of 256 column
-// edges staged in LDS.  Row tile I meets chunks c >= I*K (the first K of them
-// overlap the tile itself and keep only pairs with column index > row index).
-// A persistent grid takes equal contiguous ranges of the unit list, so a
-// block keeps its row registers across consecutive units and every block
-// does the same number of units (+-1).
+// Work decomposition.  The upper triangle of each layout's |E| x |E| pair
+// matrix is cut into units: a row tile of R = 256*K edges (each of the 256
+// threads of a block keeps K edge records in registers) against a chunk of
+// 256 column edges staged in LDS.  Row tile I meets chunks c >= I*K (the
+// first K of them overlap the tile itself and keep only pairs with column
+// index > row index).  The units of all layouts form one list; a persistent
+// grid takes equal contiguous ranges of it, so a block keeps its row
+// registers across consecutive units and every block does the same number
+// of units (+-1).  A block writes one partial result per layout it touches,
+// into slot block + layout, so the final sums run in a fixed order.
 //
 // Per pair (row edge e, column edge f), all in exact double arithmetic:
 //   o1 = L_e(P_f),  o2 = o1 + cross,   o3 = L_f(P_e),  o4 = o3 - cross,
@@ -30,37 +32,45 @@ namespace {
 
 constexpr double kHalfPi = 1.5707963267948966192;
 
+// wave-wide count of lanes with p set; the ballot of a compare result is the
+// compare's own lane mask, so this costs two scalar instructions
 __device__ __forceinline__ uint32_t popc_ballot(bool p) {
-    return (uint32_t)__popcll(__ballot(p));
+    return (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
 }
 
 __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
     return I * nC - (int64_t)K * I * (I - 1) / 2;
 }
 
-// Rare path: both products <= 0 and at least one is zero.
-__device__ __forceinline__ bool touching_pair(double p12, double p34, double rx, double ry,
-                                              double rdx, double rdy, int rs, int rt,
-                                              const EdgeRec &f) {
-    bool incident = (rs == f.s) | (rs == f.t) | (rt == f.s) | (rt == f.t);
+// Rare path for one pair: both products <= 0 and at least one is zero.  The
+// orientations are recomputed here from laundered copies of the column
+// values, which keeps this arithmetic out of the common path.
+__device__ __noinline__ bool touching_pair(double rx, double ry, double rdx, double rdy, double rc,
+                                           int2 rid, double fx, double fy, double fdx,
+                                           double fdy, double fc, int2 fid) {
+    const double o1 = fma(-rdy, fx, fma(rdx, fy, -rc));
+    const double o3 = fma(-fdy, rx, fma(fdx, ry, -fc));
+    const double cr = fma(-rdy, fdx, rdx * fdy);
+    const double p12 = o1 * (o1 + cr), p34 = o3 * (o3 - cr);
+    const bool incident = (rid.x == fid.x) | (rid.x == fid.y) | (rid.y == fid.x) | (rid.y == fid.y);
     bool ok = fmin(p12, p34) < 0.0;
     if (!ok) {
-        double ax0 = fmin(rx, rx + rdx), ax1 = fmax(rx, rx + rdx);
-        double ay0 = fmin(ry, ry + rdy), ay1 = fmax(ry, ry + rdy);
-        double bx0 = fmin(f.x, f.x + f.dx), bx1 = fmax(f.x, f.x + f.dx);
-        double by0 = fmin(f.y, f.y + f.dy), by1 = fmax(f.y, f.y + f.dy);
+        const double ax0 = fmin(rx, rx + rdx), ax1 = fmax(rx, rx + rdx);
+        const double ay0 = fmin(ry, ry + rdy), ay1 = fmax(ry, ry + rdy);
+        const double bx0 = fmin(fx, fx + fdx), bx1 = fmax(fx, fx + fdx);
+        const double by0 = fmin(fy, fy + fdy), by1 = fmax(fy, fy + fdy);
         ok = (fmax(ax0, bx0) <= fmin(ax1, bx1)) && (fmax(ay0, by0) <= fmin(ay1, by1));
     }
-    return ok & !incident;
+    return ok && !incident;
 }
 
 template <int K, bool ANGLE, bool DIAG>
 __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
+                                            const int2 *__restrict__ rid,
                                             const double (&rX)[K], const double (&rY)[K],
                                             const double (&rDX)[K], const double (&rDY)[K],
                                             const double (&rC)[K], const double (&rTH)[K],
-                                            const int (&rS)[K], const int (&rT)[K],
-                                            int64_t row0, int64_t col0, double ideal,
+                                            int tid, int64_t row0, int64_t col0, double ideal,
                                             double angc, uint32_t &n_proper, uint32_t &n_touch,
                                             double &acc) {
 #pragma unroll 2
@@ -87,100 +97,137 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
                 v = angc + fabs(u);
                 acc = fma(prop ? 1.0 : 0.0, fabs(v), acc);
             }
-            if (__ballot(zero)) {
+            if (__builtin_expect(__builtin_amdgcn_ballot_w64(zero) != 0, 0)) {
                 bool ok = false;
-                if (zero)
-                    ok = touching_pair(p12, p34, rX[r], rY[r], rDX[r], rDY[r], rS[r], rT[r],
-                                       col[j]);
+                if (zero) {
+                    double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC;
+                    __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc));
+                    const int2 fid = make_int2(col[j].s, col[j].t);
+                    ok = touching_pair(rX[r], rY[r], rDX[r], rDY[r], rC[r], rid[r * kBlock + tid],
+                                       fx, fy, fdx, fdy, fc, fid);
+                    if (ANGLE && ok) {
+                        // parallel lines or a zero-length edge: a = 0
+                        const double crs = fma(-rDY[r], fdx, rDX[r] * fdy);
+                        acc += (crs == 0.0) ? ideal : fabs(v);
+                    }
+                }
                 n_touch += popc_ballot(ok);
-                if (ANGLE && ok) acc += (cr == 0.0) ? ideal : fabs(v);
             }
         }
     }
 }
 
-template <int K, bool ANGLE>
-__global__ __launch_bounds__(kBlock) void cross_sweep_kernel(
-    const EdgeRec *__restrict__ rec, int64_t nR, int64_t nC, int64_t n_units, double ideal,
-    CrossPartial *__restrict__ part) {
+template <int K, int WAVES, bool ANGLE, bool BATCH>
+__global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
+    const EdgeRec *__restrict__ rec, SweepArgs a, double ideal, CrossPartial *__restrict__ part) {
     __shared__ EdgeRec col[kChunk];
+    __shared__ int2 rid[kBlock * K];
     __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
     __shared__ double red_d[kBlock / 64];
 
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t u_begin = n_units * b / G, u_end = n_units * (b + 1) / G;
+    const int64_t u_begin = block_first_unit(a.n_units, G, b);
+    const int64_t u_end = block_first_unit(a.n_units, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
 
-    // row tile of the first unit: the largest I with units_before(I) <= u_begin
-    int64_t lo = 0, hi = nR - 1;
+    int64_t L = 0;
+    if (BATCH) {
+        int64_t lo = 0, hi = a.n_layouts - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.table[mid].unit_off <= u_begin) lo = mid;
+            else hi = mid - 1;
+        }
+        L = lo;
+    }
+    SweepLayout lay = BATCH ? a.table[L] : a.single;
+    // row tile of the first unit: the largest I with units_before(I) <= local unit
+    const int64_t lu = u_begin - lay.unit_off;
+    int64_t lo = 0, hi = lay.n_row_tiles - 1;
     while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (units_before(mid, nC, K) <= u_begin) lo = mid;
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (units_before(mid, lay.n_chunks, K) <= lu) lo = mid;
         else hi = mid - 1;
     }
     int64_t I = lo;
-    int64_t c = I * K + (u_begin - units_before(I, nC, K));
+    int64_t c = I * K + (lu - units_before(I, lay.n_chunks, K));
 
     double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
-    int rS[K], rT[K];
-    int64_t cur_I = -1;
+    bool rows_loaded = false;
     unsigned long long tot_p = 0, tot_t = 0;
     double acc = 0.0;
+    int64_t seg_units = 0;
+
+    auto flush = [&](int64_t slot) {
+        if (ANGLE) {
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        }
+        const int wave = tid >> 6, lane = tid & 63;
+        __syncthreads();
+        if (lane == 0) {
+            red_p[wave] = tot_p;
+            red_t[wave] = tot_t;
+            red_d[wave] = acc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            CrossPartial P;
+            P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                P.proper += red_p[w];
+                P.touch += red_t[w];
+                P.dev += red_d[w];
+            }
+            part[slot] = P;
+        }
+        tot_p = 0; tot_t = 0; acc = 0.0;
+    };
 
     for (int64_t u = u_begin; u < u_end; ++u) {
-        if (I != cur_I) {
+        __syncthreads();                       // previous chunk and row ids consumed
+        if (!rows_loaded) {
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = rec[I * R + (int64_t)r * kBlock + tid];
+                const EdgeRec e = rec[lay.rec_off + I * R + (int64_t)r * kBlock + tid];
                 rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
-                rC[r] = e.c; rTH[r] = e.th; rS[r] = e.s; rT[r] = e.t;
+                rC[r] = e.c; rTH[r] = e.th;
+                rid[r * kBlock + tid] = make_int2(e.s, e.t);
             }
-            cur_I = I;
+            rows_loaded = true;
         }
-        __syncthreads();                       // previous chunk fully consumed
-        col[tid] = rec[c * kChunk + tid];
+        col[tid] = rec[lay.rec_off + c * kChunk + tid];
         __syncthreads();
         uint32_t n_p = 0, n_t = 0;
         const int64_t row0 = I * R + tid, col0 = c * kChunk;
         if (c < (I + 1) * K)
-            sweep_chunk<K, ANGLE, true>(col, rX, rY, rDX, rDY, rC, rTH, rS, rT, row0, col0,
+            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, row0, col0,
                                         ideal, angc, n_p, n_t, acc);
         else
-            sweep_chunk<K, ANGLE, false>(col, rX, rY, rDX, rDY, rC, rTH, rS, rT, row0, col0,
+            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, row0, col0,
                                          ideal, angc, n_p, n_t, acc);
         tot_p += n_p;
         tot_t += n_t;
-        if (++c == nC) {
+        ++seg_units;
+        if (++c == lay.n_chunks) {
             ++I;
             c = I * K;
+            rows_loaded = false;
+            if (BATCH && I == lay.n_row_tiles) {
+                flush(b + L);
+                seg_units = 0;
+                ++L;
+                if (L < a.n_layouts) lay = a.table[L];
+                I = 0;
+                c = 0;
+            }
         }
     }
-
-    // block reduction (fixed order: deterministic)
-    if (ANGLE) {
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    }
-    const int wave = tid >> 6, lane = tid & 63;
-    if (lane == 0) {
-        red_p[wave] = tot_p;
-        red_t[wave] = tot_t;
-        red_d[wave] = acc;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        CrossPartial P;
-        P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            P.proper += red_p[w];
-            P.touch += red_t[w];
-            P.dev += red_d[w];
-        }
-        part[b] = P;
-    }
+    if (seg_units > 0) flush(BATCH ? b + L : b);
 }
 
+// Sum of the partial slots of one layout, in slot order.
 __global__ __launch_bounds__(256) void cross_finalize_kernel(
     const CrossPartial *__restrict__ part, int n_part, double ideal,
     unsigned long long *out_count, unsigned long long *out_proper, double *out_metric,
@@ -215,44 +262,73 @@ __global__ __launch_bounds__(256) void cross_finalize_kernel(
     }
 }
 
-int g_cross_grid[2] = {0, 0};
+constexpr SweepVariant kCross[kCrossVariants] = {{1, 7}, {2, 5}, {4, 4}, {4, 3}};
+
+template <int V>
+struct CrossV {
+    static constexpr int K = kCross[V].rows, W = kCross[V].waves;
+};
+
+template <int V, bool ANGLE, bool BATCH>
+void launch_v(const EdgeRec *rec, const SweepArgs &a, int grid, double ideal, CrossPartial *part,
+              hipStream_t st) {
+    hipLaunchKernelGGL((cross_sweep_kernel<CrossV<V>::K, CrossV<V>::W, ANGLE, BATCH>),
+                       dim3(grid), dim3(kBlock), 0, st, rec, a, ideal, part);
+}
+
+template <int V>
+const void *kernel_ptr(bool angle) {
+    return angle ? (const void *)cross_sweep_kernel<CrossV<V>::K, CrossV<V>::W, true, false>
+                 : (const void *)cross_sweep_kernel<CrossV<V>::K, CrossV<V>::W, false, false>;
+}
+
+int g_cross_grid[kCrossVariants][2];
 
 }  // namespace
 
-SweepPlan plan_cross(int64_t n_edges, bool angle) {
-    SweepPlan p{};
-    constexpr int K = kCrossRows;
-    const int64_t R = (int64_t)kBlock * K;
-    const int64_t E = n_edges > 0 ? n_edges : 1;
-    p.n_row_tiles = (E + R - 1) / R;
-    p.n_chunks = (E + kChunk - 1) / kChunk;
-    p.n_units = p.n_row_tiles * p.n_chunks - (int64_t)K * p.n_row_tiles * (p.n_row_tiles - 1) / 2;
-    int &g = g_cross_grid[angle ? 1 : 0];
+SweepVariant cross_variant(int v) { return kCross[v]; }
+
+int cross_grid(int v, bool angle) {
+    int &g = g_cross_grid[v][angle ? 1 : 0];
     if (g == 0) {
+        const void *k = nullptr;
+        switch (v) {
+            case 0: k = kernel_ptr<0>(angle); break;
+            case 1: k = kernel_ptr<1>(angle); break;
+            case 2: k = kernel_ptr<2>(angle); break;
+            default: k = kernel_ptr<3>(angle); break;
+        }
         int per_cu = 0;
-        if (angle)
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, cross_sweep_kernel<K, true>, kBlock, 0);
-        else
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, cross_sweep_kernel<K, false>, kBlock, 0);
-        if (per_cu < 1) per_cu = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
         g = per_cu * device_cu_count();
         if (g > kMaxPartials) g = kMaxPartials;
     }
-    p.grid = (int)(p.n_units < g ? p.n_units : g);
-    return p;
+    return g;
 }
 
-hipError_t launch_cross_sweep(const EdgeRec *rec, const SweepPlan &p, bool angle, double ideal,
-                              CrossPartial *part, hipStream_t st) {
-    constexpr int K = kCrossRows;
-    if (angle)
-        hipLaunchKernelGGL((cross_sweep_kernel<K, true>), dim3(p.grid), dim3(kBlock), 0, st, rec,
-                           p.n_row_tiles, p.n_chunks, p.n_units, ideal, part);
-    else
-        hipLaunchKernelGGL((cross_sweep_kernel<K, false>), dim3(p.grid), dim3(kBlock), 0, st, rec,
-                           p.n_row_tiles, p.n_chunks, p.n_units, ideal, part);
+hipError_t launch_cross_sweep(int v, bool angle, const EdgeRec *rec, const SweepArgs &a,
+                              int grid, double ideal, CrossPartial *part, hipStream_t st) {
+    const bool batch = a.table != nullptr;
+#define RB_CASE(V)                                                                  \
+    case V:                                                                         \
+        if (angle) {                                                                \
+            if (batch) launch_v<V, true, true>(rec, a, grid, ideal, part, st);      \
+            else launch_v<V, true, false>(rec, a, grid, ideal, part, st);           \
+        } else {                                                                    \
+            if (batch) launch_v<V, false, true>(rec, a, grid, ideal, part, st);     \
+            else launch_v<V, false, false>(rec, a, grid, ideal, part, st);          \
+        }                                                                           \
+        break;
+    switch (v) {
+        RB_CASE(0)
+        RB_CASE(1)
+        RB_CASE(2)
+        RB_CASE(3)
+        default: return hipErrorInvalidValue;
+    }
+#undef RB_CASE
     return hipGetLastError();
 }
 

@@ -3,10 +3,11 @@
 //
 // Same decomposition as the edge sweep: a row tile of R = 256*K nodes held in
 // registers against chunks of 256 nodes staged in LDS, over the upper
-// triangle, by a persistent grid taking equal contiguous unit ranges.
-// The exact integer test |p_u - p_v|^2 <= T (T = largest integer < d^2) is
-// evaluated as  g = x_u x_v + (y_u y_v + q_v) >= h_u  (two fused multiply-adds
-// and one compare per pair; see NodeRec).
+// triangle of each layout, by a persistent grid taking equal contiguous
+// ranges of the unit list of all layouts.  The exact integer test
+// |p_u - p_v|^2 <= T (T = largest integer < d^2) is evaluated as
+// g = x_u x_v + (y_u y_v + q_v) >= h_u: two fused multiply-adds and one
+// compare per pair (see NodeRec).
 #include "rb_internal.h"
 
 namespace rb {
@@ -30,66 +31,95 @@ __device__ __forceinline__ uint32_t occl_chunk(const NodeRec *__restrict__ col,
             const double g = fma(rX[r], cX, fma(rY[r], cY, cQ));
             bool hit = g >= rH[r];
             if (DIAG) hit = hit & (col0 + j > row0 + (int64_t)r * kBlock);
-            n += (uint32_t)__popcll(__ballot(hit));
+            n += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
         }
     }
     return n;
 }
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void occl_sweep_kernel(const NodeRec *__restrict__ rec,
-                                                            int64_t nR, int64_t nC,
-                                                            int64_t n_units,
-                                                            OcclPartial *__restrict__ part) {
+template <int K, int WAVES, bool BATCH>
+__global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
+    const NodeRec *__restrict__ rec, SweepArgs a, OcclPartial *__restrict__ part) {
     __shared__ NodeRec col[kChunk];
     __shared__ unsigned long long red[kBlock / 64];
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t u_begin = n_units * b / G, u_end = n_units * (b + 1) / G;
+    const int64_t u_begin = block_first_unit(a.n_units, G, b);
+    const int64_t u_end = block_first_unit(a.n_units, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
 
-    int64_t lo = 0, hi = nR - 1;
+    int64_t L = 0;
+    if (BATCH) {
+        int64_t lo = 0, hi = a.n_layouts - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.table[mid].unit_off <= u_begin) lo = mid;
+            else hi = mid - 1;
+        }
+        L = lo;
+    }
+    SweepLayout lay = BATCH ? a.table[L] : a.single;
+    const int64_t lu = u_begin - lay.unit_off;
+    int64_t lo = 0, hi = lay.n_row_tiles - 1;
     while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (units_before(mid, nC, K) <= u_begin) lo = mid;
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (units_before(mid, lay.n_chunks, K) <= lu) lo = mid;
         else hi = mid - 1;
     }
     int64_t I = lo;
-    int64_t c = I * K + (u_begin - units_before(I, nC, K));
+    int64_t c = I * K + (lu - units_before(I, lay.n_chunks, K));
 
     double rX[K], rY[K], rH[K];
-    int64_t cur_I = -1;
+    bool rows_loaded = false;
     unsigned long long tot = 0;
+    int64_t seg_units = 0;
+
+    auto flush = [&](int64_t slot) {
+        const int wave = tid >> 6, lane = tid & 63;
+        __syncthreads();
+        if (lane == 0) red[wave] = tot;
+        __syncthreads();
+        if (tid == 0) {
+            OcclPartial P;
+            P.count = 0;
+            P.pad = 0;
+            for (int w = 0; w < kBlock / 64; ++w) P.count += red[w];
+            part[slot] = P;
+        }
+        tot = 0;
+    };
+
     for (int64_t u = u_begin; u < u_end; ++u) {
-        if (I != cur_I) {
+        if (!rows_loaded) {
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const NodeRec v = rec[I * R + (int64_t)r * kBlock + tid];
+                const NodeRec v = rec[lay.rec_off + I * R + (int64_t)r * kBlock + tid];
                 rX[r] = v.x; rY[r] = v.y; rH[r] = v.h;
             }
-            cur_I = I;
+            rows_loaded = true;
         }
         __syncthreads();
-        col[tid] = rec[c * kChunk + tid];
+        col[tid] = rec[lay.rec_off + c * kChunk + tid];
         __syncthreads();
         const int64_t row0 = I * R + tid, col0 = c * kChunk;
         if (c < (I + 1) * K) tot += occl_chunk<K, true>(col, rX, rY, rH, row0, col0);
         else tot += occl_chunk<K, false>(col, rX, rY, rH, row0, col0);
-        if (++c == nC) {
+        ++seg_units;
+        if (++c == lay.n_chunks) {
             ++I;
             c = I * K;
+            rows_loaded = false;
+            if (BATCH && I == lay.n_row_tiles) {
+                flush(b + L);
+                seg_units = 0;
+                ++L;
+                if (L < a.n_layouts) lay = a.table[L];
+                I = 0;
+                c = 0;
+            }
         }
     }
-    const int wave = tid >> 6, lane = tid & 63;
-    if (lane == 0) red[wave] = tot;
-    __syncthreads();
-    if (tid == 0) {
-        OcclPartial P;
-        P.count = 0;
-        P.pad = 0;
-        for (int w = 0; w < kBlock / 64; ++w) P.count += red[w];
-        part[b] = P;
-    }
+    if (seg_units > 0) flush(BATCH ? b + L : b);
 }
 
 __global__ __launch_bounds__(256) void occl_finalize_kernel(const OcclPartial *__restrict__ part,
@@ -108,34 +138,51 @@ __global__ __launch_bounds__(256) void occl_finalize_kernel(const OcclPartial *_
     if (tid == 0) *out_count = s[0];
 }
 
-int g_occl_grid = 0;
+constexpr SweepVariant kOccl[kOcclVariants] = {{8, 4}, {16, 2}, {4, 6}};
+
+template <int V>
+struct OcclV {
+    static constexpr int K = kOccl[V].rows, W = kOccl[V].waves;
+};
+
+template <int V, bool BATCH>
+void launch_v(const NodeRec *rec, const SweepArgs &a, int grid, OcclPartial *part,
+              hipStream_t st) {
+    hipLaunchKernelGGL((occl_sweep_kernel<OcclV<V>::K, OcclV<V>::W, BATCH>), dim3(grid),
+                       dim3(kBlock), 0, st, rec, a, part);
+}
+
+int g_occl_grid[kOcclVariants];
 
 }  // namespace
 
-SweepPlan plan_occl(int64_t n_nodes) {
-    SweepPlan p{};
-    constexpr int K = kOcclRows;
-    const int64_t R = (int64_t)kBlock * K;
-    const int64_t V = n_nodes > 0 ? n_nodes : 1;
-    p.n_row_tiles = (V + R - 1) / R;
-    p.n_chunks = (V + kChunk - 1) / kChunk;
-    p.n_units = p.n_row_tiles * p.n_chunks - (int64_t)K * p.n_row_tiles * (p.n_row_tiles - 1) / 2;
-    if (g_occl_grid == 0) {
+SweepVariant occl_variant(int v) { return kOccl[v]; }
+
+int occl_grid(int v) {
+    int &g = g_occl_grid[v];
+    if (g == 0) {
+        const void *k = v == 0   ? (const void *)occl_sweep_kernel<OcclV<0>::K, OcclV<0>::W, false>
+                        : v == 1 ? (const void *)occl_sweep_kernel<OcclV<1>::K, OcclV<1>::W, false>
+                                 : (const void *)occl_sweep_kernel<OcclV<2>::K, OcclV<2>::W, false>;
         int per_cu = 0;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, occl_sweep_kernel<K>, kBlock,
-                                                           0);
-        if (per_cu < 1) per_cu = 1;
-        g_occl_grid = per_cu * device_cu_count();
-        if (g_occl_grid > kMaxPartials) g_occl_grid = kMaxPartials;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        g = per_cu * device_cu_count();
+        if (g > kMaxPartials) g = kMaxPartials;
     }
-    p.grid = (int)(p.n_units < g_occl_grid ? p.n_units : g_occl_grid);
-    return p;
+    return g;
 }
 
-hipError_t launch_occl_sweep(const NodeRec *rec, const SweepPlan &p, OcclPartial *part,
-                             hipStream_t st) {
-    hipLaunchKernelGGL((occl_sweep_kernel<kOcclRows>), dim3(p.grid), dim3(kBlock), 0, st, rec,
-                       p.n_row_tiles, p.n_chunks, p.n_units, part);
+hipError_t launch_occl_sweep(int v, const NodeRec *rec, const SweepArgs &a, int grid,
+                             OcclPartial *part, hipStream_t st) {
+    const bool batch = a.table != nullptr;
+    switch (v) {
+        case 0: batch ? launch_v<0, true>(rec, a, grid, part, st) : launch_v<0, false>(rec, a, grid, part, st); break;
+        case 1: batch ? launch_v<1, true>(rec, a, grid, part, st) : launch_v<1, false>(rec, a, grid, part, st); break;
+        case 2: batch ? launch_v<2, true>(rec, a, grid, part, st) : launch_v<2, false>(rec, a, grid, part, st); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,115 @@
+// Host-side planning of the all-pairs sweeps and the autotuning table that
+// picks a sweep variant (rows per thread, waves per SIMD) per size class.
+//
+// Size class = floor(log2(n)) of the number of records of a single layout,
+// or of the mean number of records per layout of a batch.  The table starts
+// from built-in defaults, is updated by rb_autotune / rb_batch_autotune, and
+// can be saved to and loaded from a text file ("kind batch class variant"
+// per line).  RB_TUNE_CACHE names a file loaded on first use.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "rb_internal.h"
+
+namespace rb {
+
+SweepLayout sweep_layout(int64_t n_items, int rows, int64_t unit_off, int64_t rec_off) {
+    const int64_t R = (int64_t)kBlock * rows;
+    const int64_t n = n_items > 0 ? n_items : 1;
+    SweepLayout l;
+    l.unit_off = unit_off;
+    l.rec_off = rec_off;
+    l.n_row_tiles = (n + R - 1) / R;
+    l.n_chunks = (n + kChunk - 1) / kChunk;
+    return l;
+}
+
+int64_t sweep_units(int64_t n_items, int rows) {
+    const SweepLayout l = sweep_layout(n_items, rows, 0, 0);
+    return l.n_row_tiles * l.n_chunks - (int64_t)rows * l.n_row_tiles * (l.n_row_tiles - 1) / 2;
+}
+
+namespace {
+
+constexpr int kClasses = 40;
+constexpr int kKinds = 3;            // 0 crossing, 1 crossing + angle, 2 occlusion
+constexpr int kDefault[kKinds] = {1, 1, 0};
+
+struct Table {
+    std::mutex mu;
+    bool init = false;
+    int v[kKinds][2][kClasses];
+} g_tab;
+
+int size_class(int64_t n) {
+    int c = 0;
+    while (n > 1 && c < kClasses - 1) {
+        n >>= 1;
+        ++c;
+    }
+    return c;
+}
+
+int n_variants(int kind) { return kind == 2 ? kOcclVariants : kCrossVariants; }
+
+void load_locked(const char *path) {
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    int kind, batch, cls, var;
+    while (fscanf(f, "%d %d %d %d", &kind, &batch, &cls, &var) == 4) {
+        if (kind >= 0 && kind < kKinds && (batch == 0 || batch == 1) && cls >= 0 &&
+            cls < kClasses && var >= 0 && var < n_variants(kind))
+            g_tab.v[kind][batch][cls] = var;
+    }
+    fclose(f);
+}
+
+void init_locked() {
+    if (g_tab.init) return;
+    for (int k = 0; k < kKinds; ++k)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < kClasses; ++c) g_tab.v[k][b][c] = kDefault[k];
+    g_tab.init = true;
+    const char *path = getenv("RB_TUNE_CACHE");
+    if (path && *path) load_locked(path);
+}
+
+}  // namespace
+
+int tuned_variant(int kind, bool batch, int64_t n) {
+    std::lock_guard<std::mutex> g(g_tab.mu);
+    init_locked();
+    return g_tab.v[kind][batch ? 1 : 0][size_class(n)];
+}
+
+void set_tuned_variant(int kind, bool batch, int64_t n, int variant) {
+    std::lock_guard<std::mutex> g(g_tab.mu);
+    init_locked();
+    g_tab.v[kind][batch ? 1 : 0][size_class(n)] = variant;
+}
+
+bool save_tuning(const char *path) {
+    std::lock_guard<std::mutex> g(g_tab.mu);
+    init_locked();
+    FILE *f = fopen(path, "w");
+    if (!f) return false;
+    for (int k = 0; k < kKinds; ++k)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < kClasses; ++c)
+                if (g_tab.v[k][b][c] != kDefault[k]) fprintf(f, "%d %d %d %d\n", k, b, c, g_tab.v[k][b][c]);
+    return fclose(f) == 0;
+}
+
+bool load_tuning(const char *path) {
+    std::lock_guard<std::mutex> g(g_tab.mu);
+    init_locked();
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    fclose(f);
+    load_locked(path);
+    return true;
+}
+
+}  // namespace rb

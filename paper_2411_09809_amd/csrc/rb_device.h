@@ -1,0 +1,67 @@
+// Device helpers shared by the per-layout and batched kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rb {
+namespace dev {
+
+constexpr double kTwoPi = 6.283185307179586476925;
+
+// ids out of range violate the preconditions; such edges are skipped so that
+// no kernel reads or writes outside its buffers
+__device__ __forceinline__ bool valid_ids(int32_t s, int32_t t, int64_t n_nodes) {
+    return s >= 0 && t >= 0 && s < n_nodes && t < n_nodes;
+}
+
+// Euclidean length of the edge s-t: dx^2 + dy^2 < 2^44 is exact in double
+__device__ __forceinline__ double edge_length(const float *x, const float *y, int64_t s,
+                                              int64_t t) {
+    const double dx = (double)x[t] - (double)x[s];
+    const double dy = (double)y[t] - (double)y[s];
+    return sqrt(fma(dx, dx, dy * dy));
+}
+
+// angle of the direction (dx, dy) with the x axis, in [0, 2 pi)
+__device__ __forceinline__ double direction_angle(double dx, double dy) {
+    const double a = atan2(dy, dx);
+    return a < 0.0 ? a + kTwoPi : a;
+}
+
+// d_v = (2 pi/deg - phi_min) / (2 pi/deg)
+__device__ __forceinline__ double dv_of(double phi_min, uint32_t deg) {
+    const double ideal = kTwoPi / (double)deg;
+    return (ideal - phi_min) / ideal;
+}
+
+// sum over the block (blockDim.x a power of two <= 1024); sh has blockDim.x slots
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// index of the layout owning item i, given offsets off[0..n] (off[0] = 0,
+// nondecreasing, off[n] > i): the largest L with off[L] <= i and
+// off[L + 1] > i
+__device__ __forceinline__ int64_t owner(const int64_t *off, int64_t n, int64_t i) {
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    while (lo + 1 < n && off[lo + 1] <= i) ++lo;     // skip empty layouts
+    return lo;
+}
+
+}  // namespace dev
+}  // namespace rb

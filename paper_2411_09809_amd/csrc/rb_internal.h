@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rb.h"
+
 namespace rb {
 
 // ------------------------------------------------------------------ records
@@ -32,7 +34,7 @@ struct __align__(16) NodeRec {
 };
 static_assert(sizeof(NodeRec) == 32, "node record is 32 bytes");
 
-// Partial results of one block of a sweep.
+// Partial results of one (block, layout) segment of a sweep.
 struct __align__(16) CrossPartial {
     unsigned long long proper, touch;   // proper crossings, other closed crossings
     double dev;                         // sum of |ideal - a| (radians)
@@ -46,15 +48,43 @@ struct __align__(16) OcclPartial {
 // ------------------------------------------------------------------ tiling
 constexpr int kBlock = 256;          // threads per sweep block (4 waves)
 constexpr int kChunk = 256;          // column records staged in LDS per unit
-constexpr int kCrossRows = 4;        // edge rows held per thread
-constexpr int kOcclRows = 16;        // node rows held per thread
-constexpr int kEdgePad = kBlock * 8; // edge records padded to a multiple of this
-constexpr int kNodePad = kBlock * 16;
-constexpr int kMaxPartials = 8192;   // partial slots per sweep
+constexpr int kMaxRows = 16;         // largest rows-per-thread of any variant
+constexpr int kRecPad = kBlock * kMaxRows;   // record segments padded to this
+constexpr int kMaxPartials = 16384;  // partial slots per single-layout sweep
 constexpr int kSmallDeg = 16;        // min-angle: thread-per-node up to this degree
 constexpr int kLdsDeg = 2048;        // min-angle: block sort in LDS up to this degree
 
-// Layout of the caller's workspace (byte offsets, 256-aligned).
+// One layout inside a sweep's unit list.  Row tile I (R = 256*K records)
+// meets column chunks c = I*K .. n_chunks-1 (256 records each); the layout's
+// units are numbered from unit_off in that order.
+struct SweepLayout {
+    int64_t unit_off;       // first global unit of this layout
+    int64_t rec_off;        // first record of this layout (multiple of kRecPad)
+    int64_t n_row_tiles;
+    int64_t n_chunks;
+};
+
+// Kernel arguments of a sweep.  A single layout travels by value; a batch
+// reads its table (n_layouts + 1 entries, the last holding only unit_off =
+// total units) from device memory.
+struct SweepArgs {
+    const SweepLayout *table;
+    SweepLayout single;
+    int64_t n_layouts;
+    int64_t n_units;
+};
+
+// Sweep kernel variants: rows per thread and minimum waves per SIMD.
+struct SweepVariant {
+    int rows;
+    int waves;
+};
+constexpr int kCrossVariants = 4;
+constexpr int kOcclVariants = 3;
+SweepVariant cross_variant(int v);
+SweepVariant occl_variant(int v);
+
+// Layout of the caller's workspace for one layout (byte offsets, 256-aligned).
 struct WsLayout {
     size_t edge_rec, node_rec, partial, scalars;
     size_t deg, cursor, offs, angles, dv, big_list, hash;
@@ -73,6 +103,21 @@ struct __align__(16) Scalars {
     int32_t pad[7];
 };
 
+// ------------------------------------------------------------------ plans
+struct SweepPlan {
+    int variant;
+    int rows;
+    int grid;
+    int64_t n_units;
+    SweepLayout single;
+};
+// Unit list of one layout of n_items records for a variant.
+SweepLayout sweep_layout(int64_t n_items, int rows, int64_t unit_off, int64_t rec_off);
+int64_t sweep_units(int64_t n_items, int rows);
+// Persistent grid size (blocks) of a variant on the current device.
+int cross_grid(int variant, bool angle);
+int occl_grid(int variant);
+
 // ------------------------------------------------------------------ launches
 // Every launcher enqueues on `st` and returns the launch status.
 hipError_t launch_edge_prep(const float *x, const float *y, const int32_t *src,
@@ -81,36 +126,64 @@ hipError_t launch_edge_prep(const float *x, const float *y, const int32_t *src,
 hipError_t launch_node_prep(const float *x, const float *y, int64_t n_nodes, int64_t n_pad,
                             double T, NodeRec *rec, hipStream_t st);
 
-struct SweepPlan {
-    int64_t n_row_tiles, n_chunks, n_units;
-    int grid;
-};
-SweepPlan plan_cross(int64_t n_edges, bool angle);
-SweepPlan plan_occl(int64_t n_nodes);
-
-hipError_t launch_cross_sweep(const EdgeRec *rec, const SweepPlan &p, bool angle,
-                              double ideal, CrossPartial *part, hipStream_t st);
+hipError_t launch_cross_sweep(int variant, bool angle, const EdgeRec *rec, const SweepArgs &a,
+                              int grid, double ideal, CrossPartial *part, hipStream_t st);
 hipError_t launch_cross_finalize(const CrossPartial *part, int n_part, double ideal,
                                  unsigned long long *out_count, unsigned long long *out_proper,
                                  double *out_metric, double *out_dev_sum, hipStream_t st);
-hipError_t launch_occl_sweep(const NodeRec *rec, const SweepPlan &p, OcclPartial *part,
-                             hipStream_t st);
+hipError_t launch_occl_sweep(int variant, const NodeRec *rec, const SweepArgs &a, int grid,
+                             OcclPartial *part, hipStream_t st);
 hipError_t launch_occl_finalize(const OcclPartial *part, int n_part,
                                 unsigned long long *out_count, hipStream_t st);
 
 hipError_t launch_elv(const float *x, const float *y, const int32_t *src, const int32_t *dst,
-                      int64_t n_nodes, int64_t n_edges, double *partial, Scalars *sc, double *out_metric,
-                      double *out_mean, hipStream_t st);
+                      int64_t n_nodes, int64_t n_edges, double *partial, Scalars *sc,
+                      double *out_metric, double *out_mean, hipStream_t st);
 
 hipError_t launch_min_angle(const float *x, const float *y, int64_t n_nodes,
                             const int32_t *src, const int32_t *dst, int64_t n_edges,
                             const WsLayout &L, char *ws, double *out_metric,
                             double *out_sum_dv, unsigned long long *out_n_used, hipStream_t st);
 
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
+hipError_t launch_zero_scalars(Scalars *sc, hipStream_t st);
+// exclusive scan of deg[0..n) into offs[0..n] (tile: ceil(n/2048) scratch words)
+hipError_t launch_scan(const uint32_t *deg, int64_t n, unsigned long long *tile, uint32_t *offs,
+                       hipStream_t st);
+// d_v of every node from its CSR segment of direction angles (sorts in place)
+hipError_t launch_min_angle_nodes(const uint32_t *deg, const uint32_t *offs, double *ang,
+                                  int64_t n_nodes, double *dv, int32_t *big, Scalars *sc,
+                                  hipStream_t st);
+
 hipError_t launch_validate(const float *x, const float *y, int64_t n_nodes,
                            const int32_t *src, const int32_t *dst, int64_t n_edges,
                            const WsLayout &L, char *ws, hipStream_t st);
 
 int device_cu_count();
+
+// Error text of the calling host thread (api.hip); set_error and hip_error
+// return the status they were given (RB_EHIP for hip_error).
+int set_error(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_error(hipError_t e, const char *what);
+void clear_error();
+
+// Largest integer T with T < d^2 (d finite, >= 0): the squared-distance
+// threshold of the occlusion test.  fma(d, d, -n) carries the exact sign of
+// d^2 - n.  Squared distances are below 2^43, so T is capped at 2^44.
+double occlusion_threshold(double d);
+
+// Autotuning table (plan.hip).  kind: 0 crossing, 1 crossing + angle,
+// 2 occlusion; n: records per layout (mean per layout for a batch).
+int tuned_variant(int kind, bool batch, int64_t n);
+void set_tuned_variant(int kind, bool batch, int64_t n, int variant);
+bool save_tuning(const char *path);
+bool load_tuning(const char *path);
+
+// ------------------------------------------------------------------ helpers
+// Block b of a grid of G blocks owns units [U*b/G, U*(b+1)/G).
+__host__ __device__ inline int64_t block_first_unit(int64_t U, int64_t G, int64_t b) {
+    return U * b / G;
+}
 
 }  // namespace rb

@@ -3,39 +3,19 @@
 //   precondition checks.
 // Every floating-point reduction runs over a fixed grid and combines block
 // partials in a fixed order, so results are bit-reproducible.
+#include "rb_device.h"
 #include "rb_internal.h"
 
 namespace rb {
 namespace {
 
-constexpr double kTwoPi = 6.283185307179586476925;
+using dev::block_sum;
+using dev::direction_angle;
+using dev::dv_of;
+using dev::edge_length;
+using dev::kTwoPi;
+using dev::valid_ids;
 constexpr int kRedGrid = 1024;       // blocks of the fixed-grid reductions
-
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (tid < s) sh[tid] += sh[tid + s];
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-// ids out of range violate the preconditions; such edges are skipped so that
-// no kernel reads or writes outside its buffers
-__device__ __forceinline__ bool valid_ids(int32_t s, int32_t t, int64_t n_nodes) {
-    return s >= 0 && t >= 0 && s < n_nodes && t < n_nodes;
-}
-
-__device__ __forceinline__ double edge_length(const float *x, const float *y, int32_t s,
-                                              int32_t t) {
-    const double dx = (double)x[t] - (double)x[s];
-    const double dy = (double)y[t] - (double)y[s];
-    return sqrt(fma(dx, dx, dy * dy));      // dx^2 + dy^2 < 2^44 is exact
-}
 
 // ---------------------------------------------------- edge length variation
 
@@ -191,11 +171,6 @@ __global__ __launch_bounds__(256) void scan_tile_apply_kernel(const uint32_t *__
     }
 }
 
-__device__ __forceinline__ double direction_angle(double dx, double dy) {
-    double a = atan2(dy, dx);
-    return a < 0.0 ? a + kTwoPi : a;               // [0, 2 pi)
-}
-
 __global__ __launch_bounds__(256) void fill_angles_kernel(const float *__restrict__ x,
                                                           const float *__restrict__ y,
                                                           const int32_t *__restrict__ src,
@@ -218,12 +193,6 @@ __global__ __launch_bounds__(256) void fill_angles_kernel(const float *__restric
         ang[ps] = direction_angle(dx, dy);       // at s, towards t
         ang[pt] = direction_angle(rdx, rdy);     // at t, towards s
     }
-}
-
-// d_v = (2 pi/deg - phi_min) / (2 pi/deg)
-__device__ __forceinline__ double dv_of(double phi_min, uint32_t deg) {
-    const double ideal = kTwoPi / (double)deg;
-    return (ideal - phi_min) / ideal;
 }
 
 // Nodes of degree <= kSmallDeg: one thread each.  The smallest gap between
@@ -480,6 +449,46 @@ hipError_t launch_elv(const float *x, const float *y, const int32_t *src, const 
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st) {
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_scalars(Scalars *sc, hipStream_t st) {
+    hipLaunchKernelGGL(zero_scalars_kernel, dim3(1), dim3(64), 0, st, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t *deg, int64_t n, unsigned long long *tile, uint32_t *offs,
+                       hipStream_t st) {
+    const int64_t n_tiles = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, deg, n,
+                       tile);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(scan_tile_offsets_kernel, dim3(1), dim3(256), 0, st, tile, n_tiles);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(scan_tile_apply_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, deg, n,
+                       tile, offs);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_angle_nodes(const uint32_t *deg, const uint32_t *offs, double *ang,
+                                  int64_t n_nodes, double *dv, int32_t *big, Scalars *sc,
+                                  hipStream_t st) {
+    if (n_nodes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(min_angle_small_kernel, dim3(grid_for(n_nodes)), dim3(256), 0, st, deg,
+                       offs, ang, n_nodes, dv, big, sc);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(min_angle_big_kernel, dim3(1024), dim3(256), 0, st, deg, offs, ang, big, sc,
+                       dv);
+    return hipGetLastError();
+}
+
 hipError_t launch_min_angle(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                             const int32_t *dst, int64_t n_edges, const WsLayout &L, char *ws,
                             double *out_metric, double *out_sum_dv,
@@ -496,39 +505,21 @@ hipError_t launch_min_angle(const float *x, const float *y, int64_t n_nodes, con
     unsigned long long *tile = (unsigned long long *)dv;   // dv is written only later
 
     const int64_t V = n_nodes > 0 ? n_nodes : 1;
-    hipLaunchKernelGGL(zero_scalars_kernel, dim3(1), dim3(64), 0, st, sc);
-    RB_LAUNCHED();
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(V)), dim3(256), 0, st, deg, V, 0u);
-    RB_LAUNCHED();
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(V)), dim3(256), 0, st, cursor, V, 0u);
-    RB_LAUNCHED();
+    RB_TRY(launch_zero_scalars(sc, st));
+    RB_TRY(launch_fill_u32(deg, V, 0u, st));
+    RB_TRY(launch_fill_u32(cursor, V, 0u, st));
     if (n_edges > 0) {
         hipLaunchKernelGGL(degree_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, src, dst,
                            n_nodes, n_edges, deg);
         RB_LAUNCHED();
     }
-    const int64_t n_tiles = (V + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, deg, V,
-                       tile);
-    RB_LAUNCHED();
-    hipLaunchKernelGGL(scan_tile_offsets_kernel, dim3(1), dim3(256), 0, st, tile, n_tiles);
-    RB_LAUNCHED();
-    hipLaunchKernelGGL(scan_tile_apply_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, deg, V,
-                       tile, offs);
-    RB_LAUNCHED();
+    RB_TRY(launch_scan(deg, V, tile, offs, st));
     if (n_edges > 0) {
         hipLaunchKernelGGL(fill_angles_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, x, y,
                            src, dst, n_nodes, n_edges, offs, cursor, ang);
         RB_LAUNCHED();
     }
-    if (n_nodes > 0) {
-        hipLaunchKernelGGL(min_angle_small_kernel, dim3(grid_for(n_nodes)), dim3(256), 0, st, deg,
-                           offs, ang, n_nodes, dv, big, sc);
-        RB_LAUNCHED();
-        hipLaunchKernelGGL(min_angle_big_kernel, dim3(1024), dim3(256), 0, st, deg, offs, ang, big,
-                           sc, dv);
-        RB_LAUNCHED();
-    }
+    RB_TRY(launch_min_angle_nodes(deg, offs, ang, n_nodes, dv, big, sc, st));
     const int g = grid_for(n_nodes, kRedGrid);
     hipLaunchKernelGGL(dv_sum_kernel, dim3(g), dim3(256), 0, st, deg, dv, n_nodes, partial, used);
     RB_LAUNCHED();

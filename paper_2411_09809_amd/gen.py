@@ -82,6 +82,8 @@ def distinct_random_edges(rng: np.random.Generator, n_nodes: int, n_edges: int,
     """
     if n_edges > n_nodes * (n_nodes - 1) // 2:
         raise ValueError("more edges than node pairs")
+    if n_edges == 0:
+        return np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64)
     p = None
     if weights is not None:
         p = np.asarray(weights, dtype=np.float64)

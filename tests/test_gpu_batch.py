@@ -1,0 +1,207 @@
+"""Batched evaluation (rb_batch_*), hipGraph replay and sweep variants.
+
+* every layout of a batch matches the oracle (sampled) and the
+  single-layout calls (all of them): counts bit for bit, floats to 1e-12;
+* graph replays match the eager evaluation, with eager work in between;
+* every sweep variant (tile shape) gives identical results.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_09809_amd import gen
+
+pytestmark = pytest.mark.gpu
+IDEAL = gen.IDEAL_ANGLE
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+def mixed_layouts(seed=0):
+    """Uneven sizes with edge cases: empty edge set, one node, crowded grids."""
+    rng = np.random.default_rng(seed)
+    out = [gen.uniform_layout(2, 1, extent=4, seed=1), gen.uniform_layout(1, 0, seed=2)]
+    out[-1].diameter = 3.0
+    for k in range(14):
+        V = int(rng.integers(3, 1500))
+        E = int(min(V * (V - 1) // 2, rng.integers(1, 4 * V)))
+        ext = int(rng.choice([8, 64, 4096, 1 << 16]))
+        out.append(gen.uniform_layout(V, E, extent=ext, diameter=float(rng.choice([2.5, 8, 40])),
+                                      seed=100 + k))
+    out.append(gen._finish(np.arange(5), np.zeros(5), np.zeros(0), np.zeros(0), diameter=1.5,
+                           name="no_edges"))
+    out.append(gen.complete_convex(12))
+    out.append(gen.grid(7, 9))
+    return out
+
+
+def single_results(torch, B):
+    from paper_2411_09809_amd import metrics
+    res = []
+    for i in range(B.n):
+        x, y, s, d, diam = B.layout_views(i)
+        occ = metrics.node_occlusion(x, y, diam)
+        eca, cnt, _ = metrics.crossing_angle(x, y, s, d)
+        ma = metrics.min_angle(x, y, s, d)[0]
+        ml = metrics.edge_length_variation(x, y, s, d)[0]
+        res.append((occ, cnt, eca, ma, ml))
+    return res
+
+
+def check_against_single(R, single):
+    for i, (occ, cnt, eca, ma, ml) in enumerate(single):
+        assert R["node_occlusion"][i] == occ, i
+        assert R["edge_crossing"][i] == cnt, i
+        assert R["crossing_angle"][i] == pytest.approx(eca, rel=1e-12, abs=1e-14), i
+        assert R["min_angle"][i] == pytest.approx(ma, rel=1e-12, abs=1e-14), i
+        assert R["edge_length_variation"][i] == pytest.approx(ml, rel=1e-12, abs=1e-14), i
+
+
+def check_against_oracle(R, layouts, idx):
+    for i in idx:
+        L = layouts[i]
+        want = oracle.all_metrics(L)
+        assert R["node_occlusion"][i] == want["node_occlusion"], i
+        assert R["edge_crossing"][i] == want["edge_crossing"], i
+        for k in ("crossing_angle", "min_angle", "edge_length_variation"):
+            assert abs(R[k][i] - want[k]) <= 1e-5 * abs(want[k]) + 1e-12, (i, k, R[k][i], want[k])
+
+
+def test_mixed_batch_matches_oracle_and_single(torch_mod):
+    from paper_2411_09809_amd.batch import Batch
+    layouts = mixed_layouts()
+    say(f"[batch] mixed {len(layouts)} layouts")
+    B = Batch(layouts)
+    B.evaluate()
+    R = B.results()
+    check_against_oracle(R, layouts, range(len(layouts)))
+    check_against_single(R, single_results(torch_mod, B))
+
+
+def test_graph_replay_matches_eager(torch_mod):
+    from paper_2411_09809_amd import metrics
+    from paper_2411_09809_amd.batch import Batch
+    layouts = mixed_layouts(seed=3)
+    say("[batch] graph replay")
+    B = Batch(layouts)
+    B.evaluate()
+    eager = B.results()
+    B.capture()
+    for rep in range(3):
+        for t in (B.out_occlusion, B.out_crossings, B.out_crossing_angle, B.out_min_angle,
+                  B.out_elv):
+            t.fill_(-7)
+        # eager work on the same stream and workspace tables between replays
+        x, y, s, d, diam = B.layout_views(5)
+        metrics.crossing_angle(x, y, s, d)
+        B.replay()
+        torch_mod.cuda.synchronize()
+        R = B.results()
+        for k in eager:
+            np.testing.assert_array_equal(R[k], eager[k], err_msg=f"replay {rep} {k}")
+    B.release_graph()
+
+
+def test_batch_of_512_uneven_layouts(torch_mod):
+    """The 512-layout workload (|V| log-uniform in [200, 20000], |E| =
+    U[1.5,4]|V|, coords in [0,2^16)^2): all layouts against single calls,
+    16 of them against the oracle."""
+    from paper_2411_09809_amd.batch import Batch
+    layouts = gen.batch_layouts(512, seed=0)
+    say(f"[batch] 512 layouts, {sum(L.n_edges for L in layouts)} edges")
+    B = Batch(layouts)
+    B.evaluate()
+    R = B.results()
+    sizes = np.array([L.n_edges for L in layouts])
+    small = [int(i) for i in np.argsort(sizes)[:12]]
+    rng = np.random.default_rng(1)
+    idx = small + [int(i) for i in rng.choice(np.where(sizes < 6000)[0], 4, replace=False)]
+    check_against_oracle(R, layouts, idx)
+    check_against_single(R, single_results(torch_mod, B))
+
+
+def test_batch_autotune_keeps_results(torch_mod):
+    from paper_2411_09809_amd.batch import Batch
+    layouts = mixed_layouts(seed=5)
+    B = Batch(layouts)
+    B.evaluate()
+    before = B.results()
+    ms = B.autotune(repeats=1)
+    assert ms > 0
+    B.evaluate()
+    after = B.results()
+    for k in before:
+        if k in ("node_occlusion", "edge_crossing"):
+            np.testing.assert_array_equal(after[k], before[k])
+        else:
+            np.testing.assert_allclose(after[k], before[k], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_every_sweep_variant_agrees(torch_mod, kind):
+    """All tile shapes give identical counts (and angle sums to rounding)."""
+    import ctypes as C
+    from paper_2411_09809_amd import _lib, metrics
+    L = gen.uniform_layout(3000, 7000, extent=300, diameter=6.0, seed=9)
+    D = metrics.DeviceLayout.from_host(L)
+    n_items = L.n_nodes if kind == 2 else L.n_edges
+    lib = _lib.lib()
+    rows, waves = C.c_int(), C.c_int()
+    _lib.check(lib.rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves)), "query")
+    default = None
+    for v in range(3 if kind == 2 else 4):
+        _lib.check(lib.rb_tune_set(kind, 0, n_items, v), "rb_tune_set")
+        say(f"[variant] kind {kind} variant {v}")
+        if kind == 0:
+            r = metrics.edge_crossing(D.x, D.y, D.src, D.dst)
+        elif kind == 1:
+            r = metrics.crossing_angle(D.x, D.y, D.src, D.dst)
+        else:
+            r = metrics.node_occlusion(D.x, D.y, L.diameter)
+        if default is None:
+            default = r
+        elif kind == 1:
+            assert r[1] == default[1] and r[0] == pytest.approx(default[0], rel=1e-12)
+        else:
+            assert r == default
+    want = oracle.all_metrics(L)
+    if kind == 0:
+        assert default == (want["edge_crossing"], want["proper_crossing"])
+    elif kind == 1:
+        assert default[1] == want["edge_crossing"]
+    else:
+        assert default == want["node_occlusion"]
+
+
+def test_autotune_single_layout(torch_mod):
+    import ctypes as C
+    from paper_2411_09809_amd import _lib, metrics
+    L = gen.uniform_layout(5000, 12000, extent=1 << 14, diameter=20.0, seed=4)
+    D = metrics.DeviceLayout.from_host(L)
+    before = metrics.evaluate(D)
+    ws = metrics.workspace(L.n_nodes, L.n_edges, D.x.device)
+    w, wb = metrics._ws_args(ws)
+    ms = C.c_double()
+    _lib.check(_lib.lib().rb_autotune(D.x.data_ptr(), D.y.data_ptr(), L.n_nodes, D.src.data_ptr(),
+                                      D.dst.data_ptr(), L.n_edges, L.diameter, IDEAL, 2,
+                                      C.byref(ms), w, wb, metrics._stream(D.x.device)),
+               "rb_autotune")
+    assert ms.value > 0
+    after = metrics.evaluate(D)
+    for k in ("node_occlusion", "edge_crossing", "min_angle_n_used"):
+        assert after[k] == before[k]
+    assert after["crossing_angle"] == pytest.approx(before["crossing_angle"], rel=1e-12)
