@@ -43,6 +43,11 @@ def lib():
         L.oracle_min_angle.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _dp, _dp, _u64p]
         L.oracle_edge_length_variation.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _dp, _dp]
         L.oracle_segment_pair.argtypes = [_dp, C.c_double, C.POINTER(C.c_int), _dp]
+        L.oracle_crossing_pairs.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64, _i64p]
+        L.oracle_loss.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64, C.c_double,
+                                  C.c_double, C.c_double, _dp]
+        L.oracle_loss_grad.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64,
+                                       C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -140,6 +145,46 @@ def segment_pair(p, ideal_angle: float = 1.2217304763960306) -> tuple[int, float
     _check(lib().oracle_segment_pair(_p(a, _dp), float(ideal_angle), C.byref(kind),
                                      C.byref(ang)), "segment_pair")
     return int(kind.value), float(ang.value)
+
+
+def crossing_pairs(x, y, src, dst) -> np.ndarray:
+    """The crossing set S as an (|S|, 2) array of edge indices e < f."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    n = C.c_int64()
+    _check(lib().oracle_crossing_pairs(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                       _p(d, _i32p), s.shape[0], None, 0, C.byref(n)),
+           "crossing_pairs")
+    out = np.zeros((max(n.value, 1), 2), dtype=np.int64)
+    _check(lib().oracle_crossing_pairs(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                       _p(d, _i32p), s.shape[0], _p(out, _i64p), n.value,
+                                       C.byref(n)), "crossing_pairs")
+    return out[:n.value]
+
+
+def loss(x, y, src, dst, pairs, ideal_angle, w_angle=1.0, w_length=1.0) -> float:
+    """w_a (1 - E_ca) + w_l M_l at (possibly non-integer) coordinates, with
+    the crossing set frozen to ``pairs``."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    P = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    out = C.c_double()
+    _check(lib().oracle_loss(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p), _p(d, _i32p),
+                             s.shape[0], _p(P, _i64p), P.shape[0], float(ideal_angle),
+                             float(w_angle), float(w_length), C.byref(out)), "loss")
+    return float(out.value)
+
+
+def loss_grad(x, y, src, dst, pairs, ideal_angle, w_angle=1.0, w_length=1.0):
+    """(loss, dL/dx, dL/dy) -- the analytic gradient of ``loss``."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    P = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    gx = np.zeros(x.shape[0])
+    gy = np.zeros(x.shape[0])
+    out = C.c_double()
+    _check(lib().oracle_loss_grad(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                  _p(d, _i32p), s.shape[0], _p(P, _i64p), P.shape[0],
+                                  float(ideal_angle), float(w_angle), float(w_length),
+                                  C.byref(out), _p(gx, _dp), _p(gy, _dp)), "loss_grad")
+    return float(out.value), gx, gy
 
 
 def all_metrics(L) -> dict:

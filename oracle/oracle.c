@@ -376,3 +376,123 @@ int oracle_segment_pair(const double *p, double ideal_angle, int *out_kind,
     free(ix); free(iy);
     return 0;
 }
+
+/* ------------------------------ loss of a layout-optimisation step (adjoint)
+ *
+ * The paper names layout optimisation as an application (Conclusion) without
+ * defining a loss; the reading used here (R14) is
+ *     L = w_a (1 - E_ca) + w_l M_l
+ *       = w_a / (ideal |S|) sum_{(e,f) in S} |ideal - a_ef|  +  w_l M_l,
+ * with the crossing set S frozen (found on the integer layout, then held
+ * fixed while the coordinates move), a_ef = atan2(|c|, |g|) the acute line
+ * angle from c = d_e x d_f and g = d_e . d_f, and M_l of Algorithm 3.
+ * The gradient is the plain chain rule of that expression, with the
+ * one-sided kinks (a = ideal, g = 0, c = 0, equal edge lengths, zero-length
+ * edges) contributing 0. */
+
+/* S: every crossing pair e < f (Algorithms 4/5 with readings R2, R3). */
+int oracle_crossing_pairs(const double *x, const double *y, int64_t n,
+                          const int32_t *src, const int32_t *dst, int64_t m,
+                          int64_t *out_pairs, int64_t cap, int64_t *out_n) {
+    if (n < 0 || m < 0 || !out_n || cap < 0 || (cap > 0 && !out_pairs)) return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    int64_t k = 0;
+    for (int64_t e = 0; e < m; ++e)
+        for (int64_t f = e + 1; f < m; ++f)
+            if (edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) {
+                if (k < cap) { out_pairs[2 * k] = e; out_pairs[2 * k + 1] = f; }
+                ++k;
+            }
+    free(ix); free(iy);
+    *out_n = k;
+    return 0;
+}
+
+static double sgn(double v) { return (v > 0.0) - (v < 0.0); }
+
+/* loss and, when gx/gy are given, its analytic gradient (arrays of n) */
+static int loss_impl(const double *x, const double *y, int64_t n, const int32_t *src,
+                     const int32_t *dst, int64_t m, const int64_t *pairs, int64_t n_pairs,
+                     double ideal, double w_a, double w_l, double *out_loss, double *gx,
+                     double *gy) {
+    if (n < 0 || m < 0 || n_pairs < 0 || (n_pairs > 0 && !pairs) || !(ideal > 0.0) || !out_loss)
+        return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    for (int64_t i = 0; i < n_pairs; ++i)
+        if (pairs[2 * i] < 0 || pairs[2 * i] >= m || pairs[2 * i + 1] < 0 || pairs[2 * i + 1] >= m)
+            return 1;
+    if (gx) for (int64_t v = 0; v < n; ++v) { gx[v] = 0.0; gy[v] = 0.0; }
+    /* crossing-angle term */
+    nsum dev = {0.0, 0.0};
+    const double scale = n_pairs ? w_a / (ideal * (double)n_pairs) : 0.0;
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        const int64_t e = pairs[2 * i], f = pairs[2 * i + 1];
+        const double ax = x[dst[e]] - x[src[e]], ay = y[dst[e]] - y[src[e]];
+        const double bx = x[dst[f]] - x[src[f]], by = y[dst[f]] - y[src[f]];
+        const double c = ax * by - ay * bx, g = ax * bx + ay * by;
+        const double a = atan2(fabs(c), fabs(g));
+        nsum_add(&dev, fabs(ideal - a));
+        if (!gx || c == 0.0) continue;
+        /* d|ideal - a|/da = -sgn(ideal - a);  a = atan2(|c|, |g|) */
+        const double k = -sgn(ideal - a) * scale;
+        const double den = c * c + g * g;
+        const double da_dc = sgn(c) * fabs(g) / den, da_dg = -sgn(g) * fabs(c) / den;
+        /* c = ax by - ay bx,  g = ax bx + ay by */
+        const double dax = da_dc * by + da_dg * bx, day = -da_dc * bx + da_dg * by;
+        const double dbx = -da_dc * ay + da_dg * ax, dby = da_dc * ax + da_dg * ay;
+        gx[dst[e]] += k * dax; gx[src[e]] -= k * dax;
+        gy[dst[e]] += k * day; gy[src[e]] -= k * day;
+        gx[dst[f]] += k * dbx; gx[src[f]] -= k * dbx;
+        gy[dst[f]] += k * dby; gy[src[f]] -= k * dby;
+    }
+    double loss = n_pairs ? w_a * nsum_get(&dev) / (ideal * (double)n_pairs) : 0.0;
+    /* edge-length-variation term (Algorithm 3) */
+    if (m >= 2) {
+        double *len = (double *)malloc(sizeof(double) * (size_t)m);
+        nsum s1 = {0.0, 0.0};
+        for (int64_t e = 0; e < m; ++e) {
+            const double dx = x[dst[e]] - x[src[e]], dy = y[dst[e]] - y[src[e]];
+            len[e] = sqrt(dx * dx + dy * dy);
+            nsum_add(&s1, len[e]);
+        }
+        const double N = (double)m, mu = nsum_get(&s1) / N;
+        nsum s2 = {0.0, 0.0};
+        for (int64_t e = 0; e < m; ++e) nsum_add(&s2, (len[e] - mu) * (len[e] - mu));
+        if (mu > 0.0) {
+            const double sigma = sqrt(nsum_get(&s2) / N);        /* population spread */
+            const double ml = sigma / mu / sqrt(N - 1.0);
+            loss += w_l * ml;
+            if (gx && sigma > 0.0) {
+                for (int64_t e = 0; e < m; ++e) {
+                    if (len[e] == 0.0) continue;
+                    /* dM_l/dl_e = ((l_e - mu)/(N sigma mu) - sigma/(N mu^2)) / sqrt(N - 1) */
+                    const double dl = w_l * ((len[e] - mu) / (N * sigma * mu) - sigma / (N * mu * mu)) /
+                                      sqrt(N - 1.0);
+                    const double dx = x[dst[e]] - x[src[e]], dy = y[dst[e]] - y[src[e]];
+                    gx[dst[e]] += dl * dx / len[e]; gx[src[e]] -= dl * dx / len[e];
+                    gy[dst[e]] += dl * dy / len[e]; gy[src[e]] -= dl * dy / len[e];
+                }
+            }
+        }
+        free(len);
+    }
+    *out_loss = loss;
+    return 0;
+}
+
+int oracle_loss(const double *x, const double *y, int64_t n, const int32_t *src,
+                const int32_t *dst, int64_t m, const int64_t *pairs, int64_t n_pairs,
+                double ideal, double w_a, double w_l, double *out_loss) {
+    return loss_impl(x, y, n, src, dst, m, pairs, n_pairs, ideal, w_a, w_l, out_loss, NULL, NULL);
+}
+
+int oracle_loss_grad(const double *x, const double *y, int64_t n, const int32_t *src,
+                     const int32_t *dst, int64_t m, const int64_t *pairs, int64_t n_pairs,
+                     double ideal, double w_a, double w_l, double *out_loss, double *gx,
+                     double *gy) {
+    if (!gx || !gy) return 1;
+    return loss_impl(x, y, n, src, dst, m, pairs, n_pairs, ideal, w_a, w_l, out_loss, gx, gy);
+}

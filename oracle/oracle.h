@@ -26,4 +26,14 @@ int oracle_edge_length_variation(const double *x, const double *y, int64_t n,
                                  double *out_metric, double *out_mean);
 int oracle_segment_pair(const double *p, double ideal_angle, int *out_kind,
                         double *out_angle);
+int oracle_crossing_pairs(const double *x, const double *y, int64_t n,
+                          const int32_t *src, const int32_t *dst, int64_t m,
+                          int64_t *out_pairs, int64_t cap, int64_t *out_n);
+int oracle_loss(const double *x, const double *y, int64_t n, const int32_t *src,
+                const int32_t *dst, int64_t m, const int64_t *pairs, int64_t n_pairs,
+                double ideal, double w_a, double w_l, double *out_loss);
+int oracle_loss_grad(const double *x, const double *y, int64_t n, const int32_t *src,
+                     const int32_t *dst, int64_t m, const int64_t *pairs, int64_t n_pairs,
+                     double ideal, double w_a, double w_l, double *out_loss, double *gx,
+                     double *gy);
 #endif

@@ -1,0 +1,104 @@
+"""Pins of the oracle's layout-optimisation loss and its analytic gradient.
+
+L = w_a (1 - E_ca) + w_l M_l with the crossing set S frozen.  Independent
+checks: central finite differences of the loss, the three exact symmetry
+identities of a translation-, rotation- and scale-invariant function, the
+metrics of Algorithms 3 and 5 at integer coordinates, and a closed-form
+derivative (rotating one edge of a crossing pair).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2411_09809_amd import gen
+
+IDEAL = gen.IDEAL_ANGLE
+
+
+def jittered(seed, n=60, m=120, extent=400):
+    """An integer layout, its crossing set, and coordinates moved off the
+    grid by a small random amount (away from every kink)."""
+    import oracle
+    L = gen.uniform_layout(n, m, extent=extent, seed=seed)
+    S = oracle.crossing_pairs(L.x, L.y, L.src, L.dst)
+    rng = np.random.default_rng(seed)
+    x = L.x.astype(np.float64) + rng.uniform(-0.3, 0.3, size=n)
+    y = L.y.astype(np.float64) + rng.uniform(-0.3, 0.3, size=n)
+    return L, S, x, y
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_gradient_matches_central_differences(orc, seed):
+    L, S, x, y = jittered(seed)
+    assert S.shape[0] > 20
+    f0, gx, gy = orc.loss_grad(x, y, L.src, L.dst, S, IDEAL)
+    h = 1e-5
+    scale = max(np.abs(gx).max(), np.abs(gy).max())
+    for v in range(L.n_nodes):
+        for arr, g in ((x, gx), (y, gy)):
+            old = arr[v]
+            arr[v] = old + h
+            fp = orc.loss(x, y, L.src, L.dst, S, IDEAL)
+            arr[v] = old - h
+            fm = orc.loss(x, y, L.src, L.dst, S, IDEAL)
+            arr[v] = old
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - g[v]) <= 1e-6 * scale, (v, fd, g[v])
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_gradient_symmetry_identities(orc, seed):
+    """L is invariant under translation, rotation and scaling, so its
+    gradient has zero net force, zero torque and zero virial."""
+    L, S, x, y = jittered(seed, n=200, m=500, extent=3000)
+    _, gx, gy = orc.loss_grad(x, y, L.src, L.dst, S, IDEAL, 1.0, 1.0)
+    mag = np.abs(gx).sum() + np.abs(gy).sum()
+    r = np.abs(x).max() + np.abs(y).max()
+    assert abs(gx.sum()) <= 1e-12 * mag
+    assert abs(gy.sum()) <= 1e-12 * mag
+    assert abs((x * gy - y * gx).sum()) <= 1e-12 * mag * r
+    assert abs((x * gx + y * gy).sum()) <= 1e-12 * mag * r
+
+
+def test_loss_at_integer_points_is_the_metrics(orc):
+    L = gen.uniform_layout(400, 900, extent=2000, seed=8)
+    S = orc.crossing_pairs(L.x, L.y, L.src, L.dst)
+    eca, cnt, _ = orc.crossing_angle(L.x, L.y, L.src, L.dst, IDEAL)
+    ml, _ = orc.edge_length_variation(L.x, L.y, L.src, L.dst)
+    assert S.shape[0] == cnt
+    assert orc.loss(L.x, L.y, L.src, L.dst, S, IDEAL, 1.0, 1.0) == pytest.approx(
+        (1 - eca) + ml, rel=1e-13)
+    assert orc.loss(L.x, L.y, L.src, L.dst, S, IDEAL, 2.5, 0.0) == pytest.approx(
+        2.5 * (1 - eca), rel=1e-13)
+
+
+def test_rotating_one_edge_of_a_crossing_pair(orc):
+    """Edges (0,0)-(4,0) and (1,-1)-(3,1) cross at a = 45 deg < ideal.
+    Rotating the second edge about its midpoint by dphi changes a by dphi,
+    so d(|ideal - a| / ideal)/dphi = -1/ideal."""
+    x = np.array([0.0, 4.0, 1.0, 3.0])
+    y = np.array([0.0, 0.0, -1.0, 1.0])
+    src, dst = np.array([0, 2]), np.array([1, 3])
+    S = np.array([[0, 1]])
+    f, gx, gy = orc.loss_grad(x, y, src, dst, S, IDEAL, 1.0, 0.0)
+    assert f == pytest.approx((IDEAL - math.pi / 4) / IDEAL, rel=1e-14)
+    # infinitesimal rotation about (2, 0): p -> p + dphi * (-(p_y - 0), p_x - 2)
+    dphi = gx[2] * 1.0 + gy[2] * (-1.0) + gx[3] * (-1.0) + gy[3] * 1.0
+    assert dphi == pytest.approx(-1.0 / IDEAL, rel=1e-12)
+    # sliding an end of the horizontal edge along its own line keeps a
+    assert gx[0] == pytest.approx(0.0, abs=1e-15) and gx[1] == pytest.approx(0.0, abs=1e-15)
+
+
+def test_kinks_contribute_zero(orc):
+    """Perpendicular crossing (g = 0) and parallel overlap (c = 0) give no
+    angle gradient; equal edge lengths give no length gradient."""
+    x = np.array([0.0, 2.0, 0.0, 2.0])
+    y = np.array([0.0, 2.0, 2.0, 0.0])
+    f, gx, gy = orc.loss_grad(x, y, [0, 2], [1, 3], [[0, 1]], IDEAL, 1.0, 1.0)
+    assert f == pytest.approx(20 / 70, rel=1e-14)
+    assert np.abs(gx).max() == 0.0 and np.abs(gy).max() == 0.0
+    x = np.array([0.0, 4.0, 2.0, 6.0])
+    y = np.zeros(4)
+    f, gx, gy = orc.loss_grad(x, y, [0, 2], [1, 3], [[0, 1]], IDEAL, 1.0, 0.0)
+    assert f == pytest.approx(1.0) and np.abs(gx).max() == 0.0 and np.abs(gy).max() == 0.0
