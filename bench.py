@@ -103,6 +103,45 @@ def bench_batch(torch, steps: int):
             "variants": B.variants()}
 
 
+def bench_adjoint(torch, reps: int, gd_steps: int):
+    """Random geometric layout (|V| = 20,000, ~60,000 edges): the loss
+    forward (crossing-angle sweep + edge lengths) against forward + adjoint,
+    and a gradient-descent run with the exact crossing count every step."""
+    from paper_2411_09809_amd import gen, metrics, optim
+
+    L = gen.geometric_layout(seed=0)
+    D = metrics.DeviceLayout.from_host(L)
+    pairs = math.comb(L.n_edges, 2)
+
+    def fwd():
+        metrics.crossing_angle(D.x, D.y, D.src, D.dst, async_=True)
+        metrics.edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)
+
+    def fwd_bwd():
+        optim.loss_grad(D.x, D.y, D.src, D.dst)
+
+    out = {}
+    for name, fn in (("forward_ms", fwd), ("forward_backward_ms", fwd_bwd)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) * 1e3 / reps
+    t0 = time.perf_counter()
+    _, _, hist = optim.descend(D.x, D.y, D.src, D.dst, steps=gd_steps, step_size=2.0)
+    torch.cuda.synchronize()
+    out.update({"workload": f"random geometric graph |V|={L.n_nodes} |E|={L.n_edges} in "
+                            "[0,2^16)^2, ideal angle 70 deg",
+                "edge_pairs": pairs,
+                "backward_over_forward": out["forward_backward_ms"] / out["forward_ms"],
+                "gd_steps": gd_steps, "gd_total_s": time.perf_counter() - t0,
+                "gd_loss_first_last": [hist[0][0], hist[-1][0]],
+                "gd_crossings_first_last": [hist[0][1], hist[-1][1]]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +152,7 @@ def main():
     ap.add_argument("--cpu-pairs", type=float, default=5e9,
                     help="edge pairs in the CPU-baseline sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-layout comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward part")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -225,6 +265,9 @@ def main():
     if not args.no_batch:
         log("[bench] batched 512 layouts ...")
         rec["batched"] = bench_batch(torch, max(3, args.steps // 4))
+    if not args.no_adjoint:
+        log("[bench] forward + adjoint ...")
+        rec["fwd_bwd"] = bench_adjoint(torch, max(3, args.steps // 2), 100)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(L, args.cpu_pairs)

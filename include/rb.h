@@ -128,6 +128,24 @@ rb_status rb_edge_length_variation(const float *x, const float *y, int64_t n_nod
                                    double *out_metric, double *out_mean,
                                    void *ws, size_t ws_bytes, void *stream);
 
+/* Layout-optimisation loss and its gradient (the application the paper's
+ * Conclusion names; the loss is this library's choice, built from the
+ * Algorithm 5 and Algorithm 3 metrics):
+ *     L = w_angle (1 - E_ca) + w_length M_l
+ * with the crossing set S of the current layout held fixed, and
+ * d L / d(x, y) of every node, computed exactly as the chain rule through
+ * each crossing pair's acute angle and each edge's length.  Kinks (a pair
+ * at exactly the ideal angle, perpendicular or parallel lines, equal edge
+ * lengths, zero-length edges) contribute 0.  The coordinates must satisfy
+ * the layout preconditions (the crossing set is exact on integers).
+ * out_loss: device double[1]; out_grad_x, out_grad_y: device double[n_nodes]
+ * (overwritten); out_count: device uint64[1] or NULL -- |S| = E_c. */
+rb_status rb_loss_grad(const float *x, const float *y, int64_t n_nodes,
+                       const int32_t *src, const int32_t *dst, int64_t n_edges,
+                       double ideal_angle, double w_angle, double w_length,
+                       double *out_loss, double *out_grad_x, double *out_grad_y,
+                       uint64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+
 /* Checks the layout preconditions listed above on the GPU and waits for the
  * result (this call synchronises `stream`).  Returns RB_OK or RB_EDOMAIN;
  * *out_flags (host int32, may be NULL) receives a bit set:

@@ -390,7 +390,8 @@ int oracle_segment_pair(const double *p, double ideal_angle, int *out_kind,
  * one-sided kinks (a = ideal, g = 0, c = 0, equal edge lengths, zero-length
  * edges) contributing 0. */
 
-/* S: every crossing pair e < f (Algorithms 4/5 with readings R2, R3). */
+/* S: every crossing pair e < f (Algorithms 4/5 with readings R2, R3), in
+ * (e, f) order; written only when cap >= |S|. */
 int oracle_crossing_pairs(const double *x, const double *y, int64_t n,
                           const int32_t *src, const int32_t *dst, int64_t m,
                           int64_t *out_pairs, int64_t cap, int64_t *out_n) {
@@ -399,13 +400,31 @@ int oracle_crossing_pairs(const double *x, const double *y, int64_t n,
     int64_t *ix, *iy;
     int st = to_int_coords(x, y, n, &ix, &iy);
     if (st) return st;
-    int64_t k = 0;
-    for (int64_t e = 0; e < m; ++e)
+    /* count per row, then fill each row's slice: the pairs come out in
+     * (e, f) order whatever the thread count */
+    int64_t *row = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t e = 0; e < m; ++e) {
+        int64_t c = 0;
         for (int64_t f = e + 1; f < m; ++f)
-            if (edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) {
-                if (k < cap) { out_pairs[2 * k] = e; out_pairs[2 * k + 1] = f; }
-                ++k;
-            }
+            c += edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f]) != 0;
+        row[e + 1] = c;
+    }
+    for (int64_t e = 0; e < m; ++e) row[e + 1] += row[e];
+    const int64_t k = m ? row[m] : 0;
+    if (cap >= k && k > 0) {
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t e = 0; e < m; ++e) {
+            int64_t at = row[e];
+            for (int64_t f = e + 1; f < m; ++f)
+                if (edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) {
+                    out_pairs[2 * at] = e;
+                    out_pairs[2 * at + 1] = f;
+                    ++at;
+                }
+        }
+    }
+    free(row);
     free(ix); free(iy);
     *out_n = k;
     return 0;

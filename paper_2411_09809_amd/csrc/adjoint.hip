@@ -1,0 +1,305 @@
+// Gradient of a layout-optimisation loss built from two of the metrics:
+//     L = w_a (1 - E_ca) + w_l M_l
+//       = w_a / (ideal |S|) sum_{(e,f) in S} |ideal - a_ef|  +  w_l M_l,
+// with the crossing set S frozen at the current (integer) layout.
+//
+// Through the line angles th in [0, pi) of the edges (a = pi/2 - ||d| - pi/2|,
+// d = th_e - th_f), the derivative of one term is
+//     d|ideal - a_ef| / d th_e = - d|ideal - a_ef| / d th_f
+//                              = sgn(v) * sgn(dot) * sgn(cross)  in {-1, 0, 1},
+// where v = (ideal - pi/2) + ||d| - pi/2| (so sgn(a - ideal) = -sgn(v)),
+// cross = d_e x d_f and dot = d_e . d_f.  The branch signs come from the exact
+// integer cross and dot products (the folding of directions into [0, pi)
+// cancels), so perpendicular (dot = 0) and parallel (cross = 0) pairs give 0,
+// the symmetric choice at those kinks.  The backward sweep therefore only
+// accumulates integers: k_e = sum_f q_ef per edge (rows in registers,
+// columns via wave popcounts and LDS, then integer atomics: exact and
+// order-independent).  A per-edge pass applies the chain rule in double:
+//     dL/dD_e = w_a k_e / (ideal |S|) (-dy, dx) / l^2 + w_l dM_l/dl_e (dx, dy) / l,
+//     dM_l/dl_e = ((l_e - mu)/(N s mu) - s/(N mu^2)) / sqrt(N - 1)   (s: population
+//     spread of the lengths), and scatters +dL/dD_e to the head node and
+//     -dL/dD_e to the tail node.
+#include <algorithm>
+
+#include "rb_device.h"
+#include "rb_internal.h"
+
+namespace rb {
+namespace {
+
+constexpr double kHalfPi = 1.5707963267948966192;
+
+__device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
+    return I * nC - (int64_t)K * I * (I - 1) / 2;
+}
+
+// touching pairs: same decision as the forward sweep (incident pairs never
+// count; both products zero need overlapping bounding boxes)
+__device__ __noinline__ bool touching_pair_b(double rx, double ry, double rdx, double rdy,
+                                             double rc, int2 rid, double fx, double fy,
+                                             double fdx, double fdy, double fc, int2 fid) {
+    const double o1 = fma(-rdy, fx, fma(rdx, fy, -rc));
+    const double o3 = fma(-fdy, rx, fma(fdx, ry, -fc));
+    const double cr = fma(-rdy, fdx, rdx * fdy);
+    const double p12 = o1 * (o1 + cr), p34 = o3 * (o3 - cr);
+    const bool incident = (rid.x == fid.x) | (rid.x == fid.y) | (rid.y == fid.x) | (rid.y == fid.y);
+    bool ok = fmin(p12, p34) < 0.0;
+    if (!ok) {
+        const double ax0 = fmin(rx, rx + rdx), ax1 = fmax(rx, rx + rdx);
+        const double ay0 = fmin(ry, ry + rdy), ay1 = fmax(ry, ry + rdy);
+        const double bx0 = fmin(fx, fx + fdx), bx1 = fmax(fx, fx + fdx);
+        const double by0 = fmin(fy, fy + fdy), by1 = fmax(fy, fy + fdy);
+        ok = (fmax(ax0, bx0) <= fmin(ax1, bx1)) && (fmax(ay0, by0) <= fmin(ay1, by1));
+    }
+    return ok && !incident;
+}
+
+template <int K, bool DIAG>
+__device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
+                                              const int2 *__restrict__ rid,
+                                              int *__restrict__ colk, const double (&rX)[K],
+                                              const double (&rY)[K], const double (&rDX)[K],
+                                              const double (&rDY)[K], const double (&rC)[K],
+                                              const double (&rTH)[K], int (&kr)[K], int tid,
+                                              int64_t row0, int64_t col0, double angc) {
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int j = 0; j < kChunk; ++j) {
+        const double cX = col[j].x, cY = col[j].y;
+        const double cDX = col[j].dx, cDY = col[j].dy;
+        const double cC = col[j].c, cTH = col[j].th;
+        int colsum = 0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const double o1 = fma(-rDY[r], cX, fma(rDX[r], cY, -rC[r]));
+            const double o3 = fma(-cDY, rX[r], fma(cDX, rY[r], -cC));
+            const double cr = fma(-rDY[r], cDX, rDX[r] * cDY);
+            const double p12 = o1 * (o1 + cr);
+            const double p34 = o3 * (o3 - cr);
+            const double m = fmax(p12, p34);
+            const bool in_tri = !DIAG || (col0 + j > row0 + (int64_t)r * kBlock);
+            bool closed = (m < 0.0) & in_tri;
+            const bool zero = (m == 0.0) & in_tri;
+            const double u = fabs(rTH[r] - cTH) - kHalfPi;
+            const double v = angc + fabs(u);
+            const double dot = fma(rDX[r], cDX, rDY[r] * cDY);
+            const double s = (v * dot) * cr;
+            if (__builtin_expect(__builtin_amdgcn_ballot_w64(zero) != 0, 0)) {
+                if (zero) {
+                    double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC;
+                    __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc));
+                    const int2 fid = make_int2(col[j].s, col[j].t);
+                    closed = touching_pair_b(rX[r], rY[r], rDX[r], rDY[r], rC[r],
+                                             rid[r * kBlock + tid], fx, fy, fdx, fdy, fc, fid);
+                }
+            }
+            const bool pos = closed & (s > 0.0);
+            const bool neg = closed & (s < 0.0);
+            kr[r] += (int)pos - (int)neg;
+            colsum += (int)__popcll(__builtin_amdgcn_ballot_w64(pos)) -
+                      (int)__popcll(__builtin_amdgcn_ballot_w64(neg));
+        }
+        if (lane == 0) colk[wave * kChunk + j] = colsum;
+    }
+}
+
+template <int K, int WAVES>
+__global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
+    const EdgeRec *__restrict__ rec, SweepLayout lay, int64_t n_units, double ideal,
+    int *__restrict__ kacc) {
+    __shared__ EdgeRec col[kChunk];
+    __shared__ int2 rid[kBlock * K];
+    __shared__ int colk[(kBlock / 64) * kChunk];
+    const int tid = threadIdx.x;
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t u_begin = block_first_unit(n_units, G, b);
+    const int64_t u_end = block_first_unit(n_units, G, b + 1);
+    constexpr int64_t R = (int64_t)kBlock * K;
+    const double angc = ideal - kHalfPi;
+    int64_t lo = 0, hi = lay.n_row_tiles - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (units_before(mid, lay.n_chunks, K) <= u_begin) lo = mid;
+        else hi = mid - 1;
+    }
+    int64_t I = lo;
+    int64_t c = I * K + (u_begin - units_before(I, lay.n_chunks, K));
+    double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
+    int kr[K];
+    bool rows_loaded = false;
+
+    auto flush_rows = [&]() {
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (kr[r] != 0) atomicAdd(&kacc[I * R + (int64_t)r * kBlock + tid], kr[r]);
+        }
+    };
+
+    for (int64_t u = u_begin; u < u_end; ++u) {
+        __syncthreads();                      // previous chunk, ids and column sums consumed
+        if (!rows_loaded) {
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const EdgeRec e = rec[I * R + (int64_t)r * kBlock + tid];
+                rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
+                rC[r] = e.c; rTH[r] = e.th;
+                rid[r * kBlock + tid] = make_int2(e.s, e.t);
+                kr[r] = 0;
+            }
+            rows_loaded = true;
+        }
+        col[tid] = rec[c * kChunk + tid];
+        __syncthreads();
+        const int64_t row0 = I * R + tid, col0 = c * kChunk;
+        if (c < (I + 1) * K)
+            adjoint_chunk<K, true>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, row0, col0,
+                                   angc);
+        else
+            adjoint_chunk<K, false>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, row0, col0,
+                                    angc);
+        __syncthreads();
+        {   // the column edge f of a pair receives -q
+            int sum = 0;
+            for (int w = 0; w < kBlock / 64; ++w) sum += colk[w * kChunk + tid];
+            if (sum != 0) atomicSub(&kacc[col0 + tid], sum);
+        }
+        if (++c == lay.n_chunks) {
+            flush_rows();
+            ++I;
+            c = I * K;
+            rows_loaded = false;
+        }
+    }
+    if (rows_loaded) flush_rows();
+}
+
+// Chain rule per edge, scattered to the end nodes; thread 0 also writes the loss.
+__global__ __launch_bounds__(256) void edge_grad_kernel(
+    const EdgeRec *__restrict__ rec, const int *__restrict__ kacc, int64_t n_edges,
+    const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t n_nodes,
+    const Scalars *__restrict__ sc, double ideal, double w_a, double w_l, double *gx, double *gy,
+    double *out_loss) {
+    const unsigned long long S = sc->count;
+    const double mu = sc->mean, ml = sc->ml, N = (double)n_edges;
+    // population spread of the lengths, from M_l = s / mu / sqrt(N - 1)
+    const double spread = (n_edges >= 2) ? ml * mu * sqrt(N - 1.0) : 0.0;
+    const double ka = S ? w_a / (ideal * (double)S) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && out_loss)
+        *out_loss = (S ? w_a * (1.0 - sc->eca) : 0.0) + w_l * ml;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_edges;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = src[e], t = dst[e];
+        if (!dev::valid_ids(s, t, n_nodes)) continue;
+        const EdgeRec r = rec[e];
+        const double l2 = fma(r.dx, r.dx, r.dy * r.dy);
+        if (l2 == 0.0) continue;                        // zero-length edge: no direction
+        const double l = sqrt(l2);
+        const double gth = ka * (double)kacc[e] / l2;
+        double gdx = -gth * r.dy, gdy = gth * r.dx;
+        if (spread > 0.0 && mu > 0.0) {
+            const double dml = w_l * ((l - mu) / (N * spread * mu) - spread / (N * mu * mu)) /
+                               sqrt(N - 1.0);
+            gdx = fma(dml, r.dx / l, gdx);
+            gdy = fma(dml, r.dy / l, gdy);
+        }
+        atomicAdd(&gx[t], gdx);
+        atomicAdd(&gy[t], gdy);
+        atomicAdd(&gx[s], -gdx);
+        atomicAdd(&gy[s], -gdy);
+    }
+}
+
+__global__ void fill_f64_kernel(double *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// copy the forward results into the scalar block used by the gradient pass
+__global__ void stash_kernel(Scalars *sc, const unsigned long long *count, const double *eca,
+                             const double *ml, unsigned long long *out_count) {
+    if (threadIdx.x == 0) {
+        sc->count = *count;
+        sc->eca = *eca;
+        sc->ml = *ml;
+        if (out_count) *out_count = *count;
+    }
+}
+
+int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+constexpr int kAdjRows = 2, kAdjWaves = 4;
+int g_adj_grid = 0;
+
+#define RB_TRY(expr)                          \
+    do {                                      \
+        hipError_t _e = (expr);               \
+        if (_e != hipSuccess) return _e;      \
+    } while (0)
+
+}  // namespace
+
+hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                            const int32_t *dst, int64_t n_edges, double ideal, double w_a,
+                            double w_l, double *out_loss, double *gx, double *gy,
+                            unsigned long long *out_count, const WsLayout &L, char *w,
+                            hipStream_t st) {
+    EdgeRec *rec = (EdgeRec *)(w + L.edge_rec);
+    Scalars *sc = (Scalars *)(w + L.scalars);
+    int *kacc = (int *)(w + L.kacc);
+    unsigned long long *fw_count = (unsigned long long *)(w + L.fwd);
+    double *fw_eca = (double *)(w + L.fwd) + 1;
+    double *fw_ml = (double *)(w + L.fwd) + 2;
+    // forward: crossing set, E_ca and M_l (with the mean length in sc)
+    RB_TRY(launch_edge_prep(x, y, src, dst, n_nodes, n_edges, L.n_edge_pad, rec, st));
+    {
+        const int v = tuned_variant(1, false, n_edges);
+        const int rows = cross_variant(v).rows;
+        SweepArgs a;
+        a.table = nullptr;
+        a.single = sweep_layout(n_edges, rows, 0, 0);
+        a.n_layouts = 1;
+        a.n_units = sweep_units(n_edges, rows);
+        const int grid = (int)std::min<int64_t>(a.n_units, cross_grid(v, true));
+        CrossPartial *part = (CrossPartial *)(w + L.partial);
+        RB_TRY(launch_cross_sweep(v, true, rec, a, grid, ideal, part, st));
+        RB_TRY(launch_cross_finalize(part, grid, ideal, fw_count, nullptr, fw_eca, nullptr, st));
+    }
+    RB_TRY(launch_zero_scalars(sc, st));
+    RB_TRY(launch_elv(x, y, src, dst, n_nodes, n_edges, (double *)(w + L.partial), sc, fw_ml,
+                      nullptr, st));
+    hipLaunchKernelGGL(stash_kernel, dim3(1), dim3(64), 0, st, sc, fw_count, fw_eca, fw_ml,
+                       out_count);
+    RB_TRY(hipGetLastError());
+    // backward sweep: integer adjoint counts per edge
+    RB_TRY(launch_fill_u32((uint32_t *)kacc, L.n_edge_pad, 0u, st));
+    const SweepLayout lay = sweep_layout(n_edges, kAdjRows, 0, 0);
+    const int64_t U = sweep_units(n_edges, kAdjRows);
+    if (g_adj_grid == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, adjoint_sweep_kernel<kAdjRows, kAdjWaves>, kBlock, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        g_adj_grid = per_cu * device_cu_count();
+    }
+    const int grid = (int)std::min<int64_t>(U, g_adj_grid);
+    hipLaunchKernelGGL((adjoint_sweep_kernel<kAdjRows, kAdjWaves>), dim3(grid), dim3(kBlock), 0,
+                       st, rec, lay, U, ideal, kacc);
+    RB_TRY(hipGetLastError());
+    // chain rule and scatter
+    const int64_t V = n_nodes > 0 ? n_nodes : 1;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(V)), dim3(256), 0, st, gx, n_nodes);
+    RB_TRY(hipGetLastError());
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(V)), dim3(256), 0, st, gy, n_nodes);
+    RB_TRY(hipGetLastError());
+    hipLaunchKernelGGL(edge_grad_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, rec, kacc,
+                       n_edges, src, dst, n_nodes, sc, ideal, w_a, w_l, gx, gy, out_loss);
+    return hipGetLastError();
+}
+
+}  // namespace rb

@@ -163,6 +163,8 @@ bool ws_layout(int64_t n_nodes, int64_t n_edges, WsLayout *L) {
     L->dv = take(sizeof(double) * (size_t)V);
     L->big_list = take(sizeof(int32_t) * (size_t)V);
     L->hash = take(sizeof(unsigned long long) * (size_t)h);
+    L->kacc = take(sizeof(int32_t) * (size_t)L->n_edge_pad);
+    L->fwd = take(sizeof(double) * 4);
     L->total = off;
     return true;
 }
@@ -304,6 +306,29 @@ rb_status rb_edge_length_variation(const float *x, const float *y, int64_t n_nod
                               (Scalars *)(w + L.scalars), out_metric, out_mean,
                               (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "edge_length_variation launch");
+    return RB_OK;
+}
+
+rb_status rb_loss_grad(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                       const int32_t *dst, int64_t n_edges, double ideal_angle, double w_angle,
+                       double w_length, double *out_loss, double *out_grad_x, double *out_grad_y,
+                       uint64_t *out_count, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (!out_loss || (n_nodes > 0 && (!out_grad_x || !out_grad_y)))
+        return fail(RB_EINVAL, "out_loss, out_grad_x or out_grad_y is NULL");
+    if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
+        return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
+    if (!std::isfinite(w_angle) || !std::isfinite(w_length))
+        return fail(RB_EINVAL, "weights must be finite");
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    hipError_t e = launch_loss_grad(x, y, n_nodes, src, dst, n_edges, ideal_angle, w_angle,
+                                    w_length, out_loss, out_grad_x, out_grad_y,
+                                    (unsigned long long *)out_count, L, (char *)ws,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rb_loss_grad launch");
     return RB_OK;
 }
 

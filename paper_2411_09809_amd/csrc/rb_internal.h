@@ -87,7 +87,7 @@ SweepVariant occl_variant(int v);
 // Layout of the caller's workspace for one layout (byte offsets, 256-aligned).
 struct WsLayout {
     size_t edge_rec, node_rec, partial, scalars;
-    size_t deg, cursor, offs, angles, dv, big_list, hash;
+    size_t deg, cursor, offs, angles, dv, big_list, hash, kacc, fwd;
     size_t total;
     int64_t n_edge_pad, n_node_pad, hash_size;
 };
@@ -99,8 +99,11 @@ struct __align__(16) Scalars {
     double sum_dv;
     unsigned long long n_used;
     unsigned long long big_count;
+    double ml;              // forward values used by the gradient pass
+    double eca;
+    unsigned long long count;
     int32_t flags;
-    int32_t pad[7];
+    int32_t pad;
 };
 
 // ------------------------------------------------------------------ plans
@@ -155,6 +158,13 @@ hipError_t launch_scan(const uint32_t *deg, int64_t n, unsigned long long *tile,
 hipError_t launch_min_angle_nodes(const uint32_t *deg, const uint32_t *offs, double *ang,
                                   int64_t n_nodes, double *dv, int32_t *big, Scalars *sc,
                                   hipStream_t st);
+
+// loss w_a (1 - E_ca) + w_l M_l and its gradient with respect to x, y
+hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                            const int32_t *dst, int64_t n_edges, double ideal, double w_a,
+                            double w_l, double *out_loss, double *gx, double *gy,
+                            unsigned long long *out_count, const WsLayout &L, char *w,
+                            hipStream_t st);
 
 hipError_t launch_validate(const float *x, const float *y, int64_t n_nodes,
                            const int32_t *src, const int32_t *dst, int64_t n_edges,

@@ -80,6 +80,9 @@ __global__ void zero_scalars_kernel(Scalars *sc) {
         sc->sum_dv = 0.0;
         sc->n_used = 0;
         sc->big_count = 0;
+        sc->ml = 0.0;
+        sc->eca = 0.0;
+        sc->count = 0;
         sc->flags = 0;
     }
 }

@@ -1,0 +1,89 @@
+"""Layout optimisation with the readability loss (rb_loss_grad of rb.h).
+
+``CrossingAngleLengthLoss`` is a ``torch.autograd.Function`` for
+    L = w_angle (1 - E_ca) + w_length M_l
+(crossing set frozen at the evaluated layout): its forward and backward are
+both computed by librb's kernels in one call.  ``descend`` runs gradient
+descent on a float32 master copy of the coordinates, evaluating loss,
+gradient and the exact crossing count on the rounded (integer) layout at
+every step.
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from ._lib import check, lib
+from .metrics import IDEAL_ANGLE, _check_coords, _check_edges, _stream, _ws_args, workspace
+
+
+def loss_grad(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, w_angle: float = 1.0,
+              w_length: float = 1.0):
+    """(loss, dL/dx, dL/dy, crossing count) as device tensors (float64,
+    float64[V], float64[V], int64)."""
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    dev = x.device
+    n = x.numel()
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    gx = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    gy = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = workspace(n, src.numel(), dev)
+    w, wb = _ws_args(ws)
+    check(lib().rb_loss_grad(x.data_ptr(), y.data_ptr(), n, src.data_ptr(), dst.data_ptr(),
+                             src.numel(), float(ideal_angle), float(w_angle), float(w_length),
+                             loss.data_ptr(), gx.data_ptr(), gy.data_ptr(), cnt.data_ptr(), w, wb,
+                             _stream(dev)), "rb_loss_grad")
+    return loss[0], gx[:n], gy[:n], cnt[0]
+
+
+class CrossingAngleLengthLoss(torch.autograd.Function):
+    """L(x, y) = w_angle (1 - E_ca) + w_length M_l on integer-valued float32
+    coordinates; gradients come back in the coordinates' dtype."""
+
+    @staticmethod
+    def forward(ctx, x, y, src, dst, ideal_angle=IDEAL_ANGLE, w_angle=1.0, w_length=1.0):
+        loss, gx, gy, cnt = loss_grad(x, y, src, dst, ideal_angle, w_angle, w_length)
+        ctx.save_for_backward(gx, gy)
+        ctx.dtype = x.dtype
+        ctx.mark_non_differentiable(cnt)
+        return loss, cnt
+
+    @staticmethod
+    def backward(ctx, g_loss, g_cnt):
+        gx, gy = ctx.saved_tensors
+        return ((g_loss * gx).to(ctx.dtype), (g_loss * gy).to(ctx.dtype), None, None, None, None,
+                None)
+
+
+def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
+            extent: int = 1 << 16, ideal_angle: float = IDEAL_ANGLE, w_angle: float = 1.0,
+            w_length: float = 1.0, log=None):
+    """Gradient descent on the readability loss.
+
+    A float32 master copy of the coordinates moves by ``step_size`` grid
+    units along -g / max|g| each step; loss, gradient and the exact crossing
+    count are evaluated on the master rounded to integers and clamped to
+    [0, extent).  Returns (x, y, history) with history = list of
+    (loss, crossings, seconds) per step."""
+    mx = x.detach().clone().to(torch.float32)
+    my = y.detach().clone().to(torch.float32)
+    hist = []
+    for k in range(steps):
+        t0 = time.perf_counter()
+        xi = torch.clamp(torch.round(mx), 0, extent - 1).requires_grad_(True)
+        yi = torch.clamp(torch.round(my), 0, extent - 1).requires_grad_(True)
+        loss, cnt = CrossingAngleLengthLoss.apply(xi, yi, src, dst, ideal_angle, w_angle,
+                                                  w_length)
+        loss.backward()
+        with torch.no_grad():
+            scale = torch.maximum(xi.grad.abs().max(), yi.grad.abs().max()).clamp_min(1e-300)
+            mx -= step_size * xi.grad / scale
+            my -= step_size * yi.grad / scale
+        hist.append((float(loss.detach()), int(cnt), time.perf_counter() - t0))
+        if log:
+            log(k, hist[-1])
+    return (torch.clamp(torch.round(mx), 0, extent - 1), torch.clamp(torch.round(my), 0, extent - 1),
+            hist)

@@ -1,0 +1,162 @@
+"""Adjoint of the readability loss (rb_loss_grad) against the oracle.
+
+* loss and crossing count against the oracle at the integer layout;
+* gradient against the oracle's analytic gradient (a different route: the
+  cross/dot form of the angle instead of line angles) on every node;
+* gradient against FP64 central finite differences of the oracle's loss
+  (h = 1e-3, crossing set frozen) on 64 sampled nodes of the 20,000-node,
+  ~60,000-edge random geometric layout;
+* torch.autograd and a short descent run.
+Tolerance (floating point): |g - g_ref| <= 1e-5 max(|g_ref|, 1e-3 max|g_ref|).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_09809_amd import gen
+
+pytestmark = pytest.mark.gpu
+IDEAL = gen.IDEAL_ANGLE
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+def gpu_loss_grad(L, w_a=1.0, w_l=1.0):
+    from paper_2411_09809_amd import metrics, optim
+    D = metrics.DeviceLayout.from_host(L)
+    loss, gx, gy, cnt = optim.loss_grad(D.x, D.y, D.src, D.dst, IDEAL, w_a, w_l)
+    return float(loss), gx.cpu().numpy(), gy.cpu().numpy(), int(cnt)
+
+
+def close(g, ref):
+    cap = 1e-3 * np.abs(ref).max()
+    return np.abs(g - ref) <= 1e-5 * np.maximum(np.abs(ref), cap)
+
+
+@pytest.mark.parametrize("V,E,extent,seed,w", [
+    (300, 700, 64, 1, (1.0, 1.0)),          # crowded: many perpendicular / parallel / touching pairs
+    (2000, 5000, 4096, 2, (1.0, 1.0)),
+    (1500, 3500, 1 << 16, 3, (0.7, 2.5)),
+])
+def test_gradient_matches_oracle_analytic(torch_mod, V, E, extent, seed, w):
+    L = gen.uniform_layout(V, E, extent=extent, seed=seed)
+    say(f"[grad] V={V} E={E} extent={extent}")
+    S = oracle.crossing_pairs(L.x, L.y, L.src, L.dst)
+    f_ref, gx_ref, gy_ref = oracle.loss_grad(L.x, L.y, L.src, L.dst, S, IDEAL, *w)
+    f, gx, gy, cnt = gpu_loss_grad(L, *w)
+    assert cnt == S.shape[0]
+    assert f == pytest.approx(f_ref, rel=1e-12)
+    assert close(gx, gx_ref).all() and close(gy, gy_ref).all(), (
+        np.abs(gx - gx_ref).max(), np.abs(gy - gy_ref).max(), np.abs(gx_ref).max())
+
+
+def _kink_free_nodes(L, S, h):
+    """Nodes whose central difference of step h cannot cross a kink.  Moving
+    an end point by h turns an edge of length l by at most h/l radians, so a
+    node is kept only if every crossing pair of its edges has its angle more
+    than 4h/min(l_e, l_f) away from the ideal angle and from pi/2 (and is not
+    parallel), and none of its edges has zero length."""
+    x, y = L.x.astype(np.float64), L.y.astype(np.float64)
+    dx = x[L.dst] - x[L.src]
+    dy = y[L.dst] - y[L.src]
+    ln = np.hypot(dx, dy)
+    e, f = S[:, 0], S[:, 1]
+    c = dx[e] * dy[f] - dy[e] * dx[f]
+    g = dx[e] * dx[f] + dy[e] * dy[f]
+    a = np.arctan2(np.abs(c), np.abs(g))
+    margin = 4 * h / np.maximum(np.minimum(ln[e], ln[f]), 1e-300)
+    bad_pair = (c == 0) | (np.abs(a - IDEAL) < margin) | (np.abs(a - np.pi / 2) < margin)
+    bad_edge = np.zeros(L.n_edges, dtype=bool)
+    bad_edge[e[bad_pair]] = True
+    bad_edge[f[bad_pair]] = True
+    bad_edge |= ln == 0
+    bad = np.zeros(L.n_nodes, dtype=bool)
+    bad[L.src[bad_edge]] = True
+    bad[L.dst[bad_edge]] = True
+    return np.where(~bad)[0]
+
+
+def test_gradient_matches_finite_differences_rgg(torch_mod):
+    L = gen.geometric_layout(seed=0)
+    say(f"[grad-fd] rgg V={L.n_nodes} E={L.n_edges}")
+    S = oracle.crossing_pairs(L.x, L.y, L.src, L.dst)
+    f, gx, gy, cnt = gpu_loss_grad(L)
+    assert cnt == S.shape[0]
+    f_ref, gx_ref, gy_ref = oracle.loss_grad(L.x, L.y, L.src, L.dst, S, IDEAL)
+    assert f == pytest.approx(f_ref, rel=1e-12)
+    assert close(gx, gx_ref).all() and close(gy, gy_ref).all()
+    # central differences on 64 sampled nodes (nodes with crossings preferred)
+    x, y = L.x.astype(np.float64), L.y.astype(np.float64)
+    h = 1e-3
+    cand = _kink_free_nodes(L, S, h)
+    crossing_nodes = np.unique(np.concatenate([L.src[S.ravel()], L.dst[S.ravel()]]))
+    cand = np.intersect1d(cand, crossing_nodes)
+    rng = np.random.default_rng(0)
+    nodes = rng.choice(cand, size=64, replace=False)
+    # The difference quotient of the oracle's loss.  Terms that do not
+    # involve the moved node cancel exactly, so only the crossing pairs with
+    # an edge at v (normalised by the full |S|) and the edge-length term are
+    # differenced: the same quotient without the rounding noise of the
+    # O(1) constant part of the loss.
+    fd = np.zeros((64, 2))
+    nS = S.shape[0]
+    for i, v in enumerate(nodes):
+        inc = (L.src == v) | (L.dst == v)
+        Sv = S[inc[S[:, 0]] | inc[S[:, 1]]]
+        wa = Sv.shape[0] / nS
+        for k, arr in enumerate((x, y)):
+            old = arr[v]
+            vals = []
+            for step in (h, -h):
+                arr[v] = old + step
+                vals.append(oracle.loss(x, y, L.src, L.dst, Sv, IDEAL, wa, 0.0) +
+                            oracle.loss(x, y, L.src, L.dst, Sv[:0], IDEAL, 0.0, 1.0))
+            arr[v] = old
+            fd[i, k] = (vals[0] - vals[1]) / (2 * h)
+    got = np.stack([gx[nodes], gy[nodes]], axis=1)
+    rel = np.abs(got - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    say(f"[grad-fd] max relative error {rel.max():.3e}")
+    assert rel.max() <= 1e-5
+
+
+def test_autograd_function(torch_mod):
+    torch = torch_mod
+    from paper_2411_09809_amd import metrics, optim
+    L = gen.uniform_layout(800, 2000, extent=1 << 12, seed=6)
+    D = metrics.DeviceLayout.from_host(L)
+    x = D.x.clone().requires_grad_(True)
+    y = D.y.clone().requires_grad_(True)
+    loss, cnt = optim.CrossingAngleLengthLoss.apply(x, y, D.src, D.dst, IDEAL, 1.0, 1.0)
+    (3.0 * loss).backward()
+    _, gx, gy, c2 = optim.loss_grad(D.x, D.y, D.src, D.dst, IDEAL, 1.0, 1.0)
+    assert int(cnt) == int(c2)
+    assert x.grad.dtype == torch.float32
+    np.testing.assert_allclose(x.grad.cpu().numpy(), (3.0 * gx).float().cpu().numpy(), rtol=1e-6)
+    np.testing.assert_allclose(y.grad.cpu().numpy(), (3.0 * gy).float().cpu().numpy(), rtol=1e-6)
+
+
+def test_descent_steps_keep_exact_counts(torch_mod):
+    from paper_2411_09809_amd import metrics, optim
+    L = gen.uniform_layout(600, 1500, extent=1 << 12, seed=7)
+    D = metrics.DeviceLayout.from_host(L)
+    xs, ys, hist = optim.descend(D.x, D.y, D.src, D.dst, steps=8, step_size=4.0,
+                                 extent=1 << 12)
+    assert len(hist) == 8
+    xf, yf = xs.cpu().numpy(), ys.cpu().numpy()
+    assert (xf == np.round(xf)).all() and xf.min() >= 0 and xf.max() < 4096
+    c, _ = oracle.edge_crossing(xf, yf, L.src, L.dst)
+    assert metrics.edge_crossing(xs.contiguous(), ys.contiguous(), D.src, D.dst)[0] == c
+    assert min(h[0] for h in hist[1:]) < hist[0][0]      # the loss went down
