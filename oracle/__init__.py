@@ -43,6 +43,9 @@ def lib():
         L.oracle_min_angle.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _dp, _dp, _u64p]
         L.oracle_edge_length_variation.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _dp, _dp]
         L.oracle_segment_pair.argtypes = [_dp, C.c_double, C.POINTER(C.c_int), _dp]
+        L.oracle_crossing_angle_rows.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, C.c_double,
+                                                 _i64, _i64, _u64p, _dp]
+        L.oracle_node_occlusion_rows.argtypes = [_dp, _dp, _i64, C.c_double, _i64, _i64, _u64p]
         L.oracle_crossing_pairs.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64, _i64p]
         L.oracle_loss.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64, C.c_double,
                                   C.c_double, C.c_double, _dp]
@@ -145,6 +148,26 @@ def segment_pair(p, ideal_angle: float = 1.2217304763960306) -> tuple[int, float
     _check(lib().oracle_segment_pair(_p(a, _dp), float(ideal_angle), C.byref(kind),
                                      C.byref(ang)), "segment_pair")
     return int(kind.value), float(ang.value)
+
+
+def crossing_angle_rows(x, y, src, dst, ideal_angle: float, r0: int, r1: int):
+    """(crossings, sum of |ideal - a|/ideal) over pairs (e, f), r0 <= e < r1, e < f."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    cnt, dev = C.c_uint64(), C.c_double()
+    _check(lib().oracle_crossing_angle_rows(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                            _p(d, _i32p), s.shape[0], float(ideal_angle),
+                                            int(r0), int(r1), C.byref(cnt), C.byref(dev)),
+           "crossing_angle_rows")
+    return int(cnt.value), float(dev.value)
+
+
+def node_occlusion_rows(x, y, diameter: float, r0: int, r1: int) -> int:
+    """Occluded pairs (u, v), r0 <= u < r1, u < v."""
+    x, y = _f64(x), _f64(y)
+    out = C.c_uint64()
+    _check(lib().oracle_node_occlusion_rows(_p(x, _dp), _p(y, _dp), x.shape[0], float(diameter),
+                                            int(r0), int(r1), C.byref(out)), "node_occlusion_rows")
+    return int(out.value)
 
 
 def crossing_pairs(x, y, src, dst) -> np.ndarray:

@@ -515,3 +515,58 @@ int oracle_loss_grad(const double *x, const double *y, int64_t n, const int32_t 
     if (!gx || !gy) return 1;
     return loss_impl(x, y, n, src, dst, m, pairs, n_pairs, ideal, w_a, w_l, out_loss, gx, gy);
 }
+
+/* ------------------------------------------------ row slices of the sweeps
+ * The pairs (i, j) with r0 <= i < r1 and i < j (edges for crossings, nodes
+ * for occlusion): a slice of Algorithms 4/5 and 1, for checking one shard of
+ * a layout too large for the full brute force. */
+int oracle_crossing_angle_rows(const double *x, const double *y, int64_t n,
+                               const int32_t *src, const int32_t *dst, int64_t m,
+                               double ideal_angle, int64_t r0, int64_t r1,
+                               uint64_t *out_count, double *out_dev_sum) {
+    if (n < 0 || m < 0 || r0 < 0 || r1 < r0 || r1 > m || !out_count || !(ideal_angle > 0.0))
+        return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    const int64_t k = r1 - r0;
+    double *row_sum = (double *)calloc((size_t)(k > 0 ? k : 1), sizeof(double));
+    uint64_t count = 0;
+    #pragma omp parallel for schedule(dynamic, 4) reduction(+:count)
+    for (int64_t e = r0; e < r1; ++e) {
+        nsum acc = {0.0, 0.0};
+        for (int64_t f = e + 1; f < m; ++f) {
+            if (!edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) continue;
+            nsum_add(&acc, fabs(ideal_angle - crossing_angle(ix, iy, src[e], dst[e], src[f], dst[f])) /
+                               ideal_angle);
+            count += 1;
+        }
+        row_sum[e - r0] = nsum_get(&acc);
+    }
+    nsum tot = {0.0, 0.0};
+    for (int64_t i = 0; i < k; ++i) nsum_add(&tot, row_sum[i]);
+    free(row_sum); free(ix); free(iy);
+    *out_count = count;
+    if (out_dev_sum) *out_dev_sum = nsum_get(&tot);
+    return 0;
+}
+
+int oracle_node_occlusion_rows(const double *x, const double *y, int64_t n, double diameter,
+                               int64_t r0, int64_t r1, uint64_t *out_count) {
+    if (n < 0 || r0 < 0 || r1 < r0 || r1 > n || !out_count || !(diameter >= 0.0) || isinf(diameter))
+        return 1;
+    int64_t *ix, *iy;
+    int st = to_int_coords(x, y, n, &ix, &iy);
+    if (st) return st;
+    uint64_t total = 0;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+:total)
+    for (int64_t v = r0; v < r1; ++v)
+        for (int64_t u = v + 1; u < n; ++u) {
+            int64_t dx = ix[v] - ix[u], dy = iy[v] - iy[u];
+            if (less_than_square(dx * dx + dy * dy, diameter)) total += 1;
+        }
+    free(ix); free(iy);
+    *out_count = total;
+    return 0;
+}

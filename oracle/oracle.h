@@ -36,4 +36,10 @@ int oracle_loss_grad(const double *x, const double *y, int64_t n, const int32_t 
                      const int32_t *dst, int64_t m, const int64_t *pairs, int64_t n_pairs,
                      double ideal, double w_a, double w_l, double *out_loss, double *gx,
                      double *gy);
+int oracle_crossing_angle_rows(const double *x, const double *y, int64_t n,
+                               const int32_t *src, const int32_t *dst, int64_t m,
+                               double ideal_angle, int64_t r0, int64_t r1,
+                               uint64_t *out_count, double *out_dev_sum);
+int oracle_node_occlusion_rows(const double *x, const double *y, int64_t n, double diameter,
+                               int64_t r0, int64_t r1, uint64_t *out_count);
 #endif

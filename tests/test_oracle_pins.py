@@ -163,6 +163,51 @@ def test_oracle_matches_rational_brute_force_on_small_layouts(orc):
         assert abs(eca - beca) < 1e-7
 
 
+def test_row_slices_match_rational_brute_force(orc):
+    """Row slices (pairs (i, j), r0 <= i < r1, i < j) of the crossing and
+    occlusion sweeps against rational / integer brute force, and slices that
+    partition the rows sum to the whole."""
+    rng = np.random.default_rng(12)
+    for trial in range(12):
+        n = int(rng.integers(6, 14))
+        m = int(rng.integers(3, min(30, n * (n - 1) // 2)))
+        x = rng.integers(0, 5, size=n)
+        y = rng.integers(0, 5, size=n)
+        s, d = gen.distinct_random_edges(rng, n, m)
+        pts = [(int(a), int(b)) for a, b in zip(x, y)]
+        r0, r1 = sorted(int(v) for v in rng.integers(0, m + 1, size=2))
+        cnt = 0
+        dev = 0.0
+        for e in range(r0, r1):
+            for f in range(e + 1, m):
+                if {int(s[e]), int(d[e])} & {int(s[f]), int(d[f])}:
+                    continue
+                if rational_segment_relation(pts[s[e]], pts[d[e]], pts[s[f]], pts[d[f]]):
+                    cnt += 1
+                    dev += abs(IDEAL - acos_angle(pts[s[e]], pts[d[e]], pts[s[f]], pts[d[f]])) / IDEAL
+        c2, dev2 = orc.crossing_angle_rows(x, y, s, d, IDEAL, r0, r1)
+        assert c2 == cnt and abs(dev2 - dev) < 1e-7
+        diam = float(rng.choice([1.0, 1.5, 2.0, 2.9]))
+        q0, q1 = sorted(int(v) for v in rng.integers(0, n + 1, size=2))
+        occ = sum(1 for u in range(q0, q1) for v in range(u + 1, n)
+                  if (pts[u][0] - pts[v][0]) ** 2 + (pts[u][1] - pts[v][1]) ** 2 < diam * diam)
+        assert orc.node_occlusion_rows(x, y, diam, q0, q1) == occ
+    L = gen.uniform_layout(3000, 7000, extent=1 << 12, seed=5)
+    full = orc.crossing_angle(L.x, L.y, L.src, L.dst, IDEAL)
+    cuts = [0, 1, 999, 4321, 6999, 7000]
+    parts = [orc.crossing_angle_rows(L.x, L.y, L.src, L.dst, IDEAL, a, b)
+             for a, b in zip(cuts, cuts[1:])]
+    assert sum(p[0] for p in parts) == full[1]
+    assert sum(p[1] for p in parts) == pytest.approx(full[2], rel=1e-12)
+    cuts = [0, 5, 1500, 3000]
+    assert sum(orc.node_occlusion_rows(L.x, L.y, 40.0, a, b)
+               for a, b in zip(cuts, cuts[1:])) == orc.node_occlusion(L.x, L.y, 40.0)
+    with pytest.raises(Exception):
+        orc.crossing_angle_rows(L.x, L.y, L.src, L.dst, IDEAL, 10, 7001)
+    with pytest.raises(Exception):
+        orc.node_occlusion_rows(L.x, L.y, 40.0, 5, 4)
+
+
 # ---------------------------------------------------------------- closed forms
 
 @pytest.mark.parametrize("n", range(4, 11))
