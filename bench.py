@@ -26,11 +26,30 @@ sys.path.insert(0, ROOT)
 # (one FP64 FMA, FP32 or INT32 op per lane per clock; packed FP32 not used).
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # Algorithmic VALU lane-ops per edge pair of the crossing + crossing-angle
-# test: 4 orientation determinants (8 = 3 products-with-FMA pairs + 2 adds),
-# 2 sign products, 1 max, 2 classifying compares, 4 for the angle term.
+# test: 2 FMA each for the orientations of one end of either edge against the
+# other's line, 2 for the cross product of the directions (the other ends'
+# orientations follow by one add each), 2 muls and 2 adds for the two sign
+# products, 1 max, 2 classifying compares, and 4 for the angle term
+# (difference of line angles, fold, deviation, indicator FMA).
 OPS_PER_EDGE_PAIR = 17
 # per node pair of the occlusion test: 2 FMA + 1 compare
 OPS_PER_NODE_PAIR = 3
+# HBM bytes per launch of the crossing + angle sweep on this workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy: x2.000 and
+# x1.000), by (rows per thread, waves per SIMD).  Valid only for the kernel
+# source they were measured on (first 16 hex digits of its sha256).
+MEASURED_TRAFFIC = {"source_sha": "5c7a6b13cbc0925b",
+                    "bytes": {(4, 3): 351.2e6, (4, 4): 353.5e6, (2, 5): 588.8e6, (1, 7): 1131.4e6}}
+
+
+def measured_traffic(rows, waves):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2411_09809_amd", "csrc", "cross.hip")
+    with open(src, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    if sha != MEASURED_TRAFFIC["source_sha"]:
+        return None
+    return MEASURED_TRAFFIC["bytes"].get((rows, waves))
 
 
 def log(*a):
@@ -173,13 +192,14 @@ def main():
     torch.cuda.set_device(dev)
 
     if args.copy_probe:
+        # a plain elementwise copy of known size: reads and writes n bytes
         n = args.copy_probe << 20
-        a = torch.ones(n, dtype=torch.uint8, device=dev)
+        a = torch.ones(n // 4, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": n}))
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}))
         return
 
     L = gen.ba_cluster_layout(seed=args.seed)
@@ -251,7 +271,9 @@ def main():
                                "Gaussian clusters in [0,2^20)^2, diameter 64, ideal angle 70 deg",
                    "n_nodes": L.n_nodes, "n_edges": L.n_edges, "seed": args.seed},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": measured_traffic(variant["cross_angle"]["rows_per_thread"],
+                                                 variant["cross_angle"]["waves_per_simd"]),
                      "kernel": "cross_sweep_kernel (crossing + angle)",
                      "ops_per_pair": OPS_PER_EDGE_PAIR, "kernel_ms": cross_ms,
                      "variant": variant["cross_angle"]},

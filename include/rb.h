@@ -106,6 +106,31 @@ rb_status rb_crossing_angle(const float *x, const float *y, int64_t n_nodes,
                             uint64_t *out_count, double *out_dev_sum,
                             void *ws, size_t ws_bytes, void *stream);
 
+/* Shards of the two all-pairs sweeps, for splitting one layout across
+ * devices or processes (each computes its shards; the sums of the shard
+ * results are the full results) and for checking a slice of a large
+ * layout.  The rows of the pair triangle (edges for the crossing test,
+ * nodes for occlusion) are cut at the sweep's row-tile boundaries into
+ * n_shards contiguous ranges of about equal pair counts (later shards may be
+ * empty when there are more shards than tiles).  Shard k covers the pairs
+ * (i, j) with row_begin <= i < row_end and i < j < n; *out_row_begin and
+ * *out_row_end (host, may be NULL) report that range.  The ranges depend on
+ * the sweep variant in use (see rb_tune_*), so all participants must use the
+ * same one.
+ * rb_crossing_angle_shard: out_count device uint64[1] (crossings in the
+ *   shard), out_dev_sum device double[1] or NULL (sum of |ideal - a| / ideal).
+ * rb_node_occlusion_shard: out_count device uint64[1].                     */
+rb_status rb_crossing_angle_shard(const float *x, const float *y, int64_t n_nodes,
+                                  const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                  double ideal_angle, int64_t shard, int64_t n_shards,
+                                  uint64_t *out_count, double *out_dev_sum,
+                                  int64_t *out_row_begin, int64_t *out_row_end,
+                                  void *ws, size_t ws_bytes, void *stream);
+rb_status rb_node_occlusion_shard(const float *x, const float *y, int64_t n_nodes,
+                                  double diameter, int64_t shard, int64_t n_shards,
+                                  uint64_t *out_count, int64_t *out_row_begin,
+                                  int64_t *out_row_end, void *ws, size_t ws_bytes, void *stream);
+
 /* Minimum angle M_a (Section 2.1; Algorithm 2, Section 3.1.2): for each
  * node v of degree deg(v) >= 1, the directions v->u of its incident edges
  * as angles in [0, 2 pi), phi_min(v) = the smallest gap between
@@ -217,7 +242,9 @@ void rb_graph_destroy(rb_graph *graph);
  * launch times in *out_best_ms (host, may be NULL).  It synchronises
  * `stream`.  rb_tune_set forces a variant index (0 .. variants-1) for a size
  * class; rb_tune_query reports the rows and waves of the variant in use.
- * rb_tune_save / rb_tune_load write and read the table as text; the file
+ * rb_tune_save / rb_tune_load write and read the table as text (a load
+ * replaces the whole table: classes the file does not list return to the
+ * built-in defaults); the file
  * named by the environment variable RB_TUNE_CACHE is loaded on first use. */
 rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes,
                       const int32_t *src, const int32_t *dst, int64_t n_edges,

@@ -40,6 +40,11 @@ _SIGS = {
                                  C.c_int),
     "rb_validate_layout": ([_vp, _vp, _i64, _vp, _vp, _i64, C.POINTER(C.c_int32), _vp, _sz, _vp],
                            C.c_int),
+    "rb_crossing_angle_shard": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _i64, _i64, _vp, _vp,
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64), _vp, _sz, _vp],
+                                C.c_int),
+    "rb_node_occlusion_shard": ([_vp, _vp, _i64, _f64, _i64, _i64, _vp, C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int64), _vp, _sz, _vp], C.c_int),
     "rb_loss_grad": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, _f64, _vp, _vp, _vp, _vp, _vp,
                       _sz, _vp], C.c_int),
     "rb_autotune": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, C.c_int, C.POINTER(C.c_double),

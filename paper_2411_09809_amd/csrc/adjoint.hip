@@ -264,6 +264,7 @@ hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, con
         a.single = sweep_layout(n_edges, rows, 0, 0);
         a.n_layouts = 1;
         a.n_units = sweep_units(n_edges, rows);
+        a.unit_base = 0;
         const int grid = (int)std::min<int64_t>(a.n_units, cross_grid(v, true));
         CrossPartial *part = (CrossPartial *)(w + L.partial);
         RB_TRY(launch_cross_sweep(v, true, rec, a, grid, ideal, part, st));

@@ -207,6 +207,7 @@ rb_status rb_node_occlusion(const float *x, const float *y, int64_t n_nodes, dou
     a.single = sweep_layout(n_nodes, rows, 0, 0);
     a.n_layouts = 1;
     a.n_units = sweep_units(n_nodes, rows);
+    a.unit_base = 0;
     const int grid = (int)std::min<int64_t>(a.n_units, occl_grid(v));
     hipError_t e = launch_node_prep(x, y, n_nodes, L.n_node_pad, occlusion_threshold(diameter),
                                     rec, st);
@@ -240,6 +241,7 @@ static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes
     a.single = sweep_layout(n_edges, rows, 0, 0);
     a.n_layouts = 1;
     a.n_units = sweep_units(n_edges, rows);
+    a.unit_base = 0;
     const int grid = (int)std::min<int64_t>(a.n_units, cross_grid(v, angle));
     hipError_t e = launch_edge_prep(x, y, src, dst, n_nodes, n_edges, L.n_edge_pad, rec, st);
     if (e != hipSuccess) return hip_fail(e, "edge_prep launch");
@@ -250,6 +252,122 @@ static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes
     e = launch_cross_finalize(part, grid, ideal, (unsigned long long *)out_count,
                               (unsigned long long *)out_proper, out_metric, out_dev_sum, st);
     if (e != hipSuccess) return hip_fail(e, "crossing finalize launch");
+    return RB_OK;
+}
+
+// Tile-aligned, equal-work shard k of n of a single-layout unit list:
+// row tiles [t_k, t_k+1) where t_k is the first tile whose preceding units
+// reach ceil(k U / n).
+static void shard_tiles(int64_t n_items, int rows, int64_t k, int64_t n, int64_t *tile_b,
+                        int64_t *tile_e, int64_t *unit_b, int64_t *unit_e) {
+    const SweepLayout l = sweep_layout(n_items, rows, 0, 0);
+    auto before = [&](int64_t I) {
+        return I * l.n_chunks - (int64_t)rows * I * (I - 1) / 2;
+    };
+    const int64_t U = before(l.n_row_tiles);
+    auto first_tile = [&](int64_t q) {   // smallest I with before(I) >= ceil(q U / n)
+        const int64_t target = (int64_t)(((__int128)q * U + n - 1) / n);
+        int64_t lo = 0, hi = l.n_row_tiles;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (before(mid) >= target) hi = mid;
+            else lo = mid + 1;
+        }
+        return lo;
+    };
+    *tile_b = first_tile(k);
+    *tile_e = first_tile(k + 1);
+    *unit_b = before(*tile_b);
+    *unit_e = before(*tile_e);
+}
+
+rb_status rb_crossing_angle_shard(const float *x, const float *y, int64_t n_nodes,
+                                  const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                  double ideal_angle, int64_t shard, int64_t n_shards,
+                                  uint64_t *out_count, double *out_dev_sum, int64_t *out_row_begin,
+                                  int64_t *out_row_end, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (!out_count) return fail(RB_EINVAL, "out_count is NULL");
+    if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
+        return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
+    if (n_shards < 1 || shard < 0 || shard >= n_shards)
+        return fail(RB_EINVAL, "need 0 <= shard < n_shards");
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    EdgeRec *rec = (EdgeRec *)(w + L.edge_rec);
+    CrossPartial *part = (CrossPartial *)(w + L.partial);
+    const int v = tuned_variant(1, false, n_edges);
+    const int rows = cross_variant(v).rows;
+    int64_t tb, te, ub, ue;
+    shard_tiles(n_edges, rows, shard, n_shards, &tb, &te, &ub, &ue);
+    const int64_t R = (int64_t)kBlock * rows;
+    if (out_row_begin) *out_row_begin = std::min<int64_t>(tb * R, n_edges);
+    if (out_row_end) *out_row_end = std::min<int64_t>(te * R, n_edges);
+    SweepArgs a;
+    a.table = nullptr;
+    a.single = sweep_layout(n_edges, rows, 0, 0);
+    a.n_layouts = 1;
+    a.n_units = ue - ub;
+    a.unit_base = ub;
+    const int grid = (int)std::min<int64_t>(a.n_units, cross_grid(v, true));
+    hipError_t e = launch_edge_prep(x, y, src, dst, n_nodes, n_edges, L.n_edge_pad, rec, st);
+    if (e != hipSuccess) return hip_fail(e, "edge_prep launch");
+    if (grid > 0) {
+        e = launch_cross_sweep(v, true, rec, a, grid, ideal_angle, part, st);
+        if (e != hipSuccess) return hip_fail(e, "crossing sweep launch");
+    }
+    e = launch_cross_finalize(part, grid, ideal_angle, (unsigned long long *)out_count, nullptr,
+                              nullptr, out_dev_sum, st);
+    if (e != hipSuccess) return hip_fail(e, "crossing finalize launch");
+    return RB_OK;
+}
+
+rb_status rb_node_occlusion_shard(const float *x, const float *y, int64_t n_nodes,
+                                  double diameter, int64_t shard, int64_t n_shards,
+                                  uint64_t *out_count, int64_t *out_row_begin,
+                                  int64_t *out_row_end, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_sizes(n_nodes, 0);
+    if (s) return s;
+    if (n_nodes > 0 && (!x || !y)) return fail(RB_EINVAL, "x or y is NULL");
+    if (!out_count) return fail(RB_EINVAL, "out_count is NULL");
+    if (!(diameter >= 0.0) || !std::isfinite(diameter))
+        return fail(RB_EINVAL, "diameter must be finite and >= 0");
+    if (n_shards < 1 || shard < 0 || shard >= n_shards)
+        return fail(RB_EINVAL, "need 0 <= shard < n_shards");
+    WsLayout L;
+    if ((s = check_ws(ws, ws_bytes, n_nodes, 0, &L))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char *w = (char *)ws;
+    NodeRec *rec = (NodeRec *)(w + L.node_rec);
+    OcclPartial *part = (OcclPartial *)(w + L.partial);
+    const int v = tuned_variant(2, false, n_nodes);
+    const int rows = occl_variant(v).rows;
+    int64_t tb, te, ub, ue;
+    shard_tiles(n_nodes, rows, shard, n_shards, &tb, &te, &ub, &ue);
+    const int64_t R = (int64_t)kBlock * rows;
+    if (out_row_begin) *out_row_begin = std::min<int64_t>(tb * R, n_nodes);
+    if (out_row_end) *out_row_end = std::min<int64_t>(te * R, n_nodes);
+    SweepArgs a;
+    a.table = nullptr;
+    a.single = sweep_layout(n_nodes, rows, 0, 0);
+    a.n_layouts = 1;
+    a.n_units = ue - ub;
+    a.unit_base = ub;
+    const int grid = (int)std::min<int64_t>(a.n_units, occl_grid(v));
+    hipError_t e = launch_node_prep(x, y, n_nodes, L.n_node_pad, occlusion_threshold(diameter),
+                                    rec, st);
+    if (e != hipSuccess) return hip_fail(e, "node_prep launch");
+    if (grid > 0) {
+        e = launch_occl_sweep(v, rec, a, grid, part, st);
+        if (e != hipSuccess) return hip_fail(e, "occlusion sweep launch");
+    }
+    e = launch_occl_finalize(part, grid, (unsigned long long *)out_count, st);
+    if (e != hipSuccess) return hip_fail(e, "occlusion finalize launch");
     return RB_OK;
 }
 
@@ -418,6 +536,7 @@ rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes, const int
             a.single = sweep_layout(n, rows, 0, 0);
             a.n_layouts = 1;
             a.n_units = sweep_units(n, rows);
+            a.unit_base = 0;
             const int grid = (int)std::min<int64_t>(a.n_units, occl ? occl_grid(v) : cross_grid(v, angle));
             float ms = 0.f;
             if (occl)

@@ -278,6 +278,7 @@ hipError_t enqueue_cross(const rb_batch *b, char *w, const BatchIO &io, bool wit
     a.single = SweepLayout{0, 0, 0, 0};
     a.n_layouts = b->B;
     a.n_units = U;
+    a.unit_base = 0;
     RB_TRY(launch_cross_sweep(b->cross_var, true, (const EdgeRec *)(w + b->o_erec), a, grid,
                               io.ideal, part, st));
     if (!with_finalize) return hipSuccess;
@@ -297,6 +298,7 @@ hipError_t enqueue_occl(const rb_batch *b, char *w, const BatchIO &io, bool with
     a.single = SweepLayout{0, 0, 0, 0};
     a.n_layouts = b->B;
     a.n_units = U;
+    a.unit_base = 0;
     RB_TRY(launch_occl_sweep(b->occl_var, (const NodeRec *)(w + b->o_nrec), a, grid, part, st));
     if (!with_finalize) return hipSuccess;
     hipLaunchKernelGGL(batch_occl_finalize_kernel, dim3(grid_for(b->B)), dim3(256), 0, st, part,

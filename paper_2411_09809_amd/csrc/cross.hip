@@ -127,8 +127,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
 
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t u_begin = block_first_unit(a.n_units, G, b);
-    const int64_t u_end = block_first_unit(a.n_units, G, b + 1);
+    const int64_t u_begin = a.unit_base + block_first_unit(a.n_units, G, b);
+    const int64_t u_end = a.unit_base + block_first_unit(a.n_units, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
 

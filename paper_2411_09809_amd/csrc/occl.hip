@@ -44,8 +44,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
     __shared__ unsigned long long red[kBlock / 64];
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t u_begin = block_first_unit(a.n_units, G, b);
-    const int64_t u_end = block_first_unit(a.n_units, G, b + 1);
+    const int64_t u_begin = a.unit_base + block_first_unit(a.n_units, G, b);
+    const int64_t u_end = a.unit_base + block_first_unit(a.n_units, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
 
     int64_t L = 0;

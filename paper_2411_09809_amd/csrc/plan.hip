@@ -66,11 +66,15 @@ void load_locked(const char *path) {
     fclose(f);
 }
 
-void init_locked() {
-    if (g_tab.init) return;
+void defaults_locked() {
     for (int k = 0; k < kKinds; ++k)
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < kClasses; ++c) g_tab.v[k][b][c] = kDefault[k];
+}
+
+void init_locked() {
+    if (g_tab.init) return;
+    defaults_locked();
     g_tab.init = true;
     const char *path = getenv("RB_TUNE_CACHE");
     if (path && *path) load_locked(path);
@@ -108,6 +112,7 @@ bool load_tuning(const char *path) {
     FILE *f = fopen(path, "r");
     if (!f) return false;
     fclose(f);
+    defaults_locked();
     load_locked(path);
     return true;
 }

@@ -71,7 +71,8 @@ struct SweepArgs {
     const SweepLayout *table;
     SweepLayout single;
     int64_t n_layouts;
-    int64_t n_units;
+    int64_t n_units;        // units this launch covers ...
+    int64_t unit_base;      // ... starting at this global unit (single layout only)
 };
 
 // Sweep kernel variants: rows per thread and minimum waves per SIMD.

@@ -149,6 +149,41 @@ def edge_length_variation(x, y, src, dst, *, async_: bool = False):
     return float(m), float(mu)
 
 
+def crossing_angle_shard(x, y, src, dst, shard: int, n_shards: int,
+                         ideal_angle: float = IDEAL_ANGLE):
+    """(crossings, sum of |ideal - a|/ideal, row_begin, row_end) of shard k
+    of n of the edge-pair sweep: pairs (e, f), row_begin <= e < row_end, e < f."""
+    import ctypes as C
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    out = _out(2, torch.float64, x.device)
+    ws = workspace(x.numel(), src.numel(), x.device)
+    w, wb = _ws_args(ws)
+    rb, re_ = C.c_int64(), C.c_int64()
+    p = _ptr(out)
+    check(lib().rb_crossing_angle_shard(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst),
+                                        src.numel(), float(ideal_angle), int(shard), int(n_shards),
+                                        p, p + 8, C.byref(rb), C.byref(re_), w, wb,
+                                        _stream(x.device)), "rb_crossing_angle_shard")
+    vals = out.cpu()
+    return int(vals.view(torch.int64)[0]), float(vals[1]), rb.value, re_.value
+
+
+def node_occlusion_shard(x, y, diameter: float, shard: int, n_shards: int):
+    """(occluded pairs, row_begin, row_end) of shard k of n of the node-pair
+    sweep: pairs (u, v), row_begin <= u < row_end, u < v."""
+    import ctypes as C
+    _check_coords(x, y)
+    out = _out(1, torch.int64, x.device)
+    ws = workspace(x.numel(), 0, x.device)
+    w, wb = _ws_args(ws)
+    rb, re_ = C.c_int64(), C.c_int64()
+    check(lib().rb_node_occlusion_shard(_ptr(x), _ptr(y), x.numel(), float(diameter), int(shard),
+                                        int(n_shards), _ptr(out), C.byref(rb), C.byref(re_), w,
+                                        wb, _stream(x.device)), "rb_node_occlusion_shard")
+    return int(out.item()), rb.value, re_.value
+
+
 def validate_layout(x, y, src, dst) -> int:
     """Bit set of violated preconditions (0 when the layout is valid)."""
     import ctypes as C
