@@ -32,14 +32,15 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # products, 1 max, 2 classifying compares, and 4 for the angle term
 # (difference of line angles, fold, deviation, indicator FMA).
 OPS_PER_EDGE_PAIR = 17
-# per node pair of the occlusion test: 2 FMA + 1 compare
+# per node pair of the occlusion test: 2 FMA + 1 max (the exact count runs
+# only for the rare chunks that hold an occluding pair)
 OPS_PER_NODE_PAIR = 3
 # HBM bytes per launch of the crossing + angle sweep on this workload, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy: x2.000 and
 # x1.000), by (rows per thread, waves per SIMD).  Valid only for the kernel
 # source they were measured on (first 16 hex digits of its sha256).
-MEASURED_TRAFFIC = {"source_sha": "5c7a6b13cbc0925b",
-                    "bytes": {(4, 3): 351.2e6, (4, 4): 353.5e6, (2, 5): 588.8e6, (1, 7): 1131.4e6}}
+MEASURED_TRAFFIC = {"source_sha": "9f52ec281cb3e492",
+                    "bytes": {(4, 3): 345.4e6, (4, 4): 346.6e6, (2, 5): 622.1e6, (1, 7): 1134.4e6}}
 
 
 def measured_traffic(rows, waves):
@@ -161,6 +162,49 @@ def bench_adjoint(torch, reps: int, gd_steps: int):
     return out
 
 
+def bench_largest(torch):
+    """The 1,000,000-node / 3,000,000-edge power-law layout: one pass of each
+    sweep (4.5e12 edge pairs, 5.0e11 node pairs) plus the two small metrics,
+    timed with the library's launch events."""
+    import ctypes as C
+    from paper_2411_09809_amd import _lib, gen, metrics
+
+    L = gen.powerlaw_layout(seed=0)
+    D = metrics.DeviceLayout.from_host(L)
+    R = _lib.lib()
+    pairs = math.comb(L.n_edges, 2)
+    node_pairs = math.comb(L.n_nodes, 2)
+    torch.cuda.synchronize()
+    R.rb_timing_reset()
+    R.rb_timing_enable(1)
+    t0 = time.perf_counter()
+    occ = metrics.node_occlusion(D.x, D.y, D.diameter, async_=True)
+    ang = metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True)
+    ma = metrics.min_angle(D.x, D.y, D.src, D.dst, async_=True)
+    ml = metrics.edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    R.rb_timing_enable(0)
+    ms, n = C.c_double(), C.c_int64()
+    _lib.check(R.rb_timing_read(0, C.byref(ms), C.byref(n)), "rb_timing_read")
+    cross_ms = ms.value
+    _lib.check(R.rb_timing_read(1, C.byref(ms), C.byref(n)), "rb_timing_read")
+    occl_ms = ms.value
+    R.rb_timing_reset()
+    ang = ang.cpu()
+    return {"workload": f"power-law (gamma 2.3, max degree 10,000) |V|={L.n_nodes} |E|={L.n_edges}, "
+                        "hub-heavy clusters in [0,2^20)^2, diameter 16",
+            "edge_pairs": pairs, "node_pairs": node_pairs, "step_s": total,
+            "edge_pair_sweep_ms": cross_ms, "edge_pair_sweep_pairs_per_s": pairs / (cross_ms * 1e-3),
+            "edge_pair_sweep_valu_frac":
+                OPS_PER_EDGE_PAIR * pairs / (cross_ms * 1e-3) / VALU_PEAK_OPS,
+            "node_pair_sweep_ms": occl_ms,
+            "node_pair_sweep_pairs_per_s": node_pairs / (occl_ms * 1e-3),
+            "edge_crossings": int(ang.view(torch.int64)[1]), "crossing_angle": float(ang[0]),
+            "node_occlusions": int(occ.item()), "min_angle": float(ma[0]),
+            "edge_length_variation": float(ml[0])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +216,8 @@ def main():
                     help="edge pairs in the CPU-baseline sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-layout comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward part")
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the single pass over the 1M-node / 3M-edge layout")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -290,6 +336,9 @@ def main():
     if not args.no_adjoint:
         log("[bench] forward + adjoint ...")
         rec["fwd_bwd"] = bench_adjoint(torch, max(3, args.steps // 2), 100)
+    if not args.no_largest:
+        log("[bench] largest layout (1M nodes, 3M edges) ...")
+        rec["largest"] = bench_largest(torch)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(L, args.cpu_pairs)

@@ -33,27 +33,6 @@ __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
     return I * nC - (int64_t)K * I * (I - 1) / 2;
 }
 
-// touching pairs: same decision as the forward sweep (incident pairs never
-// count; both products zero need overlapping bounding boxes)
-__device__ __noinline__ bool touching_pair_b(double rx, double ry, double rdx, double rdy,
-                                             double rc, int2 rid, double fx, double fy,
-                                             double fdx, double fdy, double fc, int2 fid) {
-    const double o1 = fma(-rdy, fx, fma(rdx, fy, -rc));
-    const double o3 = fma(-fdy, rx, fma(fdx, ry, -fc));
-    const double cr = fma(-rdy, fdx, rdx * fdy);
-    const double p12 = o1 * (o1 + cr), p34 = o3 * (o3 - cr);
-    const bool incident = (rid.x == fid.x) | (rid.x == fid.y) | (rid.y == fid.x) | (rid.y == fid.y);
-    bool ok = fmin(p12, p34) < 0.0;
-    if (!ok) {
-        const double ax0 = fmin(rx, rx + rdx), ax1 = fmax(rx, rx + rdx);
-        const double ay0 = fmin(ry, ry + rdy), ay1 = fmax(ry, ry + rdy);
-        const double bx0 = fmin(fx, fx + fdx), bx1 = fmax(fx, fx + fdx);
-        const double by0 = fmin(fy, fy + fdy), by1 = fmax(fy, fy + fdy);
-        ok = (fmax(ax0, bx0) <= fmin(ax1, bx1)) && (fmax(ay0, by0) <= fmin(ay1, by1));
-    }
-    return ok && !incident;
-}
-
 template <int K, bool DIAG>
 __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                                               const int2 *__restrict__ rid,
@@ -68,6 +47,8 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
         const double cDX = col[j].dx, cDY = col[j].dy;
         const double cC = col[j].c, cTH = col[j].th;
         int colsum = 0;
+        bool zr[K];
+        uint64_t any_zero = 0;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const double o1 = fma(-rDY[r], cX, fma(rDX[r], cY, -rC[r]));
@@ -77,26 +58,43 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             const double p34 = o3 * (o3 - cr);
             const double m = fmax(p12, p34);
             const bool in_tri = !DIAG || (col0 + j > row0 + (int64_t)r * kBlock);
-            bool closed = (m < 0.0) & in_tri;
-            const bool zero = (m == 0.0) & in_tri;
+            const bool closed = (m < 0.0) & in_tri;
+            zr[r] = (m == 0.0) & in_tri;
             const double u = fabs(rTH[r] - cTH) - kHalfPi;
             const double v = angc + fabs(u);
             const double dot = fma(rDX[r], cDX, rDY[r] * cDY);
             const double s = (v * dot) * cr;
-            if (__builtin_expect(__builtin_amdgcn_ballot_w64(zero) != 0, 0)) {
-                if (zero) {
-                    double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC;
-                    __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc));
-                    const int2 fid = make_int2(col[j].s, col[j].t);
-                    closed = touching_pair_b(rX[r], rY[r], rDX[r], rDY[r], rC[r],
-                                             rid[r * kBlock + tid], fx, fy, fdx, fdy, fc, fid);
-                }
-            }
             const bool pos = closed & (s > 0.0);
             const bool neg = closed & (s < 0.0);
             kr[r] += (int)pos - (int)neg;
             colsum += (int)__popcll(__builtin_amdgcn_ballot_w64(pos)) -
                       (int)__popcll(__builtin_amdgcn_ballot_w64(neg));
+            any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
+        }
+        if (__builtin_expect(any_zero != 0, 0)) {
+            // pairs with an end point on the other edge's line
+            double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC, fth = cTH;
+            __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc), "+v"(fth));
+            const int2 fid = make_int2(col[j].s, col[j].t);
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                bool pos = false, neg = false;
+                if (zr[r]) {
+                    double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
+                    __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
+                    if (dev::touching_pair(ex, ey, edx, edy, ec, rid[r * kBlock + tid], fx, fy,
+                                           fdx, fdy, fc, fid)) {
+                        const double cr = fma(-edy, fdx, edx * fdy);
+                        const double v = angc + fabs(fabs(rTH[r] - fth) - kHalfPi);
+                        const double s = (v * fma(edx, fdx, edy * fdy)) * cr;
+                        pos = s > 0.0;
+                        neg = s < 0.0;
+                    }
+                }
+                kr[r] += (int)pos - (int)neg;
+                colsum += (int)__popcll(__builtin_amdgcn_ballot_w64(pos)) -
+                          (int)__popcll(__builtin_amdgcn_ballot_w64(neg));
+            }
         }
         if (lane == 0) colk[wave * kChunk + j] = colsum;
     }

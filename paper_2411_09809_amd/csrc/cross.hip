@@ -25,6 +25,7 @@
 // The crossing angle uses the per-edge line angles th in [0, pi):
 //   a = pi/2 - | |th_e - th_f| - pi/2 |,  dev = |ideal - a|
 // (a = 0 for parallel lines and zero-length edges).
+#include "rb_device.h"
 #include "rb_internal.h"
 
 namespace rb {
@@ -42,28 +43,6 @@ __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
     return I * nC - (int64_t)K * I * (I - 1) / 2;
 }
 
-// Rare path for one pair: both products <= 0 and at least one is zero.  The
-// orientations are recomputed here from laundered copies of the column
-// values, which keeps this arithmetic out of the common path.
-__device__ __noinline__ bool touching_pair(double rx, double ry, double rdx, double rdy, double rc,
-                                           int2 rid, double fx, double fy, double fdx,
-                                           double fdy, double fc, int2 fid) {
-    const double o1 = fma(-rdy, fx, fma(rdx, fy, -rc));
-    const double o3 = fma(-fdy, rx, fma(fdx, ry, -fc));
-    const double cr = fma(-rdy, fdx, rdx * fdy);
-    const double p12 = o1 * (o1 + cr), p34 = o3 * (o3 - cr);
-    const bool incident = (rid.x == fid.x) | (rid.x == fid.y) | (rid.y == fid.x) | (rid.y == fid.y);
-    bool ok = fmin(p12, p34) < 0.0;
-    if (!ok) {
-        const double ax0 = fmin(rx, rx + rdx), ax1 = fmax(rx, rx + rdx);
-        const double ay0 = fmin(ry, ry + rdy), ay1 = fmax(ry, ry + rdy);
-        const double bx0 = fmin(fx, fx + fdx), bx1 = fmax(fx, fx + fdx);
-        const double by0 = fmin(fy, fy + fdy), by1 = fmax(fy, fy + fdy);
-        ok = (fmax(ax0, bx0) <= fmin(ax1, bx1)) && (fmax(ay0, by0) <= fmin(ay1, by1));
-    }
-    return ok && !incident;
-}
-
 template <int K, bool ANGLE, bool DIAG>
 __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
                                             const int2 *__restrict__ rid,
@@ -79,6 +58,10 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
         const double cDX = col[j].dx, cDY = col[j].dy;
         const double cC = col[j].c;
         const double cTH = ANGLE ? col[j].th : 0.0;
+        // the K rows are independent straight-line work; one wave-uniform
+        // branch per column takes every row's rare pairs
+        bool zr[K];
+        uint64_t any_zero = 0;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const double o1 = fma(-rDY[r], cX, fma(rDX[r], cY, -rC[r]));
@@ -89,26 +72,32 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
             const double m = fmax(p12, p34);
             const bool in_tri = !DIAG || (col0 + j > row0 + (int64_t)r * kBlock);
             const bool prop = (m < 0.0) & in_tri;
-            const bool zero = (m == 0.0) & in_tri;
+            zr[r] = (m == 0.0) & in_tri;
             n_proper += popc_ballot(prop);
-            double v = 0.0;
             if (ANGLE) {
                 const double u = fabs(rTH[r] - cTH) - kHalfPi;
-                v = angc + fabs(u);
+                const double v = angc + fabs(u);
                 acc = fma(prop ? 1.0 : 0.0, fabs(v), acc);
             }
-            if (__builtin_expect(__builtin_amdgcn_ballot_w64(zero) != 0, 0)) {
+            any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
+        }
+        if (__builtin_expect(any_zero != 0, 0)) {
+            double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC, fth = cTH;
+            __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc), "+v"(fth));
+            const int2 fid = make_int2(col[j].s, col[j].t);
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
                 bool ok = false;
-                if (zero) {
-                    double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC;
-                    __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc));
-                    const int2 fid = make_int2(col[j].s, col[j].t);
-                    ok = touching_pair(rX[r], rY[r], rDX[r], rDY[r], rC[r], rid[r * kBlock + tid],
-                                       fx, fy, fdx, fdy, fc, fid);
+                if (zr[r]) {
+                    double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
+                    __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
+                    ok = dev::touching_pair(ex, ey, edx, edy, ec, rid[r * kBlock + tid], fx, fy, fdx,
+                                       fdy, fc, fid);
                     if (ANGLE && ok) {
                         // parallel lines or a zero-length edge: a = 0
-                        const double crs = fma(-rDY[r], fdx, rDX[r] * fdy);
-                        acc += (crs == 0.0) ? ideal : fabs(v);
+                        const double crs = fma(-edy, fdx, edx * fdy);
+                        const double u = fabs(rTH[r] - fth) - kHalfPi;
+                        acc += (crs == 0.0) ? ideal : fabs(angc + fabs(u));
                     }
                 }
                 n_touch += popc_ballot(ok);

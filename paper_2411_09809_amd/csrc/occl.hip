@@ -6,8 +6,13 @@
 // triangle of each layout, by a persistent grid taking equal contiguous
 // ranges of the unit list of all layouts.  The exact integer test
 // |p_u - p_v|^2 <= T (T = largest integer < d^2) is evaluated as
-// g = x_u x_v + (y_u y_v + q_v) >= h_u: two fused multiply-adds and one
-// compare per pair (see NodeRec).
+// g = x_u x_v + (y_u y_v + q_v) >= h_u (see NodeRec).
+//
+// Occluding pairs are rare in any readable layout, so a chunk is first swept
+// keeping only each row's largest g: two fused multiply-adds and one max per
+// pair, and no per-pair scalar work (the CU's single scalar unit would
+// otherwise bound the sweep).  Only when some row's maximum reaches its h
+// is the chunk swept again, counting pairs exactly.
 #include "rb_internal.h"
 
 namespace rb {
@@ -18,7 +23,7 @@ __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
 }
 
 template <int K, bool DIAG>
-__device__ __forceinline__ uint32_t occl_chunk(const NodeRec *__restrict__ col,
+__device__ __forceinline__ uint32_t occl_count(const NodeRec *__restrict__ col,
                                                const double (&rX)[K], const double (&rY)[K],
                                                const double (&rH)[K], int64_t row0,
                                                int64_t col0) {
@@ -35,6 +40,37 @@ __device__ __forceinline__ uint32_t occl_chunk(const NodeRec *__restrict__ col,
         }
     }
     return n;
+}
+
+// max of two doubles as one instruction: the compiler's fmax also quiets NaN
+// inputs, which costs an extra instruction per pair for the loop-carried
+// maximum (no NaN reaches this sweep)
+__device__ __forceinline__ double max2(double a, double b) {
+    double r;
+    __asm__("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t occl_chunk(const NodeRec *__restrict__ col,
+                                               const double (&rX)[K], const double (&rY)[K],
+                                               const double (&rH)[K], int64_t row0,
+                                               int64_t col0) {
+    double gmax[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) gmax[r] = -HUGE_VAL;
+#pragma unroll 2
+    for (int j = 0; j < kChunk; ++j) {
+        const double cX = col[j].x, cY = col[j].y, cQ = col[j].q;
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            gmax[r] = max2(gmax[r], fma(rX[r], cX, fma(rY[r], cY, cQ)));
+    }
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < K; ++r) any |= gmax[r] >= rH[r];
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(any) == 0, 1)) return 0;
+    return occl_count<K, false>(col, rX, rY, rH, row0, col0);
 }
 
 template <int K, int WAVES, bool BATCH>
@@ -102,8 +138,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
         col[tid] = rec[lay.rec_off + c * kChunk + tid];
         __syncthreads();
         const int64_t row0 = I * R + tid, col0 = c * kChunk;
-        if (c < (I + 1) * K) tot += occl_chunk<K, true>(col, rX, rY, rH, row0, col0);
-        else tot += occl_chunk<K, false>(col, rX, rY, rH, row0, col0);
+        if (c < (I + 1) * K) tot += occl_count<K, true>(col, rX, rY, rH, row0, col0);
+        else tot += occl_chunk<K>(col, rX, rY, rH, row0, col0);
         ++seg_units;
         if (++c == lay.n_chunks) {
             ++I;

@@ -35,6 +35,39 @@ __device__ __forceinline__ double dv_of(double phi_min, uint32_t deg) {
     return (ideal - phi_min) / ideal;
 }
 
+// Rarest case of the crossing test: both orientation products are zero and
+// the edges share no end id (collinear pieces, or an end point of each edge
+// on the other's line): closed segments then cross iff their bounding boxes
+// meet.  Kept out of line: it runs for a handful of pairs per layout.
+__device__ __noinline__ inline bool boxes_meet(double rx, double ry, double rdx, double rdy,
+                                               double fx, double fy, double fdx, double fdy) {
+    const double ax0 = fmin(rx, rx + rdx), ax1 = fmax(rx, rx + rdx);
+    const double ay0 = fmin(ry, ry + rdy), ay1 = fmax(ry, ry + rdy);
+    const double bx0 = fmin(fx, fx + fdx), bx1 = fmax(fx, fx + fdx);
+    const double by0 = fmin(fy, fy + fdy), by1 = fmax(fy, fy + fdy);
+    return (fmax(ax0, bx0) <= fmin(ax1, bx1)) && (fmax(ay0, by0) <= fmin(ay1, by1));
+}
+
+// Decision for an edge pair (row edge P + t D, column edge F + s G, with line
+// constants c = D x P) whose larger orientation product is zero.  Pairs
+// sharing an end id are never crossings (incident edges always have both
+// products zero); otherwise a negative product means the segments meet at an
+// end point of one of them, and two zero products need the box test.
+// Callers pass register copies the compiler cannot see through, which keeps
+// this arithmetic out of their common path.
+__device__ __forceinline__ bool touching_pair(double rx, double ry, double rdx, double rdy,
+                                              double rc, int2 rid, double fx, double fy,
+                                              double fdx, double fdy, double fc, int2 fid) {
+    const bool incident = (rid.x == fid.x) | (rid.x == fid.y) | (rid.y == fid.x) | (rid.y == fid.y);
+    const double o1 = fma(-rdy, fx, fma(rdx, fy, -rc));
+    const double o3 = fma(-fdy, rx, fma(fdx, ry, -fc));
+    const double cr = fma(-rdy, fdx, rdx * fdy);
+    const double p12 = o1 * (o1 + cr), p34 = o3 * (o3 - cr);
+    bool ok = !incident && fmin(p12, p34) < 0.0;
+    if (!incident && p12 == 0.0 && p34 == 0.0) ok = boxes_meet(rx, ry, rdx, rdy, fx, fy, fdx, fdy);
+    return ok;
+}
+
 // sum over the block (blockDim.x a power of two <= 1024); sh has blockDim.x slots
 __device__ __forceinline__ double block_sum(double v, double *sh) {
     const int tid = threadIdx.x;
