@@ -14,7 +14,10 @@
 // the symmetric choice at those kinks.  The backward sweep therefore only
 // accumulates integers: k_e = sum_f q_ef per edge (rows in registers,
 // columns via wave popcounts and LDS, then integer atomics: exact and
-// order-independent).  A per-edge pass applies the chain rule in double:
+// order-independent).  The k_e depend neither on |S| nor on the loss, so the
+// same sweep also accumulates the forward terms of every pair (crossing
+// count, sum of |ideal - a|): one pass over the pair triangle gives both.
+// A per-edge pass applies the chain rule in double:
 //     dL/dD_e = w_a k_e / (ideal |S|) (-dy, dx) / l^2 + w_l dM_l/dl_e (dx, dy) / l,
 //     dM_l/dl_e = ((l_e - mu)/(N s mu) - s/(N mu^2)) / sqrt(N - 1)   (s: population
 //     spread of the lengths), and scatters +dL/dD_e to the head node and
@@ -40,7 +43,9 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                                               const double (&rY)[K], const double (&rDX)[K],
                                               const double (&rDY)[K], const double (&rC)[K],
                                               const double (&rTH)[K], int (&kr)[K], int tid,
-                                              int64_t row0, int64_t col0, double angc) {
+                                              int64_t row0, int64_t col0, double ideal,
+                                              double angc, uint32_t &n_proper,
+                                              uint32_t &n_touch, double &acc) {
     const int wave = tid >> 6, lane = tid & 63;
     for (int j = 0; j < kChunk; ++j) {
         const double cX = col[j].x, cY = col[j].y;
@@ -69,6 +74,9 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             kr[r] += (int)pos - (int)neg;
             colsum += (int)__popcll(__builtin_amdgcn_ballot_w64(pos)) -
                       (int)__popcll(__builtin_amdgcn_ballot_w64(neg));
+            // forward terms of the same pair: the count and |ideal - a|
+            n_proper += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(closed));
+            acc = fma(closed ? 1.0 : 0.0, fabs(v), acc);
             any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
         }
         if (__builtin_expect(any_zero != 0, 0)) {
@@ -78,19 +86,23 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             const int2 fid = make_int2(col[j].s, col[j].t);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                bool pos = false, neg = false;
+                bool pos = false, neg = false, ok = false;
                 if (zr[r]) {
                     double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
                     __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
-                    if (dev::touching_pair(ex, ey, edx, edy, ec, rid[r * kBlock + tid], fx, fy,
-                                           fdx, fdy, fc, fid)) {
+                    ok = dev::touching_pair(ex, ey, edx, edy, ec, rid[r * kBlock + tid], fx, fy,
+                                            fdx, fdy, fc, fid);
+                    if (ok) {
                         const double cr = fma(-edy, fdx, edx * fdy);
                         const double v = angc + fabs(fabs(rTH[r] - fth) - kHalfPi);
                         const double s = (v * fma(edx, fdx, edy * fdy)) * cr;
                         pos = s > 0.0;
                         neg = s < 0.0;
+                        // parallel lines or a zero-length edge: a = 0
+                        acc += (cr == 0.0) ? ideal : fabs(v);
                     }
                 }
+                n_touch += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(ok));
                 kr[r] += (int)pos - (int)neg;
                 colsum += (int)__popcll(__builtin_amdgcn_ballot_w64(pos)) -
                           (int)__popcll(__builtin_amdgcn_ballot_w64(neg));
@@ -103,10 +115,12 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
 template <int K, int WAVES>
 __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     const EdgeRec *__restrict__ rec, SweepLayout lay, int64_t n_units, double ideal,
-    int *__restrict__ kacc) {
+    int *__restrict__ kacc, CrossPartial *__restrict__ part) {
     __shared__ EdgeRec col[kChunk];
     __shared__ int2 rid[kBlock * K];
     __shared__ int colk[(kBlock / 64) * kChunk];
+    __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
+    __shared__ double red_d[kBlock / 64];
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
     const int64_t u_begin = block_first_unit(n_units, G, b);
@@ -124,6 +138,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
     int kr[K];
     bool rows_loaded = false;
+    uint32_t n_p = 0, n_t = 0;
+    unsigned long long tot_p = 0, tot_t = 0;
+    double acc = 0.0;
 
     auto flush_rows = [&]() {
 #pragma unroll
@@ -150,10 +167,14 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
         const int64_t row0 = I * R + tid, col0 = c * kChunk;
         if (c < (I + 1) * K)
             adjoint_chunk<K, true>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, row0, col0,
-                                   angc);
+                                   ideal, angc, n_p, n_t, acc);
         else
             adjoint_chunk<K, false>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, row0, col0,
-                                    angc);
+                                    ideal, angc, n_p, n_t, acc);
+        tot_p += n_p;
+        tot_t += n_t;
+        n_p = 0;
+        n_t = 0;
         __syncthreads();
         {   // the column edge f of a pair receives -q
             int sum = 0;
@@ -168,6 +189,26 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
         }
     }
     if (rows_loaded) flush_rows();
+    // forward partial of this block: crossing counts and the deviation sum
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const int wave = tid >> 6, lane = tid & 63;
+    __syncthreads();
+    if (lane == 0) {
+        red_p[wave] = tot_p;
+        red_t[wave] = tot_t;
+        red_d[wave] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        CrossPartial P;
+        P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            P.proper += red_p[w];
+            P.touch += red_t[w];
+            P.dev += red_d[w];
+        }
+        part[b] = P;
+    }
 }
 
 // Chain rule per edge, scattered to the end nodes; thread 0 also writes the loss.
@@ -252,29 +293,13 @@ hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, con
     unsigned long long *fw_count = (unsigned long long *)(w + L.fwd);
     double *fw_eca = (double *)(w + L.fwd) + 1;
     double *fw_ml = (double *)(w + L.fwd) + 2;
-    // forward: crossing set, E_ca and M_l (with the mean length in sc)
+    // one sweep gives the forward terms (crossing count, deviation sum) and
+    // the integer adjoint counts per edge; M_l and the mean length come from
+    // the edge-length pass
     RB_TRY(launch_edge_prep(x, y, src, dst, n_nodes, n_edges, L.n_edge_pad, rec, st));
-    {
-        const int v = tuned_variant(1, false, n_edges);
-        const int rows = cross_variant(v).rows;
-        SweepArgs a;
-        a.table = nullptr;
-        a.single = sweep_layout(n_edges, rows, 0, 0);
-        a.n_layouts = 1;
-        a.n_units = sweep_units(n_edges, rows);
-        a.unit_base = 0;
-        const int grid = (int)std::min<int64_t>(a.n_units, cross_grid(v, true));
-        CrossPartial *part = (CrossPartial *)(w + L.partial);
-        RB_TRY(launch_cross_sweep(v, true, rec, a, grid, ideal, part, st));
-        RB_TRY(launch_cross_finalize(part, grid, ideal, fw_count, nullptr, fw_eca, nullptr, st));
-    }
     RB_TRY(launch_zero_scalars(sc, st));
     RB_TRY(launch_elv(x, y, src, dst, n_nodes, n_edges, (double *)(w + L.partial), sc, fw_ml,
                       nullptr, st));
-    hipLaunchKernelGGL(stash_kernel, dim3(1), dim3(64), 0, st, sc, fw_count, fw_eca, fw_ml,
-                       out_count);
-    RB_TRY(hipGetLastError());
-    // backward sweep: integer adjoint counts per edge
     RB_TRY(launch_fill_u32((uint32_t *)kacc, L.n_edge_pad, 0u, st));
     const SweepLayout lay = sweep_layout(n_edges, kAdjRows, 0, 0);
     const int64_t U = sweep_units(n_edges, kAdjRows);
@@ -284,11 +309,16 @@ hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, con
                 &per_cu, adjoint_sweep_kernel<kAdjRows, kAdjWaves>, kBlock, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        g_adj_grid = per_cu * device_cu_count();
+        g_adj_grid = std::min(per_cu * device_cu_count(), kMaxPartials);
     }
     const int grid = (int)std::min<int64_t>(U, g_adj_grid);
+    CrossPartial *part = (CrossPartial *)(w + L.partial);
     hipLaunchKernelGGL((adjoint_sweep_kernel<kAdjRows, kAdjWaves>), dim3(grid), dim3(kBlock), 0,
-                       st, rec, lay, U, ideal, kacc);
+                       st, rec, lay, U, ideal, kacc, part);
+    RB_TRY(hipGetLastError());
+    RB_TRY(launch_cross_finalize(part, grid, ideal, fw_count, nullptr, fw_eca, nullptr, st));
+    hipLaunchKernelGGL(stash_kernel, dim3(1), dim3(64), 0, st, sc, fw_count, fw_eca, fw_ml,
+                       out_count);
     RB_TRY(hipGetLastError());
     // chain rule and scatter
     const int64_t V = n_nodes > 0 ? n_nodes : 1;
