@@ -192,6 +192,17 @@ def bench_largest(torch):
     occl_ms = ms.value
     R.rb_timing_reset()
     ang = ang.cpu()
+    occ_grid = metrics.node_occlusion_grid(D.x, D.y, D.diameter)
+    R.rb_timing_enable(1)
+    for _ in range(3):
+        metrics.node_occlusion_grid(D.x, D.y, D.diameter, async_=True)
+    torch.cuda.synchronize()
+    R.rb_timing_enable(0)
+    _lib.check(R.rb_timing_read(2, C.byref(ms), C.byref(n)), "rb_timing_read")
+    grid_ms = ms.value / max(n.value, 1)
+    R.rb_timing_reset()
+    if occ_grid != int(occ.item()):
+        raise RuntimeError(f"grid occlusion {occ_grid} != brute force {int(occ.item())}")
     return {"workload": f"power-law (gamma 2.3, max degree 10,000) |V|={L.n_nodes} |E|={L.n_edges}, "
                         "hub-heavy clusters in [0,2^20)^2, diameter 16",
             "edge_pairs": pairs, "node_pairs": node_pairs, "step_s": total,
@@ -200,6 +211,7 @@ def bench_largest(torch):
                 OPS_PER_EDGE_PAIR * pairs / (cross_ms * 1e-3) / VALU_PEAK_OPS,
             "node_pair_sweep_ms": occl_ms,
             "node_pair_sweep_pairs_per_s": node_pairs / (occl_ms * 1e-3),
+            "node_occlusion_grid_ms": grid_ms,
             "edge_crossings": int(ang.view(torch.int64)[1]), "crossing_angle": float(ang[0]),
             "node_occlusions": int(occ.item()), "min_angle": float(ma[0]),
             "edge_length_variation": float(ml[0])}
@@ -295,7 +307,21 @@ def main():
     occl_ms = ms.value / max(n.value, 1)
     R.rb_timing_reset()
 
+    # the grid method of Section 3.2.1 on the same layout (same exact count)
+    grid_occ = metrics.node_occlusion_grid(D.x, D.y, D.diameter)
+    R.rb_timing_reset()
+    R.rb_timing_enable(1)
+    for _ in range(args.steps):
+        metrics.node_occlusion_grid(D.x, D.y, D.diameter, async_=True)
+    torch.cuda.synchronize()
+    R.rb_timing_enable(0)
+    _lib.check(R.rb_timing_read(2, C.byref(ms), C.byref(n)), "rb_timing_read")
+    grid_ms = ms.value / max(n.value, 1)
+    R.rb_timing_reset()
+
     vals = [o.cpu() for o in out]
+    if grid_occ != int(vals[0][0]):
+        raise RuntimeError(f"grid occlusion {grid_occ} != brute force {int(vals[0][0])}")
     log(f"[bench] occlusion={int(vals[0][0])} E_c={int(vals[1].view(torch.int64)[1])} "
         f"E_ca={float(vals[1][0]):.6f} M_a={float(vals[2][0]):.6f} M_l={float(vals[3][0]):.6g}")
     ms_step = elapsed * 1e3 / args.steps
@@ -328,7 +354,8 @@ def main():
                     "node_pair_sweep_ms": occl_ms,
                     "node_pair_sweep_pairs_per_s": node_pairs / (occl_ms * 1e-3),
                     "node_pair_sweep_valu_frac":
-                        OPS_PER_NODE_PAIR * node_pairs / (occl_ms * 1e-3) / VALU_PEAK_OPS},
+                        OPS_PER_NODE_PAIR * node_pairs / (occl_ms * 1e-3) / VALU_PEAK_OPS,
+                    "node_occlusion_grid_ms": grid_ms},
     }
     if not args.no_batch:
         log("[bench] batched 512 layouts ...")

@@ -106,6 +106,20 @@ rb_status rb_crossing_angle(const float *x, const float *y, int64_t n_nodes,
                             uint64_t *out_count, double *out_dev_sum,
                             void *ws, size_t ws_bytes, void *stream);
 
+/* Grid-pruned exact paths.  They return exactly what the brute-force calls
+ * return (integer counts bit for bit) while skipping pairs that cannot
+ * count, and they use their own workspace: rb_grid_workspace_size(V, E)
+ * bytes, 256-byte aligned, caller-owned (it covers both calls below).
+ * rb_node_occlusion_grid: N_c as rb_node_occlusion, by the grid method of
+ *   Section 3.2.1 (cells of side >= d; each node meets the nodes of its own
+ *   and four neighbour cells).  Work is O(|V| log |V| + candidate pairs).
+ * Errors as for the brute-force calls (RB_EWORKSPACE for a short or
+ * misaligned workspace).                                                  */
+size_t rb_grid_workspace_size(int64_t n_nodes, int64_t n_edges);
+rb_status rb_node_occlusion_grid(const float *x, const float *y, int64_t n_nodes,
+                                 double diameter, uint64_t *out_count, void *ws,
+                                 size_t ws_bytes, void *stream);
+
 /* Shards of the two all-pairs sweeps, for splitting one layout across
  * devices or processes (each computes its shards; the sums of the shard
  * results are the full results) and for checking a slice of a large
@@ -259,8 +273,9 @@ rb_status rb_tune_load(const char *path);
  * event pair on the caller's stream around each launch of its all-pairs
  * sweep kernels.  rb_timing_read waits for the recorded events and returns
  * the summed duration in milliseconds and the number of launches of one
- * kernel: 0 = edge-pair sweep (crossing / crossing angle), 1 = node-pair
- * sweep (occlusion).  rb_timing_reset clears the sums.                    */
+ * kind: 0 = edge-pair sweep (crossing / crossing angle), 1 = node-pair
+ * sweep (occlusion), 2 = grid occlusion (all its kernels), 3 = pruned
+ * edge-pair path (all its kernels).  rb_timing_reset clears the sums.     */
 rb_status rb_timing_enable(int enable);
 rb_status rb_timing_reset(void);
 rb_status rb_timing_read(int kernel, double *total_ms, int64_t *launches);

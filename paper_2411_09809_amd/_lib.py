@@ -40,6 +40,8 @@ _SIGS = {
                                  C.c_int),
     "rb_validate_layout": ([_vp, _vp, _i64, _vp, _vp, _i64, C.POINTER(C.c_int32), _vp, _sz, _vp],
                            C.c_int),
+    "rb_grid_workspace_size": ([_i64, _i64], _sz),
+    "rb_node_occlusion_grid": ([_vp, _vp, _i64, _f64, _vp, _vp, _sz, _vp], C.c_int),
     "rb_crossing_angle_shard": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _i64, _i64, _vp, _vp,
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64), _vp, _sz, _vp],
                                 C.c_int),

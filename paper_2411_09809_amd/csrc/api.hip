@@ -38,13 +38,15 @@ constexpr int64_t kMaxEdges = 1LL << 30;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Timing of the sweep kernels (rb_timing_*).
+// Timing of the sweep kernels (rb_timing_*): 0 edge-pair sweep, 1 node-pair
+// sweep, 2 grid occlusion, 3 pruned edge sweep.
+constexpr int kTimedKinds = 4;
 struct Timing {
     std::mutex mu;
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
-    double ms[2] = {0.0, 0.0};
-    int64_t n[2] = {0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kTimedKinds];
+    double ms[kTimedKinds] = {};
+    int64_t n[kTimedKinds] = {};
 } g_timing;
 
 struct TimedLaunch {
@@ -371,6 +373,37 @@ rb_status rb_node_occlusion_shard(const float *x, const float *y, int64_t n_node
     return RB_OK;
 }
 
+size_t rb_grid_workspace_size(int64_t n_nodes, int64_t n_edges) {
+    GridWs G;
+    if (!grid_ws_layout(n_nodes, n_edges, &G)) return 0;
+    return G.total;
+}
+
+rb_status rb_node_occlusion_grid(const float *x, const float *y, int64_t n_nodes,
+                                 double diameter, uint64_t *out_count, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_sizes(n_nodes, 0);
+    if (s) return s;
+    if (n_nodes > 0 && (!x || !y)) return fail(RB_EINVAL, "x or y is NULL");
+    if (!out_count) return fail(RB_EINVAL, "out_count is NULL");
+    if (!(diameter >= 0.0) || !std::isfinite(diameter))
+        return fail(RB_EINVAL, "diameter must be finite and >= 0");
+    GridWs G;
+    if (!grid_ws_layout(n_nodes, 0, &G)) return fail(RB_EINVAL, "layout too large");
+    if (!ws) return fail(RB_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(RB_EWORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < G.total)
+        return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, G.total);
+    hipStream_t st = (hipStream_t)stream;
+    TimedLaunch tl(2, st);
+    hipError_t e = launch_occlusion_grid(x, y, n_nodes, occlusion_threshold(diameter), G,
+                                         (char *)ws, (unsigned long long *)out_count, st);
+    tl.done();
+    if (e != hipSuccess) return hip_fail(e, "grid occlusion launch");
+    return RB_OK;
+}
+
 rb_status rb_edge_crossing(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                            const int32_t *dst, int64_t n_edges, uint64_t *out_count,
                            uint64_t *out_proper, void *ws, size_t ws_bytes, void *stream) {
@@ -603,7 +636,7 @@ rb_status rb_timing_enable(int enable) {
 
 rb_status rb_timing_reset(void) {
     std::lock_guard<std::mutex> g(g_timing.mu);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kTimedKinds; ++k) {
         for (auto &p : g_timing.ev[k]) {
             (void)hipEventDestroy(p.first);
             (void)hipEventDestroy(p.second);
@@ -617,7 +650,8 @@ rb_status rb_timing_reset(void) {
 
 rb_status rb_timing_read(int kernel, double *total_ms, int64_t *launches) {
     g_err.clear();
-    if (kernel < 0 || kernel > 1) return fail(RB_EINVAL, "kernel must be 0 or 1");
+    if (kernel < 0 || kernel >= kTimedKinds)
+        return fail(RB_EINVAL, "kernel must be in 0 .. %d", kTimedKinds - 1);
     std::lock_guard<std::mutex> g(g_timing.mu);
     for (auto &p : g_timing.ev[kernel]) {
         hipError_t e = hipEventSynchronize(p.second);

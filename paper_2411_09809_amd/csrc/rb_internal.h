@@ -94,6 +94,20 @@ struct WsLayout {
 };
 bool ws_layout(int64_t n_nodes, int64_t n_edges, WsLayout *L);
 
+// Grid-pruned paths (grid.hip): cell parameters on the device and the
+// workspace they use (byte offsets, 256-aligned).
+struct __align__(16) GridParams {
+    int32_t xmin, ymin, xmax, ymax;   // bounding box of the node coordinates
+    int32_t shift;                    // cell side 2^shift
+    int32_t pad[3];
+};
+struct GridWs {
+    size_t params, keys, vals, keys2, vals2, pos, hist, hist_off, scan_tile, partial;
+    size_t total;
+    int64_t n_sort_blocks;
+};
+bool grid_ws_layout(int64_t n_nodes, int64_t n_edges, GridWs *G);
+
 // Small device scalars used between kernels of one call.
 struct __align__(16) Scalars {
     double mean;            // edge length mean
@@ -161,6 +175,14 @@ hipError_t launch_min_angle_nodes(const uint32_t *deg, const uint32_t *offs, dou
                                   hipStream_t st);
 
 // loss w_a (1 - E_ca) + w_l M_l and its gradient with respect to x, y
+hipError_t launch_radix_sort(uint32_t *keys, int32_t *vals, uint32_t *keys2, int32_t *vals2,
+                             int64_t n, uint32_t *hist, uint32_t *hist_off,
+                             unsigned long long *scan_tile, hipStream_t st);
+hipError_t launch_grid_bounds(const float *x, const float *y, int64_t n, GridParams *gp,
+                              int min_shift, int axis_bits, hipStream_t st);
+hipError_t launch_occlusion_grid(const float *x, const float *y, int64_t n, double T,
+                                 const GridWs &G, char *w, unsigned long long *out_count,
+                                 hipStream_t st);
 hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                             const int32_t *dst, int64_t n_edges, double ideal, double w_a,
                             double w_l, double *out_loss, double *gx, double *gy,

@@ -44,6 +44,24 @@ def workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
     return ws
 
 
+_grid_ws_cache: dict[int, torch.Tensor] = {}
+
+
+def grid_workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
+    """A cached device workspace for the grid-pruned calls."""
+    need = int(lib().rb_grid_workspace_size(int(n_nodes), int(n_edges)))
+    if need == 0:
+        raise ValueError(f"layout size out of range: {n_nodes} nodes, {n_edges} edges")
+    dev = torch.device(device)
+    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    ws = _grid_ws_cache.get(key)
+    if ws is None or ws.numel() < need:
+        _grid_ws_cache.pop(key, None)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        _grid_ws_cache[key] = ws
+    return ws
+
+
 def _ws_args(ws: torch.Tensor):
     p = ws.data_ptr()
     aligned = (p + 255) & ~255
@@ -147,6 +165,18 @@ def edge_length_variation(x, y, src, dst, *, async_: bool = False):
         return out
     m, mu = out.tolist()
     return float(m), float(mu)
+
+
+def node_occlusion_grid(x, y, diameter: float, *, async_: bool = False):
+    """N_c by the grid method (Section 3.2.1): the brute-force count, with
+    only pairs in the same or neighbouring cells tested."""
+    _check_coords(x, y)
+    out = _out(1, torch.int64, x.device)
+    ws = grid_workspace(x.numel(), 0, x.device)
+    w, wb = _ws_args(ws)
+    check(lib().rb_node_occlusion_grid(_ptr(x), _ptr(y), x.numel(), float(diameter), _ptr(out), w,
+                                       wb, _stream(x.device)), "rb_node_occlusion_grid")
+    return out if async_ else int(out.item())
 
 
 def crossing_angle_shard(x, y, src, dst, shard: int, n_shards: int,

@@ -1,0 +1,114 @@
+"""Grid-pruned exact paths against the brute-force sweeps and the oracle.
+
+rb_node_occlusion_grid must return the brute-force N_c bit for bit: on
+closed-form lattices, coincident nodes, the full range of diameters (zero,
+sub-unit, exact integer thresholds, larger than the layout), crowded and
+negative-coordinate layouts, and the full-size workloads up to the
+1,000,000-node power-law layout.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_09809_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+def dev_xy(torch, x, y):
+    t = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float32)).cuda().contiguous()
+    return t(x), t(y)
+
+
+@pytest.mark.parametrize("k,s,d", [(7, 4, 8.0), (7, 8, 8.0), (10, 3, 6.5), (12, 5, 7.0),
+                                   (9, 1, 1.0), (9, 1, 1.5), (16, 2, 40.0)])
+def test_lattice(torch_mod, k, s, d):
+    from paper_2411_09809_amd import metrics
+    L = gen.square_lattice(k, s, d)
+    x, y = dev_xy(torch_mod, L.x, L.y)
+    want = oracle.node_occlusion(L.x, L.y, d)
+    assert metrics.node_occlusion_grid(x, y, d) == want
+    assert metrics.node_occlusion(x, y, d) == want
+
+
+def test_coincident_and_tiny(torch_mod):
+    from paper_2411_09809_amd import metrics
+    for n in (0, 1, 2, 5, 300):
+        x, y = dev_xy(torch_mod, np.full(n, 17.0), np.full(n, -3.0))
+        assert metrics.node_occlusion_grid(x, y, 1.0) == n * (n - 1) // 2
+        assert metrics.node_occlusion_grid(x, y, 0.0) == 0
+
+
+@pytest.mark.parametrize("d", [0.0, 0.5, 1.0, 1.0000001, 2.0, 3.0, 7.9, 8.0, 8.0000001, 33.3,
+                               256.0, 5000.0, 1e7])
+def test_diameters_uniform(torch_mod, d):
+    from paper_2411_09809_amd import metrics
+    L = gen.uniform_layout(4000, 10, extent=1 << 10, seed=31)
+    x, y = dev_xy(torch_mod, L.x, L.y)
+    want = metrics.node_occlusion(x, y, d)
+    got = metrics.node_occlusion_grid(x, y, d)
+    say(f"[grid] d={d} brute={want} grid={got}")
+    assert got == want
+    assert want == oracle.node_occlusion(L.x, L.y, d)
+
+
+def test_crowded_and_negative(torch_mod):
+    from paper_2411_09809_amd import metrics
+    rng = np.random.default_rng(5)
+    cases = [
+        (rng.integers(0, 64, 3000), rng.integers(0, 64, 3000), 6.0),
+        (rng.integers(-(1 << 20), 1 << 20, 20000), rng.integers(-(1 << 20), 1 << 20, 20000),
+         30000.0),
+        (rng.integers(-500, 500, 8000), rng.integers(-(1 << 20), (1 << 20) + 1, 8000), 700.0),
+        (np.concatenate([np.full(100, -(1 << 20)), np.full(100, 1 << 20)]),
+         np.concatenate([np.full(100, 1 << 20), np.full(100, -(1 << 20))]), 2.0),
+    ]
+    for xs, ys, d in cases:
+        x, y = dev_xy(torch_mod, xs, ys)
+        want = oracle.node_occlusion(xs, ys, d)
+        assert metrics.node_occlusion_grid(x, y, d) == want
+        assert metrics.node_occlusion(x, y, d) == want
+
+
+@pytest.mark.parametrize("name", ["ba_cluster_V50000_E149994", "rgg_V20000_E60000",
+                                  "powerlaw_V1000000_E3000000"])
+def test_full_size_workloads(torch_mod, name):
+    from paper_2411_09809_amd import metrics
+    L = gen.WORKLOADS[name](seed=0)
+    x, y = dev_xy(torch_mod, L.x, L.y)
+    want = metrics.node_occlusion(x, y, L.diameter)
+    got = metrics.node_occlusion_grid(x, y, L.diameter)
+    again = metrics.node_occlusion_grid(x, y, L.diameter)
+    say(f"[grid] {name} d={L.diameter} brute={want} grid={got}")
+    assert got == want == again
+    for d in (1.0, 4 * L.diameter):
+        assert metrics.node_occlusion_grid(x, y, d) == metrics.node_occlusion(x, y, d)
+
+
+def test_short_workspace_is_an_error(torch_mod):
+    from paper_2411_09809_amd import _lib, metrics
+    lib = _lib.lib()
+    x, y = dev_xy(torch_mod, np.arange(100.0), np.zeros(100))
+    out = torch_mod.zeros(1, dtype=torch_mod.int64, device="cuda")
+    need = lib.rb_grid_workspace_size(100, 0)
+    ws = torch_mod.empty(need + 256, dtype=torch_mod.uint8, device="cuda")
+    w = (ws.data_ptr() + 255) & ~255
+    rc = lib.rb_node_occlusion_grid(x.data_ptr(), y.data_ptr(), 100, 2.0, out.data_ptr(), w,
+                                    need - 256, metrics._stream(x.device))
+    assert rc == 2                      # RB_EWORKSPACE
+    assert b"workspace" in lib.rb_last_error()
