@@ -162,6 +162,58 @@ def bench_adjoint(torch, reps: int, gd_steps: int):
     return out
 
 
+def time_kind(torch, kind, fn, reps):
+    """Mean duration (ms) of librb's launches of one timed kind over `reps`
+    calls of fn, from the events the library records on the launch stream."""
+    import ctypes as C
+    from paper_2411_09809_amd import _lib
+    R = _lib.lib()
+    fn()
+    torch.cuda.synchronize()
+    R.rb_timing_reset()
+    R.rb_timing_enable(1)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    R.rb_timing_enable(0)
+    ms, n = C.c_double(), C.c_int64()
+    _lib.check(R.rb_timing_read(kind, C.byref(ms), C.byref(n)), "rb_timing_read")
+    R.rb_timing_reset()
+    return ms.value / max(n.value, 1)
+
+
+def bench_pruned(torch, reps: int):
+    """Grid-pruned paths against the brute-force sweeps on the layouts with
+    short edges (random geometric) and long edges (preferential attachment):
+    same exact counts, time of the whole call (sort and planning included)."""
+    from paper_2411_09809_amd import gen, metrics
+    out = {}
+    for name in ("rgg_V20000_E60000", "ba_cluster_V50000_E149994"):
+        L = gen.WORKLOADS[name](seed=0)
+        D = metrics.DeviceLayout.from_host(L)
+        brute = metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle)
+        pruned = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, D.ideal_angle)
+        if pruned[1] != brute[1]:
+            raise RuntimeError(f"{name}: pruned E_c {pruned[1]} != brute force {brute[1]}")
+        b_ms = time_kind(torch, 0, lambda: metrics.crossing_angle(
+            D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True), reps)
+        p_ms = time_kind(torch, 3, lambda: metrics.crossing_angle_pruned(
+            D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True), reps)
+        ob = metrics.node_occlusion(D.x, D.y, D.diameter)
+        og = metrics.node_occlusion_grid(D.x, D.y, D.diameter)
+        if og != ob:
+            raise RuntimeError(f"{name}: grid N_c {og} != brute force {ob}")
+        ob_ms = time_kind(torch, 1, lambda: metrics.node_occlusion(
+            D.x, D.y, D.diameter, async_=True), reps)
+        og_ms = time_kind(torch, 2, lambda: metrics.node_occlusion_grid(
+            D.x, D.y, D.diameter, async_=True), reps)
+        out[name] = {"edge_crossings": brute[1], "crossing_sweep_ms": b_ms,
+                     "crossing_pruned_ms": p_ms, "crossing_speedup": b_ms / p_ms,
+                     "node_occlusions": ob, "occlusion_sweep_ms": ob_ms,
+                     "occlusion_grid_ms": og_ms, "occlusion_speedup": ob_ms / og_ms}
+    return out
+
+
 def bench_largest(torch):
     """The 1,000,000-node / 3,000,000-edge power-law layout: one pass of each
     sweep (4.5e12 edge pairs, 5.0e11 node pairs) plus the two small metrics,
@@ -203,6 +255,11 @@ def bench_largest(torch):
     R.rb_timing_reset()
     if occ_grid != int(occ.item()):
         raise RuntimeError(f"grid occlusion {occ_grid} != brute force {int(occ.item())}")
+    pruned = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, D.ideal_angle)
+    if pruned[1] != int(ang.view(torch.int64)[1]):
+        raise RuntimeError("pruned crossing count differs from the brute-force count")
+    pruned_ms = time_kind(torch, 3, lambda: metrics.crossing_angle_pruned(
+        D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True), 1)
     return {"workload": f"power-law (gamma 2.3, max degree 10,000) |V|={L.n_nodes} |E|={L.n_edges}, "
                         "hub-heavy clusters in [0,2^20)^2, diameter 16",
             "edge_pairs": pairs, "node_pairs": node_pairs, "step_s": total,
@@ -212,6 +269,7 @@ def bench_largest(torch):
             "node_pair_sweep_ms": occl_ms,
             "node_pair_sweep_pairs_per_s": node_pairs / (occl_ms * 1e-3),
             "node_occlusion_grid_ms": grid_ms,
+            "crossing_pruned_ms": pruned_ms,
             "edge_crossings": int(ang.view(torch.int64)[1]), "crossing_angle": float(ang[0]),
             "node_occlusions": int(occ.item()), "min_angle": float(ma[0]),
             "edge_length_variation": float(ml[0])}
@@ -228,6 +286,8 @@ def main():
                     help="edge pairs in the CPU-baseline sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-layout comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward part")
+    ap.add_argument("--no-pruned", action="store_true",
+                    help="skip the grid-pruned paths")
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the single pass over the 1M-node / 3M-edge layout")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -363,6 +423,9 @@ def main():
     if not args.no_adjoint:
         log("[bench] forward + adjoint ...")
         rec["fwd_bwd"] = bench_adjoint(torch, max(3, args.steps // 2), 100)
+    if not args.no_pruned:
+        log("[bench] grid-pruned paths ...")
+        rec["pruned"] = bench_pruned(torch, max(3, args.steps // 4))
     if not args.no_largest:
         log("[bench] largest layout (1M nodes, 3M edges) ...")
         rec["largest"] = bench_largest(torch)

@@ -113,12 +113,24 @@ rb_status rb_crossing_angle(const float *x, const float *y, int64_t n_nodes,
  * rb_node_occlusion_grid: N_c as rb_node_occlusion, by the grid method of
  *   Section 3.2.1 (cells of side >= d; each node meets the nodes of its own
  *   and four neighbour cells).  Work is O(|V| log |V| + candidate pairs).
+ * rb_crossing_angle_pruned: E_ca, E_c and the deviation sum as
+ *   rb_crossing_angle (Algorithms 4 and 5), skipping the tiles of the pair
+ *   triangle whose edges' bounding boxes cannot meet: edges are ordered by
+ *   bounding-box size class and the Morton code of the box centre first.
+ *   Counts equal the brute-force counts; the deviation sum is added in
+ *   another order (equal to rounding).  n_edges <= 2^24.  The gain depends
+ *   on the layout: large for short edges, none for edges spanning the layout.
  * Errors as for the brute-force calls (RB_EWORKSPACE for a short or
  * misaligned workspace).                                                  */
 size_t rb_grid_workspace_size(int64_t n_nodes, int64_t n_edges);
 rb_status rb_node_occlusion_grid(const float *x, const float *y, int64_t n_nodes,
                                  double diameter, uint64_t *out_count, void *ws,
                                  size_t ws_bytes, void *stream);
+rb_status rb_crossing_angle_pruned(const float *x, const float *y, int64_t n_nodes,
+                                   const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                   double ideal_angle, double *out_metric, uint64_t *out_count,
+                                   double *out_dev_sum, void *ws, size_t ws_bytes,
+                                   void *stream);
 
 /* Shards of the two all-pairs sweeps, for splitting one layout across
  * devices or processes (each computes its shards; the sums of the shard
@@ -248,7 +260,10 @@ void rb_graph_destroy(rb_graph *graph);
  * identical results.  Each call above picks the variant recorded for the
  * layout's size class (floor(log2) of its edge count, node count for the
  * occlusion sweep); built-in defaults apply until tuned.
- *   kind: 0 = edge crossing, 1 = crossing angle, 2 = node occlusion;
+ *   kind: 0 = edge crossing, 1 = crossing angle, 2 = node occlusion,
+ *         3 = pruned crossing angle (rb_crossing_angle_pruned; not timed by
+ *         rb_autotune; default 256 edges per row tile below 2^17 edges,
+ *         512 above);
  *   batch: 0 = single-layout calls, 1 = rb_batch_* calls.
  * rb_autotune times every variant of the three sweeps on the given layout
  * (`repeats` timed launches each, after one untimed launch), records the

@@ -42,6 +42,8 @@ _SIGS = {
                            C.c_int),
     "rb_grid_workspace_size": ([_i64, _i64], _sz),
     "rb_node_occlusion_grid": ([_vp, _vp, _i64, _f64, _vp, _vp, _sz, _vp], C.c_int),
+    "rb_crossing_angle_pruned": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _vp, _vp, _vp, _vp, _sz,
+                                  _vp], C.c_int),
     "rb_crossing_angle_shard": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _i64, _i64, _vp, _vp,
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64), _vp, _sz, _vp],
                                 C.c_int),

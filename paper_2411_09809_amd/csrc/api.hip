@@ -404,6 +404,37 @@ rb_status rb_node_occlusion_grid(const float *x, const float *y, int64_t n_nodes
     return RB_OK;
 }
 
+rb_status rb_crossing_angle_pruned(const float *x, const float *y, int64_t n_nodes,
+                                   const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                   double ideal_angle, double *out_metric, uint64_t *out_count,
+                                   double *out_dev_sum, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
+    if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
+        return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
+    if (n_edges > kMaxPrunedEdges)
+        return fail(RB_EINVAL, "n_edges = %lld above the pruned path's limit 2^24",
+                    (long long)n_edges);
+    GridWs G;
+    if (!grid_ws_layout(n_nodes, n_edges, &G)) return fail(RB_EINVAL, "layout too large");
+    if (!ws) return fail(RB_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(RB_EWORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < G.total)
+        return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, G.total);
+    hipStream_t st = (hipStream_t)stream;
+    const int v = tuned_variant(3, false, n_edges);
+    TimedLaunch tl(3, st);
+    hipError_t e = launch_crossing_pruned(x, y, n_nodes, src, dst, n_edges, ideal_angle, G,
+                                          (char *)ws, v, out_metric,
+                                          (unsigned long long *)out_count, out_dev_sum, st);
+    tl.done();
+    if (e != hipSuccess) return hip_fail(e, "pruned crossing launch");
+    return RB_OK;
+}
+
 rb_status rb_edge_crossing(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                            const int32_t *dst, int64_t n_edges, uint64_t *out_count,
                            uint64_t *out_proper, void *ws, size_t ws_bytes, void *stream) {
@@ -595,7 +626,7 @@ rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes, const int
 
 rb_status rb_tune_set(int kind, int batch, int64_t n_items, int variant) {
     g_err.clear();
-    if (kind < 0 || kind > 2) return fail(RB_EINVAL, "kind must be 0, 1 or 2");
+    if (kind < 0 || kind > 3) return fail(RB_EINVAL, "kind must be 0, 1, 2 or 3");
     if (n_items < 0) return fail(RB_EINVAL, "n_items must be >= 0");
     const int nv = kind == 2 ? kOcclVariants : kCrossVariants;
     if (variant < 0 || variant >= nv) return fail(RB_EINVAL, "variant must be in [0, %d)", nv);
@@ -605,7 +636,7 @@ rb_status rb_tune_set(int kind, int batch, int64_t n_items, int variant) {
 
 rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *waves) {
     g_err.clear();
-    if (kind < 0 || kind > 2) return fail(RB_EINVAL, "kind must be 0, 1 or 2");
+    if (kind < 0 || kind > 3) return fail(RB_EINVAL, "kind must be 0, 1, 2 or 3");
     if (n_items < 0) return fail(RB_EINVAL, "n_items must be >= 0");
     const int v = tuned_variant(kind, batch != 0, n_items);
     const SweepVariant sv = kind == 2 ? occl_variant(v) : cross_variant(v);

@@ -217,6 +217,94 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
 }
 
 // Sum of the partial slots of one layout, in slot order.
+// The same sweep over an explicit unit list (the pruned path): tile I meets
+// the chunks list[tile_off[I] .. tile_off[I+1]), in increasing order; the
+// list's length lives in device memory, so every block writes its partial.
+template <int K, int WAVES, bool ANGLE>
+__global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
+    const EdgeRec *__restrict__ rec, const int32_t *__restrict__ list,
+    const uint32_t *__restrict__ tile_off, int64_t n_tiles, double ideal,
+    CrossPartial *__restrict__ part) {
+    __shared__ EdgeRec col[kChunk];
+    __shared__ int2 rid[kBlock * K];
+    __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
+    __shared__ double red_d[kBlock / 64];
+
+    const int tid = threadIdx.x;
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t U = tile_off[n_tiles];
+    const int64_t u_begin = block_first_unit(U, G, b);
+    const int64_t u_end = block_first_unit(U, G, b + 1);
+    constexpr int64_t R = (int64_t)kBlock * K;
+    const double angc = ideal - kHalfPi;
+
+    // tile of the first unit: the largest I with tile_off[I] <= u_begin
+    int64_t lo = 0, hi = n_tiles - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)tile_off[mid] <= u_begin) lo = mid;
+        else hi = mid - 1;
+    }
+    int64_t I = lo;
+
+    double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
+    bool rows_loaded = false;
+    unsigned long long tot_p = 0, tot_t = 0;
+    double acc = 0.0;
+
+    for (int64_t u = u_begin; u < u_end; ++u) {
+        while ((int64_t)tile_off[I + 1] <= u) {   // u < U = tile_off[n_tiles]: stops in range
+            ++I;
+            rows_loaded = false;
+        }
+        __syncthreads();                       // previous chunk and row ids consumed
+        if (!rows_loaded) {
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const EdgeRec e = rec[I * R + (int64_t)r * kBlock + tid];
+                rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
+                rC[r] = e.c; rTH[r] = e.th;
+                rid[r * kBlock + tid] = make_int2(e.s, e.t);
+            }
+            rows_loaded = true;
+        }
+        const int64_t c = list[u];
+        col[tid] = rec[c * kChunk + tid];
+        __syncthreads();
+        uint32_t n_p = 0, n_t = 0;
+        const int64_t row0 = I * R + tid, col0 = c * kChunk;
+        if (c < (I + 1) * K)
+            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, row0, col0,
+                                        ideal, angc, n_p, n_t, acc);
+        else
+            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, row0, col0,
+                                         ideal, angc, n_p, n_t, acc);
+        tot_p += n_p;
+        tot_t += n_t;
+    }
+    if (ANGLE) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    __syncthreads();
+    if (lane == 0) {
+        red_p[wave] = tot_p;
+        red_t[wave] = tot_t;
+        red_d[wave] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        CrossPartial P;
+        P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            P.proper += red_p[w];
+            P.touch += red_t[w];
+            P.dev += red_d[w];
+        }
+        part[b] = P;
+    }
+}
+
 __global__ __launch_bounds__(256) void cross_finalize_kernel(
     const CrossPartial *__restrict__ part, int n_part, double ideal,
     unsigned long long *out_count, unsigned long long *out_proper, double *out_metric,
@@ -295,6 +383,52 @@ int cross_grid(int v, bool angle) {
         if (g > kMaxPartials) g = kMaxPartials;
     }
     return g;
+}
+
+int g_list_grid[kCrossVariants];
+
+template <int V>
+const void *list_kernel_ptr() {
+    return (const void *)cross_list_kernel<CrossV<V>::K, CrossV<V>::W, true>;
+}
+
+int cross_list_grid(int v) {
+    int &g = g_list_grid[v];
+    if (g == 0) {
+        const void *k = nullptr;
+        switch (v) {
+            case 0: k = list_kernel_ptr<0>(); break;
+            case 1: k = list_kernel_ptr<1>(); break;
+            case 2: k = list_kernel_ptr<2>(); break;
+            default: k = list_kernel_ptr<3>(); break;
+        }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        g = per_cu * device_cu_count();
+        if (g > kMaxPartials) g = kMaxPartials;
+    }
+    return g;
+}
+
+hipError_t launch_cross_list(int v, const EdgeRec *rec, const int32_t *list,
+                             const uint32_t *tile_off, int64_t n_tiles, int grid, double ideal,
+                             CrossPartial *part, hipStream_t st) {
+#define RB_LCASE(V)                                                                       \
+    case V:                                                                               \
+        hipLaunchKernelGGL((cross_list_kernel<CrossV<V>::K, CrossV<V>::W, true>), dim3(grid), \
+                           dim3(kBlock), 0, st, rec, list, tile_off, n_tiles, ideal, part);  \
+        break;
+    switch (v) {
+        RB_LCASE(0)
+        RB_LCASE(1)
+        RB_LCASE(2)
+        RB_LCASE(3)
+        default: return hipErrorInvalidValue;
+    }
+#undef RB_LCASE
+    return hipGetLastError();
 }
 
 hipError_t launch_cross_sweep(int v, bool angle, const EdgeRec *rec, const SweepArgs &a,

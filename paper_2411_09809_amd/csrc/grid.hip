@@ -11,6 +11,15 @@
 // paper instead maps each node to every cell its disc overlaps and removes
 // duplicate pairs afterwards; the half stencil needs no duplicate removal.
 //
+// Edge crossings with unit culling: every crossing pair of closed segments
+// has intersecting bounding boxes, so a (row tile, column chunk) unit of the
+// all-pairs sweep whose two boxes (the unions of their edges' boxes) are
+// disjoint holds no crossing and can be skipped.  To make the boxes small,
+// edges are first ordered along a Hilbert curve by their box centre, the
+// edges longer than 1/16 of the layout after the others in octave classes.  The kept units
+// run through the same sweep body as the brute-force path, so every count is
+// the brute-force count; only the order of the floating-point sum changes.
+//
 // The sort is a stable least-significant-digit radix sort of (key, value)
 // pairs with 8-bit digits written here: per-block digit histograms, one
 // exclusive scan over (digit, block), and a scatter that ranks items of equal
@@ -114,7 +123,15 @@ __global__ __launch_bounds__(256) void bounds_kernel(const float *__restrict__ x
         x1 = max(x1, __shfl_xor(x1, off, 64));
         y1 = max(y1, __shfl_xor(y1, off, 64));
     }
-    if ((threadIdx.x & 63) == 0) {
+    // one atomic per block and bound
+    __shared__ int4 w[4];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = make_int4(x0, y0, x1, y1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            x0 = min(x0, w[k].x); y0 = min(y0, w[k].y);
+            x1 = max(x1, w[k].z); y1 = max(y1, w[k].w);
+        }
         atomicMin(&gp->xmin, x0);
         atomicMin(&gp->ymin, y0);
         atomicMax(&gp->xmax, x1);
@@ -245,6 +262,154 @@ __global__ __launch_bounds__(256) void occl_grid_count_kernel(const uint32_t *__
     }
 }
 
+// index of cell (x, y) along the Hilbert curve over a 2^14 x 2^14 grid: cells
+// close on the curve are close in the plane, with none of the Morton
+// order's jumps, so a run of edges in this order has a compact box
+__device__ __forceinline__ uint32_t hilbert14(uint32_t x, uint32_t y) {
+    constexpr uint32_t n = 1u << 14;
+    uint32_t d = 0;
+    for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {                        // rotate the quadrant
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            const uint32_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
+}
+
+// key of an edge: edges whose box side is at most 1/16 of the layout's span
+// first, in Hilbert order of their box centre; longer edges after them in
+// classes by octave of their side (one long edge in a tile of short ones
+// would widen that tile's box), each class again in Hilbert order; edges
+// with bad ids after all others
+__global__ __launch_bounds__(256) void edge_key_kernel(const float *__restrict__ x,
+                                                       const float *__restrict__ y,
+                                                       const int32_t *__restrict__ src,
+                                                       const int32_t *__restrict__ dst,
+                                                       int64_t n_nodes, int64_t m,
+                                                       const GridParams *__restrict__ gp,
+                                                       uint32_t *__restrict__ keys,
+                                                       int32_t *__restrict__ vals) {
+    const int shift = gp->shift;
+    const long long x0 = gp->xmin, y0 = gp->ymin;
+    const long long span = max((long long)gp->xmax - x0, (long long)gp->ymax - y0);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = src[e], t = dst[e];
+        uint32_t key = 0xffffffffu;
+        if (dev::valid_ids(s, t, n_nodes)) {
+            const long long xs = (int)x[s], ys = (int)y[s], xt = (int)x[t], yt = (int)y[t];
+            const long long bx0 = min(xs, xt), bx1 = max(xs, xt);
+            const long long by0 = min(ys, yt), by1 = max(ys, yt);
+            const long long r = 16 * max(bx1 - bx0, by1 - by0);
+            uint32_t cls = 0;
+            while (span > 0 && cls < 7 && r > (span << cls)) ++cls;
+            const uint32_t cx = (uint32_t)((bx0 - x0 + bx1 - x0) >> (shift + 1));
+            const uint32_t cy = (uint32_t)((by0 - y0 + by1 - y0) >> (shift + 1));
+            key = (cls << 28) | hilbert14(cx & 0x3fffu, cy & 0x3fffu);
+        }
+        keys[e] = key;
+        vals[e] = (int32_t)e;
+    }
+}
+
+// bounding box of the edges of each 256-record chunk (padding records excluded)
+__global__ __launch_bounds__(256) void chunk_box_kernel(const EdgeRec *__restrict__ rec,
+                                                        int4 *__restrict__ box) {
+    const EdgeRec r = rec[(int64_t)blockIdx.x * 256 + threadIdx.x];
+    int x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
+    if (r.s >= 0) {
+        const int ax = (int)r.x, ay = (int)r.y;
+        const int bx = (int)(r.x + r.dx), by = (int)(r.y + r.dy);
+        x0 = min(ax, bx); x1 = max(ax, bx);
+        y0 = min(ay, by); y1 = max(ay, by);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        x0 = min(x0, __shfl_xor(x0, off, 64));
+        y0 = min(y0, __shfl_xor(y0, off, 64));
+        x1 = max(x1, __shfl_xor(x1, off, 64));
+        y1 = max(y1, __shfl_xor(y1, off, 64));
+    }
+    __shared__ int4 w[4];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = make_int4(x0, y0, x1, y1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int4 b = w[0];
+        for (int k = 1; k < 4; ++k) {
+            b.x = min(b.x, w[k].x); b.y = min(b.y, w[k].y);
+            b.z = max(b.z, w[k].z); b.w = max(b.w, w[k].w);
+        }
+        box[blockIdx.x] = b;
+    }
+}
+
+__device__ __forceinline__ int4 tile_box(const int4 *__restrict__ box, int64_t I, int K,
+                                         int64_t n_chunks) {
+    int4 b = make_int4(INT_MAX, INT_MAX, INT_MIN, INT_MIN);
+    for (int64_t c = I * K; c < min((I + 1) * K, n_chunks); ++c) {
+        const int4 q = box[c];
+        b.x = min(b.x, q.x); b.y = min(b.y, q.y);
+        b.z = max(b.z, q.z); b.w = max(b.w, q.w);
+    }
+    return b;
+}
+
+// a unit is kept if its chunk overlaps the tile itself or the closed boxes meet
+__device__ __forceinline__ bool keep_unit(const int4 *__restrict__ box, int4 tb, int64_t I,
+                                          int K, int64_t c) {
+    if (c < (I + 1) * K) return true;
+    const int4 q = box[c];
+    return q.x <= tb.z && tb.x <= q.z && q.y <= tb.w && tb.y <= q.w;
+}
+
+// one block per row tile: number of kept chunks
+__global__ __launch_bounds__(256) void tile_count_kernel(const int4 *__restrict__ box,
+                                                         int64_t n_chunks, int K,
+                                                         uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t red[4];
+    const int64_t I = blockIdx.x;
+    const int4 tb = tile_box(box, I, K, n_chunks);
+    uint32_t k = 0;
+    for (int64_t c = I * K + threadIdx.x; c < n_chunks; c += 256)
+        k += keep_unit(box, tb, I, K, c) ? 1u : 0u;
+    for (int off = 32; off > 0; off >>= 1) k += __shfl_xor(k, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[I] = red[0] + red[1] + red[2] + red[3];
+}
+
+// one block per row tile: the kept chunks in increasing order
+__global__ __launch_bounds__(256) void tile_fill_kernel(const int4 *__restrict__ box,
+                                                        int64_t n_chunks, int K,
+                                                        const uint32_t *__restrict__ off,
+                                                        int32_t *__restrict__ list) {
+    __shared__ uint32_t wsum[4];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t I = blockIdx.x;
+    const int4 tb = tile_box(box, I, K, n_chunks);
+    int64_t base = off[I];
+    for (int64_t c0 = I * K; c0 < n_chunks; c0 += 256) {
+        const int64_t c = c0 + tid;
+        const bool keep = c < n_chunks && keep_unit(box, tb, I, K, c);
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
+        if (lane == 0) wsum[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (keep) list[base + before + (uint32_t)__popcll(m & below)] = (int32_t)c;
+        base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+}
+
 __global__ void set_count_kernel(unsigned long long *out, unsigned long long v) {
     if (threadIdx.x == 0) *out = v;
 }
@@ -286,6 +451,18 @@ bool grid_ws_layout(int64_t n_nodes, int64_t n_edges, GridWs *G) {
     G->hist_off = take(sizeof(uint32_t) * (n_hist + 1));
     G->scan_tile = take(sizeof(unsigned long long) * ((n_hist + 2047) / 2048 + 1));
     G->partial = take(sizeof(CrossPartial) * kMaxPartials);
+    // pruned edge sweep: records, chunk boxes, per-tile counts and offsets and
+    // the unit list, sized for the smallest row tile (256 edges), which has
+    // the most units
+    const int64_t me = std::max<int64_t>(n_edges, 1);
+    G->n_edge_pad = (me + kRecPad - 1) / kRecPad * kRecPad;
+    const int64_t n_chunks = G->n_edge_pad / kChunk;
+    G->max_units = n_edges <= kMaxPrunedEdges ? sweep_units(me, 1) : 0;
+    G->rec = take(sizeof(EdgeRec) * G->n_edge_pad);
+    G->box = take(sizeof(int4) * n_chunks);
+    G->tile_cnt = take(sizeof(uint32_t) * n_chunks);
+    G->tile_off = take(sizeof(uint32_t) * (n_chunks + 1));
+    G->list = take(sizeof(int32_t) * std::max<int64_t>(G->max_units, 1));
     G->n_sort_blocks = nb;
     G->total = off;
     return true;
@@ -322,6 +499,53 @@ hipError_t launch_grid_bounds(const float *x, const float *y, int64_t n, GridPar
     }
     hipLaunchKernelGGL(grid_shift_kernel, dim3(1), dim3(64), 0, st, gp, min_shift, axis_bits);
     return hipGetLastError();
+}
+
+hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_nodes,
+                                  const int32_t *src, const int32_t *dst, int64_t m,
+                                  double ideal, const GridWs &G, char *w, int variant,
+                                  double *out_metric, unsigned long long *out_count,
+                                  double *out_dev_sum, hipStream_t st) {
+    GridParams *gp = (GridParams *)(w + G.params);
+    uint32_t *keys = (uint32_t *)(w + G.keys);
+    int32_t *vals = (int32_t *)(w + G.vals);
+    EdgeRec *rec = (EdgeRec *)(w + G.rec);
+    int4 *box = (int4 *)(w + G.box);
+    uint32_t *cnt = (uint32_t *)(w + G.tile_cnt);
+    uint32_t *toff = (uint32_t *)(w + G.tile_off);
+    int32_t *list = (int32_t *)(w + G.list);
+    const int K = cross_variant(variant).rows;
+    const SweepLayout lay = sweep_layout(m, K, 0, 0);
+    // order: size class, then Morton code of the box centre on <= 2^14 cells per axis
+    RB_TRY(launch_grid_bounds(x, y, n_nodes, gp, 0, 14, st));
+    const int32_t *order = nullptr;
+    if (m > 0) {
+        hipLaunchKernelGGL(edge_key_kernel, dim3(blocks_for(m)), dim3(256), 0, st, x, y, src, dst,
+                           n_nodes, m, gp, keys, vals);
+        RB_TRY(hipGetLastError());
+        RB_TRY(launch_radix_sort(keys, vals, (uint32_t *)(w + G.keys2),
+                                 (int32_t *)(w + G.vals2), m, (uint32_t *)(w + G.hist),
+                                 (uint32_t *)(w + G.hist_off),
+                                 (unsigned long long *)(w + G.scan_tile), st));
+        order = vals;
+    }
+    RB_TRY(launch_edge_prep_ordered(x, y, src, dst, n_nodes, m, G.n_edge_pad, order, rec, st));
+    // boxes of every chunk of the padded records (trailing ones are empty)
+    hipLaunchKernelGGL(chunk_box_kernel, dim3((unsigned)(G.n_edge_pad / kChunk)), dim3(256), 0,
+                       st, rec, box);
+    RB_TRY(hipGetLastError());
+    hipLaunchKernelGGL(tile_count_kernel, dim3((unsigned)lay.n_row_tiles), dim3(256), 0, st, box,
+                       lay.n_chunks, K, cnt);
+    RB_TRY(hipGetLastError());
+    RB_TRY(launch_scan(cnt, lay.n_row_tiles, (unsigned long long *)(w + G.scan_tile), toff, st));
+    hipLaunchKernelGGL(tile_fill_kernel, dim3((unsigned)lay.n_row_tiles), dim3(256), 0, st, box,
+                       lay.n_chunks, K, toff, list);
+    RB_TRY(hipGetLastError());
+    const int grid = cross_list_grid(variant);
+    CrossPartial *part = (CrossPartial *)(w + G.partial);
+    RB_TRY(launch_cross_list(variant, rec, list, toff, lay.n_row_tiles, grid, ideal, part, st));
+    return launch_cross_finalize(part, grid, ideal, out_count, nullptr, out_metric, out_dev_sum,
+                                 st);
 }
 
 hipError_t launch_occlusion_grid(const float *x, const float *y, int64_t n, double T,

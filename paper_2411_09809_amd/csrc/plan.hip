@@ -34,8 +34,8 @@ int64_t sweep_units(int64_t n_items, int rows) {
 namespace {
 
 constexpr int kClasses = 40;
-constexpr int kKinds = 3;            // 0 crossing, 1 crossing + angle, 2 occlusion
-constexpr int kDefault[kKinds] = {1, 1, 0};
+constexpr int kKinds = 4;   // 0 crossing, 1 crossing + angle, 2 occlusion, 3 pruned crossing
+constexpr int kDefault[kKinds] = {1, 1, 0, 0};
 
 struct Table {
     std::mutex mu;
@@ -66,10 +66,14 @@ void load_locked(const char *path) {
     fclose(f);
 }
 
+// the built-in default of a kind and size class: the pruned sweep takes the
+// 1-row tiles (tightest boxes) below 2^17 edges and 2-row tiles above
+int default_variant(int k, int c) { return (k == 3 && c >= 17) ? 1 : kDefault[k]; }
+
 void defaults_locked() {
     for (int k = 0; k < kKinds; ++k)
         for (int b = 0; b < 2; ++b)
-            for (int c = 0; c < kClasses; ++c) g_tab.v[k][b][c] = kDefault[k];
+            for (int c = 0; c < kClasses; ++c) g_tab.v[k][b][c] = default_variant(k, c);
 }
 
 void init_locked() {
@@ -102,7 +106,8 @@ bool save_tuning(const char *path) {
     for (int k = 0; k < kKinds; ++k)
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < kClasses; ++c)
-                if (g_tab.v[k][b][c] != kDefault[k]) fprintf(f, "%d %d %d %d\n", k, b, c, g_tab.v[k][b][c]);
+                if (g_tab.v[k][b][c] != default_variant(k, c))
+                    fprintf(f, "%d %d %d %d\n", k, b, c, g_tab.v[k][b][c]);
     return fclose(f) == 0;
 }
 

@@ -12,12 +12,18 @@ __global__ __launch_bounds__(256) void edge_prep_kernel(const float *__restrict_
                                                         const int32_t *__restrict__ src,
                                                         const int32_t *__restrict__ dst,
                                                         int64_t n_nodes, int64_t n_edges,
-                                                        int64_t n_pad, EdgeRec *__restrict__ rec) {
+                                                        int64_t n_pad,
+                                                        const int32_t *__restrict__ order,
+                                                        EdgeRec *__restrict__ rec) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_pad;
          e += (int64_t)gridDim.x * blockDim.x) {
         EdgeRec r;
-        const int32_t s = e < n_edges ? src[e] : -1;
-        const int32_t t = e < n_edges ? dst[e] : -1;
+        // record e holds edge order[e] when an order is given (a permutation
+        // of the edge ids), else edge e
+        const int64_t k = (order && e < n_edges) ? (int64_t)order[e] : e;
+        const bool in = e < n_edges && k >= 0 && k < n_edges;
+        const int32_t s = in ? src[k] : -1;
+        const int32_t t = in ? dst[k] : -1;
         // ids out of range (a precondition violation) become padding edges
         if (s >= 0 && t >= 0 && s < n_nodes && t < n_nodes) {
             const double px = x[s], py = y[s];
@@ -78,8 +84,15 @@ int grid_for(int64_t n) {
 hipError_t launch_edge_prep(const float *x, const float *y, const int32_t *src,
                             const int32_t *dst, int64_t n_nodes, int64_t n_edges, int64_t n_pad,
                             EdgeRec *rec, hipStream_t st) {
+    return launch_edge_prep_ordered(x, y, src, dst, n_nodes, n_edges, n_pad, nullptr, rec, st);
+}
+
+hipError_t launch_edge_prep_ordered(const float *x, const float *y, const int32_t *src,
+                                    const int32_t *dst, int64_t n_nodes, int64_t n_edges,
+                                    int64_t n_pad, const int32_t *order, EdgeRec *rec,
+                                    hipStream_t st) {
     hipLaunchKernelGGL(edge_prep_kernel, dim3(grid_for(n_pad)), dim3(256), 0, st, x, y, src,
-                       dst, n_nodes, n_edges, n_pad, rec);
+                       dst, n_nodes, n_edges, n_pad, order, rec);
     return hipGetLastError();
 }
 

@@ -103,9 +103,12 @@ struct __align__(16) GridParams {
 };
 struct GridWs {
     size_t params, keys, vals, keys2, vals2, pos, hist, hist_off, scan_tile, partial;
+    size_t rec, box, tile_cnt, tile_off, list;   // pruned edge sweep
     size_t total;
-    int64_t n_sort_blocks;
+    int64_t n_sort_blocks, n_edge_pad, max_units;
 };
+// largest edge count of the pruned edge sweep (its unit list is indexed in 32 bits)
+constexpr int64_t kMaxPrunedEdges = 1ll << 24;
 bool grid_ws_layout(int64_t n_nodes, int64_t n_edges, GridWs *G);
 
 // Small device scalars used between kernels of one call.
@@ -141,6 +144,10 @@ int occl_grid(int variant);
 hipError_t launch_edge_prep(const float *x, const float *y, const int32_t *src,
                             const int32_t *dst, int64_t n_nodes, int64_t n_edges, int64_t n_pad,
                             EdgeRec *rec, hipStream_t st);
+hipError_t launch_edge_prep_ordered(const float *x, const float *y, const int32_t *src,
+                                    const int32_t *dst, int64_t n_nodes, int64_t n_edges,
+                                    int64_t n_pad, const int32_t *order, EdgeRec *rec,
+                                    hipStream_t st);
 hipError_t launch_node_prep(const float *x, const float *y, int64_t n_nodes, int64_t n_pad,
                             double T, NodeRec *rec, hipStream_t st);
 
@@ -180,6 +187,17 @@ hipError_t launch_radix_sort(uint32_t *keys, int32_t *vals, uint32_t *keys2, int
                              unsigned long long *scan_tile, hipStream_t st);
 hipError_t launch_grid_bounds(const float *x, const float *y, int64_t n, GridParams *gp,
                               int min_shift, int axis_bits, hipStream_t st);
+// Sweep over an explicit unit list: tile I meets chunks list[tile_off[I] ..
+// tile_off[I+1]) (cross.hip).
+int cross_list_grid(int variant);
+hipError_t launch_cross_list(int variant, const EdgeRec *rec, const int32_t *list,
+                             const uint32_t *tile_off, int64_t n_tiles, int grid, double ideal,
+                             CrossPartial *part, hipStream_t st);
+hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_nodes,
+                                  const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                  double ideal, const GridWs &G, char *w, int variant,
+                                  double *out_metric, unsigned long long *out_count,
+                                  double *out_dev_sum, hipStream_t st);
 hipError_t launch_occlusion_grid(const float *x, const float *y, int64_t n, double T,
                                  const GridWs &G, char *w, unsigned long long *out_count,
                                  hipStream_t st);

@@ -179,6 +179,25 @@ def node_occlusion_grid(x, y, diameter: float, *, async_: bool = False):
     return out if async_ else int(out.item())
 
 
+def crossing_angle_pruned(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, *,
+                          async_: bool = False):
+    """(E_ca, E_c, sum of |ideal - a|/ideal) as ``crossing_angle``, skipping
+    tiles of edges whose bounding boxes cannot meet."""
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    out = _out(3, torch.float64, x.device)
+    ws = grid_workspace(x.numel(), src.numel(), x.device)
+    w, wb = _ws_args(ws)
+    p = _ptr(out)
+    check(lib().rb_crossing_angle_pruned(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst),
+                                         src.numel(), float(ideal_angle), p, p + 8, p + 16, w,
+                                         wb, _stream(x.device)), "rb_crossing_angle_pruned")
+    if async_:
+        return out
+    vals = out.cpu()
+    return float(vals[0]), int(vals.view(torch.int64)[1]), float(vals[2])
+
+
 def crossing_angle_shard(x, y, src, dst, shard: int, n_shards: int,
                          ideal_angle: float = IDEAL_ANGLE):
     """(crossings, sum of |ideal - a|/ideal, row_begin, row_end) of shard k

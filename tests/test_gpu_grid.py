@@ -112,3 +112,93 @@ def test_short_workspace_is_an_error(torch_mod):
                                     need - 256, metrics._stream(x.device))
     assert rc == 2                      # RB_EWORKSPACE
     assert b"workspace" in lib.rb_last_error()
+
+
+# ------------------------------------------------------------ pruned crossings
+
+def _both(metrics, D, ideal=gen.IDEAL_ANGLE):
+    brute = metrics.crossing_angle(D.x, D.y, D.src, D.dst, ideal)
+    pruned = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, ideal)
+    return brute, pruned
+
+
+def _same(brute, pruned):
+    assert pruned[1] == brute[1]
+    assert pruned[2] == pytest.approx(brute[2], rel=1e-9, abs=1e-12)
+    assert pruned[0] == pytest.approx(brute[0], rel=1e-9, abs=1e-12)
+
+
+def _hand_layouts():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "hand_cases.json")
+    for c in json.load(open(path))["cases"]:
+        if "edges" not in c:                    # node-only (lattice) cases
+            continue
+        e = np.array(c["edges"], dtype=np.int64).reshape(-1, 2)
+        yield c["name"], gen._finish(np.array(c["x"]), np.array(c["y"]), e[:, 0], e[:, 1],
+                                     diameter=1.0, name=c["name"])
+
+
+def test_pruned_hand_cases(torch_mod):
+    from paper_2411_09809_amd import metrics
+    for name, L in _hand_layouts():
+        if L.n_edges == 0:
+            continue
+        D = metrics.DeviceLayout.from_host(L)
+        eca, cnt, dev = oracle.crossing_angle(L.x, L.y, L.src, L.dst, gen.IDEAL_ANGLE)
+        p = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst)
+        assert p[1] == cnt, name
+        assert p[0] == pytest.approx(eca, rel=1e-9, abs=1e-12), name
+
+
+@pytest.mark.parametrize("V,E,extent,seed", [(300, 700, 64, 1), (2000, 5000, 4096, 2),
+                                             (5000, 2, 100, 3), (3000, 7000, 1 << 20, 4),
+                                             (50, 1, 10, 5)])
+def test_pruned_uniform_vs_oracle(torch_mod, V, E, extent, seed):
+    from paper_2411_09809_amd import metrics
+    L = gen.uniform_layout(V, E, extent=extent, seed=seed)
+    D = metrics.DeviceLayout.from_host(L)
+    eca, cnt, dev = oracle.crossing_angle(L.x, L.y, L.src, L.dst, gen.IDEAL_ANGLE)
+    brute, pruned = _both(metrics, D)
+    assert brute[1] == cnt
+    _same(brute, pruned)
+    assert pruned[2] == pytest.approx(dev, rel=1e-9, abs=1e-12)
+
+
+def test_pruned_local_edges(torch_mod):
+    """Short edges on a large canvas (most tiles skipped), negative
+    coordinates, collinear and touching configurations."""
+    from paper_2411_09809_amd import metrics
+    rng = np.random.default_rng(7)
+    n = 40000
+    x = rng.integers(-(1 << 19), 1 << 19, n)
+    y = rng.integers(-(1 << 19), 1 << 19, n)
+    # each node linked to a few near neighbours along x
+    order = np.lexsort((y, x))
+    src = np.concatenate([order[:-1], order[:-2]])
+    dst = np.concatenate([order[1:], order[2:]])
+    L = gen._finish(x, y, src, dst, diameter=1.0, name="local")
+    D = metrics.DeviceLayout.from_host(L)
+    brute, pruned = _both(metrics, D)
+    say(f"[pruned] local: E_c={brute[1]}")
+    _same(brute, pruned)
+    # a crowded lattice of collinear and touching segments
+    L = gen.uniform_layout(600, 3000, extent=8, seed=9)
+    D = metrics.DeviceLayout.from_host(L)
+    brute, pruned = _both(metrics, D)
+    assert brute[1] == oracle.edge_crossing(L.x, L.y, L.src, L.dst)[0]
+    _same(brute, pruned)
+
+
+@pytest.mark.parametrize("name", ["rgg_V20000_E60000", "ba_cluster_V50000_E149994",
+                                  "powerlaw_V1000000_E3000000"])
+def test_pruned_full_size(torch_mod, name):
+    from paper_2411_09809_amd import metrics
+    L = gen.WORKLOADS[name](seed=0)
+    D = metrics.DeviceLayout.from_host(L)
+    brute, pruned = _both(metrics, D)
+    again = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst)
+    say(f"[pruned] {name}: E_c={brute[1]} E_ca={brute[0]:.12f} pruned E_ca={pruned[0]:.12f}")
+    _same(brute, pruned)
+    assert again == pruned                      # deterministic
