@@ -140,8 +140,12 @@ def bench_adjoint(torch, reps: int, gd_steps: int):
     def fwd_bwd():
         optim.loss_grad(D.x, D.y, D.src, D.dst)
 
+    def fwd_bwd_pruned():
+        optim.loss_grad(D.x, D.y, D.src, D.dst, pruned=True)
+
     out = {}
-    for name, fn in (("forward_ms", fwd), ("forward_backward_ms", fwd_bwd)):
+    for name, fn in (("forward_ms", fwd), ("forward_backward_ms", fwd_bwd),
+                     ("forward_backward_pruned_ms", fwd_bwd_pruned)):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -152,11 +156,18 @@ def bench_adjoint(torch, reps: int, gd_steps: int):
     t0 = time.perf_counter()
     _, _, hist = optim.descend(D.x, D.y, D.src, D.dst, steps=gd_steps, step_size=2.0)
     torch.cuda.synchronize()
+    gd_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, hist_p = optim.descend(D.x, D.y, D.src, D.dst, steps=gd_steps, step_size=2.0,
+                                 pruned=True)
+    torch.cuda.synchronize()
+    gd_pruned_s = time.perf_counter() - t0
     out.update({"workload": f"random geometric graph |V|={L.n_nodes} |E|={L.n_edges} in "
                             "[0,2^16)^2, ideal angle 70 deg",
                 "edge_pairs": pairs,
                 "backward_over_forward": out["forward_backward_ms"] / out["forward_ms"],
-                "gd_steps": gd_steps, "gd_total_s": time.perf_counter() - t0,
+                "gd_steps": gd_steps, "gd_total_s": gd_s, "gd_pruned_total_s": gd_pruned_s,
+                "gd_pruned_crossings_first_last": [hist_p[0][1], hist_p[-1][1]],
                 "gd_loss_first_last": [hist[0][0], hist[-1][0]],
                 "gd_crossings_first_last": [hist[0][1], hist[-1][1]]})
     return out

@@ -131,6 +131,15 @@ rb_status rb_crossing_angle_pruned(const float *x, const float *y, int64_t n_nod
                                    double ideal_angle, double *out_metric, uint64_t *out_count,
                                    double *out_dev_sum, void *ws, size_t ws_bytes,
                                    void *stream);
+/* rb_loss_grad_pruned: loss, gradient and crossing count as rb_loss_grad,
+ * with the same culled sweep (the per-edge integer adjoint sums are the same
+ * integers; the node gradients are the same sums added in another order).
+ * Uses the rb_grid_workspace_size workspace.  n_edges <= 2^24.            */
+rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
+                              const int32_t *src, const int32_t *dst, int64_t n_edges,
+                              double ideal_angle, double w_angle, double w_length,
+                              double *out_loss, double *out_grad_x, double *out_grad_y,
+                              uint64_t *out_count, void *ws, size_t ws_bytes, void *stream);
 
 /* Shards of the two all-pairs sweeps, for splitting one layout across
  * devices or processes (each computes its shards; the sums of the shard

@@ -44,6 +44,8 @@ _SIGS = {
     "rb_node_occlusion_grid": ([_vp, _vp, _i64, _f64, _vp, _vp, _sz, _vp], C.c_int),
     "rb_crossing_angle_pruned": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _vp, _vp, _vp, _vp, _sz,
                                   _vp], C.c_int),
+    "rb_loss_grad_pruned": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, _f64, _vp, _vp, _vp,
+                             _vp, _vp, _sz, _vp], C.c_int),
     "rb_crossing_angle_shard": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _i64, _i64, _vp, _vp,
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64), _vp, _sz, _vp],
                                 C.c_int),

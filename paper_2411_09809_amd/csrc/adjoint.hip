@@ -112,10 +112,13 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
     }
 }
 
-template <int K, int WAVES>
+// LIST: the units come from an explicit list (the pruned plan): tile I meets
+// chunks list[tile_off[I] .. tile_off[I+1]); its length is read on the device.
+template <int K, int WAVES, bool LIST>
 __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
-    const EdgeRec *__restrict__ rec, SweepLayout lay, int64_t n_units, double ideal,
-    int *__restrict__ kacc, CrossPartial *__restrict__ part) {
+    const EdgeRec *__restrict__ rec, SweepLayout lay, int64_t n_units,
+    const int32_t *__restrict__ list, const uint32_t *__restrict__ tile_off, int64_t n_tiles,
+    double ideal, int *__restrict__ kacc, CrossPartial *__restrict__ part) {
     __shared__ EdgeRec col[kChunk];
     __shared__ int2 rid[kBlock * K];
     __shared__ int colk[(kBlock / 64) * kChunk];
@@ -123,18 +126,20 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     __shared__ double red_d[kBlock / 64];
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t u_begin = block_first_unit(n_units, G, b);
-    const int64_t u_end = block_first_unit(n_units, G, b + 1);
+    const int64_t U = LIST ? (int64_t)tile_off[n_tiles] : n_units;
+    const int64_t u_begin = block_first_unit(U, G, b);
+    const int64_t u_end = block_first_unit(U, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
-    int64_t lo = 0, hi = lay.n_row_tiles - 1;
+    int64_t lo = 0, hi = (LIST ? n_tiles : lay.n_row_tiles) - 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
-        if (units_before(mid, lay.n_chunks, K) <= u_begin) lo = mid;
+        const int64_t first = LIST ? (int64_t)tile_off[mid] : units_before(mid, lay.n_chunks, K);
+        if (first <= u_begin) lo = mid;
         else hi = mid - 1;
     }
     int64_t I = lo;
-    int64_t c = I * K + (u_begin - units_before(I, lay.n_chunks, K));
+    int64_t c = LIST ? 0 : I * K + (u_begin - units_before(I, lay.n_chunks, K));
     double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
     int kr[K];
     bool rows_loaded = false;
@@ -150,6 +155,14 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     };
 
     for (int64_t u = u_begin; u < u_end; ++u) {
+        if (LIST) {
+            while ((int64_t)tile_off[I + 1] <= u) {   // u < tile_off[n_tiles]: stops in range
+                if (rows_loaded) flush_rows();
+                ++I;
+                rows_loaded = false;
+            }
+            c = list[u];
+        }
         __syncthreads();                      // previous chunk, ids and column sums consumed
         if (!rows_loaded) {
 #pragma unroll
@@ -181,7 +194,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
             for (int w = 0; w < kBlock / 64; ++w) sum += colk[w * kChunk + tid];
             if (sum != 0) atomicSub(&kacc[col0 + tid], sum);
         }
-        if (++c == lay.n_chunks) {
+        if (!LIST && ++c == lay.n_chunks) {
             flush_rows();
             ++I;
             c = I * K;
@@ -213,10 +226,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
 
 // Chain rule per edge, scattered to the end nodes; thread 0 also writes the loss.
 __global__ __launch_bounds__(256) void edge_grad_kernel(
-    const EdgeRec *__restrict__ rec, const int *__restrict__ kacc, int64_t n_edges,
-    const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t n_nodes,
-    const Scalars *__restrict__ sc, double ideal, double w_a, double w_l, double *gx, double *gy,
-    double *out_loss) {
+    const EdgeRec *__restrict__ rec, const int *__restrict__ kacc, int64_t n_rec,
+    int64_t n_edges, const Scalars *__restrict__ sc, double ideal, double w_a, double w_l,
+    double *gx, double *gy, double *out_loss) {
     const unsigned long long S = sc->count;
     const double mu = sc->mean, ml = sc->ml, N = (double)n_edges;
     // population spread of the lengths, from M_l = s / mu / sqrt(N - 1)
@@ -224,15 +236,16 @@ __global__ __launch_bounds__(256) void edge_grad_kernel(
     const double ka = S ? w_a / (ideal * (double)S) : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0 && out_loss)
         *out_loss = (S ? w_a * (1.0 - sc->eca) : 0.0) + w_l * ml;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_edges;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t s = src[e], t = dst[e];
-        if (!dev::valid_ids(s, t, n_nodes)) continue;
-        const EdgeRec r = rec[e];
+    // one record per edge (in whatever order the sweep used); padding records
+    // and edges with bad ids carry s = t = -1
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n_rec;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const EdgeRec r = rec[p];
+        if (r.s < 0) continue;
         const double l2 = fma(r.dx, r.dx, r.dy * r.dy);
         if (l2 == 0.0) continue;                        // zero-length edge: no direction
         const double l = sqrt(l2);
-        const double gth = ka * (double)kacc[e] / l2;
+        const double gth = ka * (double)kacc[p] / l2;
         double gdx = -gth * r.dy, gdy = gth * r.dx;
         if (spread > 0.0 && mu > 0.0) {
             const double dml = w_l * ((l - mu) / (N * spread * mu) - spread / (N * mu * mu)) /
@@ -240,10 +253,10 @@ __global__ __launch_bounds__(256) void edge_grad_kernel(
             gdx = fma(dml, r.dx / l, gdx);
             gdy = fma(dml, r.dy / l, gdy);
         }
-        atomicAdd(&gx[t], gdx);
-        atomicAdd(&gy[t], gdy);
-        atomicAdd(&gx[s], -gdx);
-        atomicAdd(&gy[s], -gdy);
+        atomicAdd(&gx[r.t], gdx);
+        atomicAdd(&gy[r.t], gdy);
+        atomicAdd(&gx[r.s], -gdx);
+        atomicAdd(&gy[r.s], -gdy);
     }
 }
 
@@ -273,6 +286,7 @@ int grid_for(int64_t n) {
 
 constexpr int kAdjRows = 2, kAdjWaves = 4;
 int g_adj_grid = 0;
+int g_adj_list_grid = 0;
 
 #define RB_TRY(expr)                          \
     do {                                      \
@@ -306,15 +320,17 @@ hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, con
     if (g_adj_grid == 0) {
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, adjoint_sweep_kernel<kAdjRows, kAdjWaves>, kBlock, 0) != hipSuccess ||
+                &per_cu, adjoint_sweep_kernel<kAdjRows, kAdjWaves, false>, kBlock, 0) !=
+                hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         g_adj_grid = std::min(per_cu * device_cu_count(), kMaxPartials);
     }
     const int grid = (int)std::min<int64_t>(U, g_adj_grid);
     CrossPartial *part = (CrossPartial *)(w + L.partial);
-    hipLaunchKernelGGL((adjoint_sweep_kernel<kAdjRows, kAdjWaves>), dim3(grid), dim3(kBlock), 0,
-                       st, rec, lay, U, ideal, kacc, part);
+    hipLaunchKernelGGL((adjoint_sweep_kernel<kAdjRows, kAdjWaves, false>), dim3(grid),
+                       dim3(kBlock), 0, st, rec, lay, U, nullptr, nullptr, (int64_t)0, ideal, kacc,
+                       part);
     RB_TRY(hipGetLastError());
     RB_TRY(launch_cross_finalize(part, grid, ideal, fw_count, nullptr, fw_eca, nullptr, st));
     hipLaunchKernelGGL(stash_kernel, dim3(1), dim3(64), 0, st, sc, fw_count, fw_eca, fw_ml,
@@ -327,7 +343,55 @@ hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, con
     hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(V)), dim3(256), 0, st, gy, n_nodes);
     RB_TRY(hipGetLastError());
     hipLaunchKernelGGL(edge_grad_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, rec, kacc,
-                       n_edges, src, dst, n_nodes, sc, ideal, w_a, w_l, gx, gy, out_loss);
+                       n_edges, n_edges, sc, ideal, w_a, w_l, gx, gy, out_loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
+                                   const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                   double ideal, double w_a, double w_l, double *out_loss,
+                                   double *gx, double *gy, unsigned long long *out_count,
+                                   const GridWs &G, char *w, hipStream_t st) {
+    // the pruned plan (records in Hilbert order, unit list of 2-row tiles),
+    // then the same fused sweep over the kept units only
+    RB_TRY(launch_prune_plan(x, y, n_nodes, src, dst, n_edges, kAdjRows, G, w, st));
+    const EdgeRec *rec = (const EdgeRec *)(w + G.rec);
+    Scalars *sc = (Scalars *)(w + G.scalars);
+    int *kacc = (int *)(w + G.kacc);
+    unsigned long long *fw_count = (unsigned long long *)(w + G.fwd);
+    double *fw_eca = (double *)(w + G.fwd) + 1;
+    double *fw_ml = (double *)(w + G.fwd) + 2;
+    RB_TRY(launch_zero_scalars(sc, st));
+    RB_TRY(launch_elv(x, y, src, dst, n_nodes, n_edges, (double *)(w + G.partial), sc, fw_ml,
+                      nullptr, st));
+    RB_TRY(launch_fill_u32((uint32_t *)kacc, G.n_edge_pad, 0u, st));
+    if (g_adj_list_grid == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, adjoint_sweep_kernel<kAdjRows, kAdjWaves, true>, kBlock, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        g_adj_list_grid = std::min(per_cu * device_cu_count(), kMaxPartials);
+    }
+    const int grid = g_adj_list_grid;
+    const SweepLayout lay = sweep_layout(n_edges, kAdjRows, 0, 0);
+    CrossPartial *part = (CrossPartial *)(w + G.partial);
+    hipLaunchKernelGGL((adjoint_sweep_kernel<kAdjRows, kAdjWaves, true>), dim3(grid),
+                       dim3(kBlock), 0, st, rec, lay, (int64_t)0, (const int32_t *)(w + G.list),
+                       (const uint32_t *)(w + G.tile_off), lay.n_row_tiles, ideal, kacc, part);
+    RB_TRY(hipGetLastError());
+    RB_TRY(launch_cross_finalize(part, grid, ideal, fw_count, nullptr, fw_eca, nullptr, st));
+    hipLaunchKernelGGL(stash_kernel, dim3(1), dim3(64), 0, st, sc, fw_count, fw_eca, fw_ml,
+                       out_count);
+    RB_TRY(hipGetLastError());
+    const int64_t V = n_nodes > 0 ? n_nodes : 1;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(V)), dim3(256), 0, st, gx, n_nodes);
+    RB_TRY(hipGetLastError());
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(V)), dim3(256), 0, st, gy, n_nodes);
+    RB_TRY(hipGetLastError());
+    hipLaunchKernelGGL(edge_grad_kernel, dim3(grid_for(G.n_edge_pad)), dim3(256), 0, st, rec,
+                       kacc, G.n_edge_pad, n_edges, sc, ideal, w_a, w_l, gx, gy, out_loss);
     return hipGetLastError();
 }
 

@@ -514,6 +514,37 @@ rb_status rb_loss_grad(const float *x, const float *y, int64_t n_nodes, const in
     return RB_OK;
 }
 
+rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
+                              const int32_t *src, const int32_t *dst, int64_t n_edges,
+                              double ideal_angle, double w_angle, double w_length,
+                              double *out_loss, double *out_grad_x, double *out_grad_y,
+                              uint64_t *out_count, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (!out_loss || (n_nodes > 0 && (!out_grad_x || !out_grad_y)))
+        return fail(RB_EINVAL, "out_loss, out_grad_x or out_grad_y is NULL");
+    if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
+        return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
+    if (!std::isfinite(w_angle) || !std::isfinite(w_length))
+        return fail(RB_EINVAL, "weights must be finite");
+    if (n_edges > kMaxPrunedEdges)
+        return fail(RB_EINVAL, "n_edges = %lld above the pruned path's limit 2^24",
+                    (long long)n_edges);
+    GridWs G;
+    if (!grid_ws_layout(n_nodes, n_edges, &G)) return fail(RB_EINVAL, "layout too large");
+    if (!ws) return fail(RB_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(RB_EWORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < G.total)
+        return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, G.total);
+    hipError_t e = launch_loss_grad_pruned(x, y, n_nodes, src, dst, n_edges, ideal_angle,
+                                           w_angle, w_length, out_loss, out_grad_x, out_grad_y,
+                                           (unsigned long long *)out_count, G, (char *)ws,
+                                           (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rb_loss_grad_pruned launch");
+    return RB_OK;
+}
+
 rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                              const int32_t *dst, int64_t n_edges, int32_t *out_flags, void *ws,
                              size_t ws_bytes, void *stream) {

@@ -463,6 +463,9 @@ bool grid_ws_layout(int64_t n_nodes, int64_t n_edges, GridWs *G) {
     G->tile_cnt = take(sizeof(uint32_t) * n_chunks);
     G->tile_off = take(sizeof(uint32_t) * (n_chunks + 1));
     G->list = take(sizeof(int32_t) * std::max<int64_t>(G->max_units, 1));
+    G->kacc = take(sizeof(int32_t) * G->n_edge_pad);
+    G->scalars = take(sizeof(Scalars));
+    G->fwd = take(sizeof(double) * 4);
     G->n_sort_blocks = nb;
     G->total = off;
     return true;
@@ -501,11 +504,9 @@ hipError_t launch_grid_bounds(const float *x, const float *y, int64_t n, GridPar
     return hipGetLastError();
 }
 
-hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_nodes,
-                                  const int32_t *src, const int32_t *dst, int64_t m,
-                                  double ideal, const GridWs &G, char *w, int variant,
-                                  double *out_metric, unsigned long long *out_count,
-                                  double *out_dev_sum, hipStream_t st) {
+hipError_t launch_prune_plan(const float *x, const float *y, int64_t n_nodes,
+                             const int32_t *src, const int32_t *dst, int64_t m, int K,
+                             const GridWs &G, char *w, hipStream_t st) {
     GridParams *gp = (GridParams *)(w + G.params);
     uint32_t *keys = (uint32_t *)(w + G.keys);
     int32_t *vals = (int32_t *)(w + G.vals);
@@ -514,9 +515,8 @@ hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_node
     uint32_t *cnt = (uint32_t *)(w + G.tile_cnt);
     uint32_t *toff = (uint32_t *)(w + G.tile_off);
     int32_t *list = (int32_t *)(w + G.list);
-    const int K = cross_variant(variant).rows;
     const SweepLayout lay = sweep_layout(m, K, 0, 0);
-    // order: size class, then Morton code of the box centre on <= 2^14 cells per axis
+    // order: Hilbert index of the box centre on <= 2^14 cells per axis
     RB_TRY(launch_grid_bounds(x, y, n_nodes, gp, 0, 14, st));
     const int32_t *order = nullptr;
     if (m > 0) {
@@ -540,10 +540,21 @@ hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_node
     RB_TRY(launch_scan(cnt, lay.n_row_tiles, (unsigned long long *)(w + G.scan_tile), toff, st));
     hipLaunchKernelGGL(tile_fill_kernel, dim3((unsigned)lay.n_row_tiles), dim3(256), 0, st, box,
                        lay.n_chunks, K, toff, list);
-    RB_TRY(hipGetLastError());
+    return hipGetLastError();
+}
+
+hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_nodes,
+                                  const int32_t *src, const int32_t *dst, int64_t m,
+                                  double ideal, const GridWs &G, char *w, int variant,
+                                  double *out_metric, unsigned long long *out_count,
+                                  double *out_dev_sum, hipStream_t st) {
+    const int K = cross_variant(variant).rows;
+    RB_TRY(launch_prune_plan(x, y, n_nodes, src, dst, m, K, G, w, st));
     const int grid = cross_list_grid(variant);
     CrossPartial *part = (CrossPartial *)(w + G.partial);
-    RB_TRY(launch_cross_list(variant, rec, list, toff, lay.n_row_tiles, grid, ideal, part, st));
+    RB_TRY(launch_cross_list(variant, (const EdgeRec *)(w + G.rec), (const int32_t *)(w + G.list),
+                             (const uint32_t *)(w + G.tile_off), sweep_layout(m, K, 0, 0).n_row_tiles,
+                             grid, ideal, part, st));
     return launch_cross_finalize(part, grid, ideal, out_count, nullptr, out_metric, out_dev_sum,
                                  st);
 }

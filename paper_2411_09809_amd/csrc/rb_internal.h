@@ -104,6 +104,7 @@ struct __align__(16) GridParams {
 struct GridWs {
     size_t params, keys, vals, keys2, vals2, pos, hist, hist_off, scan_tile, partial;
     size_t rec, box, tile_cnt, tile_off, list;   // pruned edge sweep
+    size_t kacc, scalars, fwd;                    // pruned loss and gradient
     size_t total;
     int64_t n_sort_blocks, n_edge_pad, max_units;
 };
@@ -193,6 +194,16 @@ int cross_list_grid(int variant);
 hipError_t launch_cross_list(int variant, const EdgeRec *rec, const int32_t *list,
                              const uint32_t *tile_off, int64_t n_tiles, int grid, double ideal,
                              CrossPartial *part, hipStream_t st);
+// Plan of the pruned edge sweep: records in Hilbert order, chunk boxes and the
+// unit list of tiles of 256*K edges (grid.hip).
+hipError_t launch_prune_plan(const float *x, const float *y, int64_t n_nodes,
+                             const int32_t *src, const int32_t *dst, int64_t m, int K,
+                             const GridWs &G, char *w, hipStream_t st);
+hipError_t launch_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
+                                   const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                   double ideal, double w_a, double w_l, double *out_loss,
+                                   double *gx, double *gy, unsigned long long *out_count,
+                                   const GridWs &G, char *w, hipStream_t st);
 hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_nodes,
                                   const int32_t *src, const int32_t *dst, int64_t n_edges,
                                   double ideal, const GridWs &G, char *w, int variant,

@@ -15,13 +15,15 @@ import time
 import torch
 
 from ._lib import check, lib
-from .metrics import IDEAL_ANGLE, _check_coords, _check_edges, _stream, _ws_args, workspace
+from .metrics import (IDEAL_ANGLE, _check_coords, _check_edges, _stream, _ws_args, grid_workspace,
+                      workspace)
 
 
 def loss_grad(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, w_angle: float = 1.0,
-              w_length: float = 1.0):
+              w_length: float = 1.0, pruned: bool = False):
     """(loss, dL/dx, dL/dy, crossing count) as device tensors (float64,
-    float64[V], float64[V], int64)."""
+    float64[V], float64[V], int64).  ``pruned`` uses rb_loss_grad_pruned,
+    which skips the tiles of edges whose bounding boxes cannot meet."""
     _check_coords(x, y)
     _check_edges(x, src, dst)
     dev = x.device
@@ -30,12 +32,13 @@ def loss_grad(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, w_angle: float =
     gx = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     gy = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
-    ws = workspace(n, src.numel(), dev)
+    ws = (grid_workspace if pruned else workspace)(n, src.numel(), dev)
     w, wb = _ws_args(ws)
-    check(lib().rb_loss_grad(x.data_ptr(), y.data_ptr(), n, src.data_ptr(), dst.data_ptr(),
-                             src.numel(), float(ideal_angle), float(w_angle), float(w_length),
-                             loss.data_ptr(), gx.data_ptr(), gy.data_ptr(), cnt.data_ptr(), w, wb,
-                             _stream(dev)), "rb_loss_grad")
+    fn, name = ((lib().rb_loss_grad_pruned, "rb_loss_grad_pruned") if pruned
+                else (lib().rb_loss_grad, "rb_loss_grad"))
+    check(fn(x.data_ptr(), y.data_ptr(), n, src.data_ptr(), dst.data_ptr(), src.numel(),
+             float(ideal_angle), float(w_angle), float(w_length), loss.data_ptr(), gx.data_ptr(),
+             gy.data_ptr(), cnt.data_ptr(), w, wb, _stream(dev)), name)
     return loss[0], gx[:n], gy[:n], cnt[0]
 
 
@@ -44,8 +47,9 @@ class CrossingAngleLengthLoss(torch.autograd.Function):
     coordinates; gradients come back in the coordinates' dtype."""
 
     @staticmethod
-    def forward(ctx, x, y, src, dst, ideal_angle=IDEAL_ANGLE, w_angle=1.0, w_length=1.0):
-        loss, gx, gy, cnt = loss_grad(x, y, src, dst, ideal_angle, w_angle, w_length)
+    def forward(ctx, x, y, src, dst, ideal_angle=IDEAL_ANGLE, w_angle=1.0, w_length=1.0,
+                pruned=False):
+        loss, gx, gy, cnt = loss_grad(x, y, src, dst, ideal_angle, w_angle, w_length, pruned)
         ctx.save_for_backward(gx, gy)
         ctx.dtype = x.dtype
         ctx.mark_non_differentiable(cnt)
@@ -55,12 +59,12 @@ class CrossingAngleLengthLoss(torch.autograd.Function):
     def backward(ctx, g_loss, g_cnt):
         gx, gy = ctx.saved_tensors
         return ((g_loss * gx).to(ctx.dtype), (g_loss * gy).to(ctx.dtype), None, None, None, None,
-                None)
+                None, None)
 
 
 def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
             extent: int = 1 << 16, ideal_angle: float = IDEAL_ANGLE, w_angle: float = 1.0,
-            w_length: float = 1.0, log=None):
+            w_length: float = 1.0, log=None, pruned: bool = False):
     """Gradient descent on the readability loss.
 
     A float32 master copy of the coordinates moves by ``step_size`` grid
@@ -76,7 +80,7 @@ def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
         xi = torch.clamp(torch.round(mx), 0, extent - 1).requires_grad_(True)
         yi = torch.clamp(torch.round(my), 0, extent - 1).requires_grad_(True)
         loss, cnt = CrossingAngleLengthLoss.apply(xi, yi, src, dst, ideal_angle, w_angle,
-                                                  w_length)
+                                                  w_length, pruned)
         loss.backward()
         with torch.no_grad():
             scale = torch.maximum(xi.grad.abs().max(), yi.grad.abs().max()).clamp_min(1e-300)

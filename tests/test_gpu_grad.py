@@ -160,3 +160,44 @@ def test_descent_steps_keep_exact_counts(torch_mod):
     c, _ = oracle.edge_crossing(xf, yf, L.src, L.dst)
     assert metrics.edge_crossing(xs.contiguous(), ys.contiguous(), D.src, D.dst)[0] == c
     assert min(h[0] for h in hist[1:]) < hist[0][0]      # the loss went down
+
+
+@pytest.mark.parametrize("V,E,extent,seed", [(300, 700, 64, 1), (2000, 5000, 4096, 2)])
+def test_pruned_loss_grad_matches_plain(torch_mod, V, E, extent, seed):
+    """rb_loss_grad_pruned: the same loss and count, and the same gradient
+    up to the order of the floating-point additions."""
+    from paper_2411_09809_amd import metrics, optim
+    L = gen.uniform_layout(V, E, extent=extent, seed=seed)
+    D = metrics.DeviceLayout.from_host(L)
+    f, gx, gy, c = optim.loss_grad(D.x, D.y, D.src, D.dst, IDEAL, 0.8, 1.3)
+    fp, gxp, gyp, cp = optim.loss_grad(D.x, D.y, D.src, D.dst, IDEAL, 0.8, 1.3, pruned=True)
+    assert int(cp) == int(c)
+    assert float(fp) == pytest.approx(float(f), rel=1e-12)
+    scale = max(float(gx.abs().max()), float(gy.abs().max()))
+    np.testing.assert_allclose(gxp.cpu().numpy(), gx.cpu().numpy(), rtol=1e-9, atol=1e-12 * scale)
+    np.testing.assert_allclose(gyp.cpu().numpy(), gy.cpu().numpy(), rtol=1e-9, atol=1e-12 * scale)
+
+
+def test_pruned_loss_grad_rgg_vs_oracle(torch_mod):
+    from paper_2411_09809_amd import metrics, optim
+    L = gen.geometric_layout(seed=0)
+    D = metrics.DeviceLayout.from_host(L)
+    S = oracle.crossing_pairs(L.x, L.y, L.src, L.dst)
+    f_ref, gx_ref, gy_ref = oracle.loss_grad(L.x, L.y, L.src, L.dst, S, IDEAL)
+    f, gx, gy, cnt = optim.loss_grad(D.x, D.y, D.src, D.dst, IDEAL, pruned=True)
+    assert int(cnt) == S.shape[0]
+    assert float(f) == pytest.approx(f_ref, rel=1e-12)
+    gx, gy = gx.cpu().numpy(), gy.cpu().numpy()
+    assert close(gx, gx_ref).all() and close(gy, gy_ref).all()
+
+
+def test_pruned_descent_keeps_exact_counts(torch_mod):
+    from paper_2411_09809_amd import metrics, optim
+    L = gen.uniform_layout(600, 1500, extent=1 << 12, seed=7)
+    D = metrics.DeviceLayout.from_host(L)
+    xs, ys, hist = optim.descend(D.x, D.y, D.src, D.dst, steps=8, step_size=4.0,
+                                 extent=1 << 12, pruned=True)
+    xf, yf = xs.cpu().numpy(), ys.cpu().numpy()
+    c, _ = oracle.edge_crossing(xf, yf, L.src, L.dst)
+    assert metrics.edge_crossing(xs.contiguous(), ys.contiguous(), D.src, D.dst)[0] == c
+    assert min(h[0] for h in hist[1:]) < hist[0][0]
