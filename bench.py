@@ -11,6 +11,11 @@ step: C(|E|,2) per step / step time.  ``roofline`` reports the edge-pair
 sweep kernel (the dominant kernel) against the VALU issue peak; its duration
 comes from HIP events recorded by librb on the launch stream.
 ``cpu_baseline`` times the CPU oracle on a bounded sample of the same layout.
+Further sections: ``batched`` (512 layouts, one hipGraph replay against 512
+plain launch sets), ``fwd_bwd`` (loss and gradient against the forward
+alone, and a 100-step descent), ``pruned`` (the grid-pruned exact paths
+against the brute-force sweeps) and ``largest`` (one pass over the
+1,000,000-node / 3,000,000-edge layout).
 """
 import argparse
 import json
