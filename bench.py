@@ -44,8 +44,8 @@ OPS_PER_NODE_PAIR = 3
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy: x2.000 and
 # x1.000), by (rows per thread, waves per SIMD).  Valid only for the kernel
 # source they were measured on (first 16 hex digits of its sha256).
-MEASURED_TRAFFIC = {"source_sha": "9f52ec281cb3e492",
-                    "bytes": {(4, 3): 345.4e6, (4, 4): 346.6e6, (2, 5): 622.1e6, (1, 7): 1134.4e6}}
+MEASURED_TRAFFIC = {"source_sha": "315e8b1da38d1aa4",
+                    "bytes": {(4, 3): 345.1e6, (4, 4): 347.0e6, (2, 5): 622.3e6, (1, 7): 1133.6e6}}
 
 
 def measured_traffic(rows, waves):
