@@ -46,6 +46,8 @@ def lib():
         L.oracle_crossing_angle_rows.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, C.c_double,
                                                  _i64, _i64, _u64p, _dp]
         L.oracle_node_occlusion_rows.argtypes = [_dp, _dp, _i64, C.c_double, _i64, _i64, _u64p]
+        L.oracle_enhanced_crossing.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64, C.c_int,
+                                               C.c_double, _u64p, _dp]
         L.oracle_crossing_pairs.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64, _i64p]
         L.oracle_loss.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64, C.c_double,
                                   C.c_double, C.c_double, _dp]
@@ -168,6 +170,18 @@ def node_occlusion_rows(x, y, diameter: float, r0: int, r1: int) -> int:
     _check(lib().oracle_node_occlusion_rows(_p(x, _dp), _p(y, _dp), x.shape[0], float(diameter),
                                             int(r0), int(r1), C.byref(out)), "node_occlusion_rows")
     return int(out.value)
+
+
+def enhanced_crossing(x, y, src, dst, width: int, horizontal: bool, ideal_angle: float):
+    """(count, sum of |ideal - a|/ideal) of the strip method of Sections 3.2.2
+    and 3.2.3 (strips of integer width, vertical or horizontal)."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    cnt, dev = C.c_uint64(), C.c_double()
+    _check(lib().oracle_enhanced_crossing(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                          _p(d, _i32p), s.shape[0], int(width), int(horizontal),
+                                          float(ideal_angle), C.byref(cnt), C.byref(dev)),
+           "enhanced_crossing")
+    return int(cnt.value), float(dev.value)
 
 
 def crossing_pairs(x, y, src, dst) -> np.ndarray:

@@ -208,6 +208,69 @@ def test_row_slices_match_rational_brute_force(orc):
         orc.node_occlusion_rows(L.x, L.y, 40.0, 5, 4)
 
 
+def _crossing_point_x(P0, P1, Q0, Q1):
+    """x coordinate of the single intersection point of two properly
+    crossing segments, as an exact rational."""
+    r = (P1[0] - P0[0], P1[1] - P0[1])
+    q = (Q1[0] - Q0[0], Q1[1] - Q0[1])
+    den = _cross(r[0], r[1], q[0], q[1])
+    t = Fraction(_cross(Q0[0] - P0[0], Q0[1] - P0[1], q[0], q[1]), den)
+    return P0[0] + t * r[0]
+
+
+def test_enhanced_strip_method_is_crossings_inside_spanned_strips(orc):
+    """Sections 3.2.2/3.2.3 read geometrically: a pair counts iff the two
+    segments cross at one interior point whose x lies strictly inside a strip
+    that both segments span.  Checked against rational geometry."""
+    rng = np.random.default_rng(17)
+    for trial in range(40):
+        n = int(rng.integers(6, 14))
+        m = int(rng.integers(3, min(30, n * (n - 1) // 2)))
+        x = rng.integers(0, 24, size=n)
+        y = rng.integers(0, 24, size=n)
+        s, d = gen.distinct_random_edges(rng, n, m)
+        w = int(rng.choice([1, 2, 3, 5, 8, 30]))
+        horizontal = bool(trial % 2)
+        px, py = (y, x) if horizontal else (x, y)
+        pts = [(int(a), int(b)) for a, b in zip(px, py)]
+        x0 = min(p[0] for p in pts)
+        want = 0
+        dev = 0.0
+        for e, f in itertools.combinations(range(m), 2):
+            P0, P1, Q0, Q1 = pts[s[e]], pts[d[e]], pts[s[f]], pts[d[f]]
+            if rational_segment_relation(P0, P1, Q0, Q1) != 2:
+                continue
+            xs = _crossing_point_x(P0, P1, Q0, Q1)
+            k = (xs - x0) // w
+            if (xs - x0) == k * w:                  # on a strip line
+                continue
+            lo, hi = x0 + k * w, x0 + (k + 1) * w
+            if all(min(A[0], B[0]) <= lo and max(A[0], B[0]) >= hi for A, B in ((P0, P1), (Q0, Q1))):
+                want += 1
+                dev += abs(IDEAL - acos_angle(P0, P1, Q0, Q1)) / IDEAL
+        got, gdev = orc.enhanced_crossing(x, y, s, d, w, horizontal, IDEAL)
+        assert got == want, (trial, got, want)
+        assert abs(gdev - dev) < 1e-7
+
+
+def test_enhanced_single_strip_counts_permutation_inversions(orc):
+    """Edges from (0, i) to (W, p(i)) all span the one strip [0, W] and cross
+    strictly inside it: the count is the number of inversions of p."""
+    rng = np.random.default_rng(3)
+    for n in (2, 5, 17, 60):
+        p = rng.permutation(n)
+        x = np.concatenate([np.zeros(n), np.full(n, 50)])
+        y = np.concatenate([np.arange(n), p])
+        s, d = np.arange(n), np.arange(n) + n
+        inv = sum(1 for i in range(n) for j in range(i + 1, n) if p[i] > p[j])
+        got, _ = orc.enhanced_crossing(x, y, s, d, 50, False, IDEAL)
+        assert got == inv
+        assert orc.edge_crossing(x, y, s, d)[0] == inv
+        # narrower strips: every crossing at a non-integer x still counts once
+        got4, _ = orc.enhanced_crossing(x, y, s, d, 1, False, IDEAL)
+        assert got4 <= inv
+
+
 # ---------------------------------------------------------------- closed forms
 
 @pytest.mark.parametrize("n", range(4, 11))
