@@ -141,6 +141,29 @@ rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
                               double *out_loss, double *out_grad_x, double *out_grad_y,
                               uint64_t *out_count, void *ws, size_t ws_bytes, void *stream);
 
+/* Approximate mode: the strip method of the enhanced edge-crossing and
+ * crossing-angle algorithms (Sections 3.2.2 and 3.2.3).  The plane is cut
+ * into strips of integer `width` starting at the smallest node coordinate
+ * (vertical strips, or horizontal ones if `horizontal` != 0); in each strip
+ * the edges that span it are compared, and a pair counts when the order of
+ * their coordinates at the strip's two lines is strictly reversed.  Crossings
+ * near an edge's end (inside a strip it does not span) or exactly on a strip
+ * line are missed, so the count is a lower bound of E_c.  Outputs (device):
+ * out_metric double[1] (1 - mean deviation, 1 if no pair), out_count
+ * uint64[1] or NULL, out_dev_sum double[1] or NULL; *out_pieces (host, may
+ * be NULL) receives the number of edge pieces.  The call synchronizes
+ * `stream` once (to read the piece count).  Workspace:
+ * rb_enhanced_workspace_size(n_edges, pieces) bytes; with less than that the
+ * call returns RB_EWORKSPACE after writing *out_pieces, so a caller can
+ * retry with rb_enhanced_workspace_size(n_edges, *out_pieces).  width in
+ * [1, 2^22]; fewer than 2^32 pieces.                                       */
+size_t rb_enhanced_workspace_size(int64_t n_edges, uint64_t n_pieces);
+rb_status rb_enhanced_crossing(const float *x, const float *y, int64_t n_nodes,
+                               const int32_t *src, const int32_t *dst, int64_t n_edges,
+                               int64_t width, int horizontal, double ideal_angle,
+                               double *out_metric, uint64_t *out_count, double *out_dev_sum,
+                               uint64_t *out_pieces, void *ws, size_t ws_bytes, void *stream);
+
 /* Shards of the two all-pairs sweeps, for splitting one layout across
  * devices or processes (each computes its shards; the sums of the shard
  * results are the full results) and for checking a slice of a large

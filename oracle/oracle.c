@@ -619,13 +619,16 @@ int oracle_enhanced_crossing(const double *x, const double *y, int64_t n,
         if (k1[e] > kmax) kmax = k1[e];
     }
     uint64_t count = 0;
-    nsum tot = {0.0, 0.0};
-    int64_t *mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    double *strip_sum = (double *)calloc((size_t)(kmax > 0 ? kmax : 1), sizeof(double));
+    /* strips are independent: one per iteration, sums combined in strip order */
+    #pragma omp parallel for schedule(dynamic, 1) reduction(+:count)
     for (int64_t k = 0; k < kmax; ++k) {
+        int64_t *mem = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
         int64_t cnt = 0;
         for (int64_t e = 0; e < m; ++e)
             if (k0[e] <= k && k < k1[e]) mem[cnt++] = e;
         const int64_t XL = x0 + k * width, XR = XL + width;
+        nsum acc = {0.0, 0.0};
         for (int64_t i = 0; i < cnt; ++i)
             for (int64_t j = i + 1; j < cnt; ++j) {
                 const int64_t *a = E + 4 * mem[i], *b = E + 4 * mem[j];
@@ -635,10 +638,15 @@ int oracle_enhanced_crossing(const double *x, const double *y, int64_t n,
                 int64_t cr = a[2] * b[3] - a[3] * b[2];
                 int64_t dt = a[2] * b[2] + a[3] * b[3];
                 double ang = atan2(fabs((double)cr), fabs((double)dt));
-                nsum_add(&tot, fabs(ideal_angle - ang) / ideal_angle);
+                nsum_add(&acc, fabs(ideal_angle - ang) / ideal_angle);
             }
+        strip_sum[k] = nsum_get(&acc);
+        free(mem);
     }
-    free(mem); free(E); free(k0); free(k1); free(ix); free(iy);
+    nsum tot = {0.0, 0.0};
+    for (int64_t k = 0; k < kmax; ++k) nsum_add(&tot, strip_sum[k]);
+    free(strip_sum);
+    free(E); free(k0); free(k1); free(ix); free(iy);
     *out_count = count;
     if (out_dev_sum) *out_dev_sum = nsum_get(&tot);
     return 0;

@@ -545,6 +545,52 @@ rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
     return RB_OK;
 }
 
+size_t rb_enhanced_workspace_size(int64_t n_edges, uint64_t n_pieces) {
+    if (n_edges < 0 || n_edges > kMaxEdges || n_pieces >= (1ull << 32)) return 0;
+    return strip_ws_bytes(n_edges, (int64_t)n_pieces);
+}
+
+rb_status rb_enhanced_crossing(const float *x, const float *y, int64_t n_nodes,
+                               const int32_t *src, const int32_t *dst, int64_t n_edges,
+                               int64_t width, int horizontal, double ideal_angle,
+                               double *out_metric, uint64_t *out_count, double *out_dev_sum,
+                               uint64_t *out_pieces, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
+    if (width < 1 || width > (1ll << 22)) return fail(RB_EINVAL, "width must be in [1, 2^22]");
+    if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
+        return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
+    if (!ws) return fail(RB_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(RB_EWORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < strip_ws_bytes(n_edges, 0))
+        return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed to count pieces", ws_bytes,
+                    strip_ws_bytes(n_edges, 0));
+    hipStream_t st = (hipStream_t)stream;
+    const float *px = horizontal ? y : x, *py = horizontal ? x : y;   // strips across x
+    hipError_t e = launch_strip_count(px, py, src, dst, n_nodes, n_edges, width, (char *)ws, st);
+    if (e != hipSuccess) return hip_fail(e, "strip count launch");
+    unsigned long long P = 0;
+    e = hipMemcpyAsync(&P, strip_total_ptr((const char *)ws), sizeof P, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "piece count copy");
+    if (out_pieces) *out_pieces = P;
+    if (P >= (1ull << 32))
+        return fail(RB_EINVAL, "%llu strip pieces: widen the strips", (unsigned long long)P);
+    const size_t need = strip_ws_bytes(n_edges, (int64_t)P);
+    if (ws_bytes < need)
+        return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed for %llu pieces", ws_bytes,
+                    need, (unsigned long long)P);
+    TimedLaunch tl(3, st);
+    e = launch_strip_crossing(px, py, src, dst, n_nodes, n_edges, width, (int64_t)P, ideal_angle,
+                              (char *)ws, out_metric, (unsigned long long *)out_count, out_dev_sum,
+                              st);
+    tl.done();
+    if (e != hipSuccess) return hip_fail(e, "strip crossing launch");
+    return RB_OK;
+}
+
 rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                              const int32_t *dst, int64_t n_edges, int32_t *out_flags, void *ws,
                              size_t ws_bytes, void *stream) {

@@ -209,6 +209,17 @@ hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_node
                                   double ideal, const GridWs &G, char *w, int variant,
                                   double *out_metric, unsigned long long *out_count,
                                   double *out_dev_sum, hipStream_t st);
+// Strip approximation of Sections 3.2.2 / 3.2.3 (strip.hip).
+size_t strip_ws_bytes(int64_t m, int64_t n_pieces);
+hipError_t launch_strip_count(const float *x, const float *y, const int32_t *src,
+                              const int32_t *dst, int64_t n_nodes, int64_t m, int64_t w,
+                              char *ws, hipStream_t st);
+const unsigned long long *strip_total_ptr(const char *ws);
+hipError_t launch_strip_crossing(const float *x, const float *y, const int32_t *src,
+                                 const int32_t *dst, int64_t n_nodes, int64_t m, int64_t w,
+                                 int64_t n_pieces, double ideal, char *ws, double *out_metric,
+                                 unsigned long long *out_count, double *out_dev_sum,
+                                 hipStream_t st);
 hipError_t launch_occlusion_grid(const float *x, const float *y, int64_t n, double T,
                                  const GridWs &G, char *w, unsigned long long *out_count,
                                  hipStream_t st);

@@ -198,6 +198,45 @@ def crossing_angle_pruned(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, *,
     return float(vals[0]), int(vals.view(torch.int64)[1]), float(vals[2])
 
 
+_strip_ws: dict[int, torch.Tensor] = {}
+
+
+def enhanced_crossing(x, y, src, dst, width: int, horizontal: bool = False,
+                      ideal_angle: float = IDEAL_ANGLE):
+    """The strip approximation of Sections 3.2.2 / 3.2.3 with strips of
+    integer ``width`` (vertical, or horizontal): (E_ca, crossing count, sum
+    of |ideal - a|/ideal, number of strip pieces).  Synchronizes."""
+    import ctypes as C
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    dev = x.device
+    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    out = _out(3, torch.float64, dev)
+    pieces = C.c_uint64()
+    need = int(lib().rb_enhanced_workspace_size(src.numel(), 0))
+    for _ in range(2):
+        ws = _strip_ws.get(key)
+        if ws is None or ws.numel() < need + 256:
+            _strip_ws.pop(key, None)
+            ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+            _strip_ws[key] = ws
+        w, wb = _ws_args(ws)
+        p = _ptr(out)
+        rc = lib().rb_enhanced_crossing(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst),
+                                        src.numel(), int(width), int(bool(horizontal)),
+                                        float(ideal_angle), p, p + 8, p + 16, C.byref(pieces), w,
+                                        wb, _stream(dev))
+        if rc == 2 and pieces.value:            # workspace short for this many pieces
+            need = int(lib().rb_enhanced_workspace_size(src.numel(), pieces.value))
+            if need == 0:
+                break
+            continue
+        break
+    check(rc, "rb_enhanced_crossing")
+    vals = out.cpu()
+    return float(vals[0]), int(vals.view(torch.int64)[1]), float(vals[2]), int(pieces.value)
+
+
 def crossing_angle_shard(x, y, src, dst, shard: int, n_shards: int,
                          ideal_angle: float = IDEAL_ANGLE):
     """(crossings, sum of |ideal - a|/ideal, row_begin, row_end) of shard k
