@@ -14,7 +14,8 @@ comes from HIP events recorded by librb on the launch stream.
 Further sections: ``batched`` (512 layouts, one hipGraph replay against 512
 plain launch sets), ``fwd_bwd`` (loss and gradient against the forward
 alone, and a 100-step descent), ``pruned`` (the grid-pruned exact paths
-against the brute-force sweeps) and ``largest`` (one pass over the
+against the brute-force sweeps), ``approx`` (error and time of the strip
+approximation of Sections 3.2.2 / 3.2.3) and ``largest`` (one pass over the
 1,000,000-node / 3,000,000-edge layout).
 """
 import argparse
@@ -230,6 +231,48 @@ def bench_pruned(torch, reps: int):
     return out
 
 
+def bench_approx(torch):
+    """Error of the strip approximation (Sections 3.2.2 / 3.2.3) against the
+    exact E_c and E_ca, in the manner of the paper's accuracy tables: strip
+    widths of 1/1000 and 1/2000 of the layout's span (the paper's 0.10 and
+    0.05 on a 100-unit canvas), vertical, horizontal and both (the larger of
+    the two counts), on a random layout of the preferential-attachment graph,
+    on its clustered layout and on the random geometric layout (short edges,
+    as in force-directed layouts)."""
+    import numpy as np
+    from paper_2411_09809_amd import gen, metrics
+
+    ba = gen.ba_cluster_layout(seed=0)
+    rng = np.random.default_rng(1)
+    rnd = gen._finish(rng.integers(0, 1 << 16, ba.n_nodes), rng.integers(0, 1 << 16, ba.n_nodes),
+                      ba.src, ba.dst, diameter=8.0, name="ba_V50000_random_layout")
+    out = {}
+    for L in (rnd, ba, gen.geometric_layout(seed=0)):
+        D = metrics.DeviceLayout.from_host(L)
+        ex_eca, ex_c, _ = metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle)
+        span = int(max(L.x.max() - L.x.min(), L.y.max() - L.y.min()))
+        rows = {}
+        for frac in (1000, 2000):
+            width = max(1, span // frac)
+            res = {}
+            for name, hz in (("vertical", False), ("horizontal", True)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                eca, c, _, pieces = metrics.enhanced_crossing(D.x, D.y, D.src, D.dst, width, hz,
+                                                              D.ideal_angle)
+                torch.cuda.synchronize()
+                res[name] = (eca, c, pieces, time.perf_counter() - t0)
+            best = max(res.values(), key=lambda r: r[1])
+            row = {}
+            for name, (eca, c, pieces, secs) in list(res.items()) + [("both", best)]:
+                row[name] = {"E_c_error_pct": 100.0 * (ex_c - c) / ex_c,
+                             "E_ca_error_pct": 100.0 * abs(eca - ex_eca) / ex_eca,
+                             "pieces": pieces, "seconds": secs}
+            rows[f"width_span_over_{frac}"] = row
+        out[L.name] = {"E_c": ex_c, "E_ca": ex_eca, "strips": rows}
+    return out
+
+
 def bench_largest(torch):
     """The 1,000,000-node / 3,000,000-edge power-law layout: one pass of each
     sweep (4.5e12 edge pairs, 5.0e11 node pairs) plus the two small metrics,
@@ -304,6 +347,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward part")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the grid-pruned paths")
+    ap.add_argument("--no-approx", action="store_true",
+                    help="skip the error study of the strip approximation")
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the single pass over the 1M-node / 3M-edge layout")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -442,6 +487,9 @@ def main():
     if not args.no_pruned:
         log("[bench] grid-pruned paths ...")
         rec["pruned"] = bench_pruned(torch, max(3, args.steps // 4))
+    if not args.no_approx:
+        log("[bench] strip approximation error ...")
+        rec["approx"] = bench_approx(torch)
     if not args.no_largest:
         log("[bench] largest layout (1M nodes, 3M edges) ...")
         rec["largest"] = bench_largest(torch)
