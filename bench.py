@@ -205,8 +205,9 @@ def bench_pruned(torch, reps: int):
     same exact counts, time of the whole call (sort and planning included)."""
     from paper_2411_09809_amd import gen, metrics
     out = {}
-    for name in ("rgg_V20000_E60000", "ba_cluster_V50000_E149994"):
-        L = gen.WORKLOADS[name](seed=0)
+    for name in ("rgg_V20000_E60000", "ba_cluster_V50000_E149994", "fr"):
+        L = gen.force_directed_layout(seed=0) if name == "fr" else gen.WORKLOADS[name](seed=0)
+        name = L.name
         D = metrics.DeviceLayout.from_host(L)
         brute = metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle)
         pruned = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, D.ideal_angle)
@@ -237,8 +238,9 @@ def bench_approx(torch):
     widths of 1/1000 and 1/2000 of the layout's span (the paper's 0.10 and
     0.05 on a 100-unit canvas), vertical, horizontal and both (the larger of
     the two counts), on a random layout of the preferential-attachment graph,
-    on its clustered layout and on the random geometric layout (short edges,
-    as in force-directed layouts)."""
+    on its clustered layout, on the random geometric layout (short edges) and
+    on a Fruchterman-Reingold layout of a 4,000-node community graph (the
+    kind of layout of the paper's force-directed experiment)."""
     import numpy as np
     from paper_2411_09809_amd import gen, metrics
 
@@ -247,7 +249,8 @@ def bench_approx(torch):
     rnd = gen._finish(rng.integers(0, 1 << 16, ba.n_nodes), rng.integers(0, 1 << 16, ba.n_nodes),
                       ba.src, ba.dst, diameter=8.0, name="ba_V50000_random_layout")
     out = {}
-    for L in (rnd, ba, gen.geometric_layout(seed=0)):
+    fr = gen.force_directed_layout(seed=0)
+    for L in (rnd, ba, gen.geometric_layout(seed=0), fr):
         D = metrics.DeviceLayout.from_host(L)
         ex_eca, ex_c, _ = metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle)
         span = int(max(L.x.max() - L.x.min(), L.y.max() - L.y.min()))

@@ -293,6 +293,90 @@ def powerlaw_layout(n_nodes: int = 1_000_000, n_edges: int = 3_000_000,
                    meta=dict(seed=seed, extent=extent))
 
 
+def force_directed_coords(rng: np.random.Generator, n_nodes: int, src: np.ndarray,
+                          dst: np.ndarray, iterations: int = 60, extent: int = 1 << 16,
+                          block: int = 1024) -> tuple[np.ndarray, np.ndarray]:
+    """Fruchterman-Reingold spring embedding (the layout algorithm of the
+    paper's force-directed experiment): on a unit square, all node pairs
+    repel with k^2/d and edges attract with d^2/k, k = sqrt(1/|V|); each
+    iteration moves every node along its net force by at most a temperature
+    that cools linearly from 0.1 to 0.  The result is scaled into
+    [0, extent)^2 and rounded to integers.  Elementwise numpy only (the
+    repulsion in row blocks), so the output is the same on every x86 host."""
+    pos = rng.random((n_nodes, 2))
+    k = math.sqrt(1.0 / max(n_nodes, 1))
+    s = np.asarray(src, dtype=np.int64)
+    d = np.asarray(dst, dtype=np.int64)
+    for it in range(iterations):
+        t = 0.1 * (1.0 - it / iterations)
+        disp = np.zeros_like(pos)
+        for b0 in range(0, n_nodes, block):
+            p = pos[b0:b0 + block]
+            dx = p[:, None, 0] - pos[None, :, 0]
+            dy = p[:, None, 1] - pos[None, :, 1]
+            d2 = dx * dx + dy * dy
+            d2[d2 < 1e-12] = 1e-12                   # self and coincident pairs
+            f = (k * k) / d2                         # k^2/d along the unit vector d/|d|
+            f[np.arange(p.shape[0]), np.arange(b0, b0 + p.shape[0])] = 0.0
+            disp[b0:b0 + block, 0] += (dx * f).sum(axis=1)
+            disp[b0:b0 + block, 1] += (dy * f).sum(axis=1)
+        ex = pos[s, 0] - pos[d, 0]
+        ey = pos[s, 1] - pos[d, 1]
+        el = np.sqrt(ex * ex + ey * ey)
+        fa = el / k                                  # d^2/k along the unit vector
+        np.subtract.at(disp[:, 0], s, ex * fa)
+        np.subtract.at(disp[:, 1], s, ey * fa)
+        np.add.at(disp[:, 0], d, ex * fa)
+        np.add.at(disp[:, 1], d, ey * fa)
+        dl = np.sqrt((disp * disp).sum(axis=1))
+        step = np.minimum(dl, t) / np.maximum(dl, 1e-300)
+        pos += disp * step[:, None]
+        pos = np.clip(pos, 0.0, 1.0)
+    lo, hi = pos.min(axis=0), pos.max(axis=0)
+    scale = (extent - 1) / np.maximum(hi - lo, 1e-300)
+    xy = np.rint((pos - lo) * scale).astype(np.int64)
+    return xy[:, 0], xy[:, 1]
+
+
+def community_edges(rng: np.random.Generator, n_nodes: int, n_groups: int, intra: int,
+                    inter: int) -> tuple[np.ndarray, np.ndarray]:
+    """Planted-partition graph: nodes split into n_groups equal groups,
+    `intra` distinct edges drawn uniformly inside each group and `inter`
+    distinct edges between different groups."""
+    group = np.arange(n_nodes) % n_groups
+    src, dst = [], []
+    for g in range(n_groups):
+        members = np.flatnonzero(group == g)
+        a, b = distinct_random_edges(rng, members.shape[0], intra)
+        src.append(members[a])
+        dst.append(members[b])
+    seen = set()
+    while len(seen) < inter:
+        a, b = (int(v) for v in rng.integers(0, n_nodes, size=2))
+        if group[a] == group[b] or (min(a, b), max(a, b)) in seen:
+            continue
+        seen.add((min(a, b), max(a, b)))
+    e = np.array(sorted(seen), dtype=np.int64).reshape(-1, 2)
+    src.append(e[:, 0])
+    dst.append(e[:, 1])
+    return np.concatenate(src), np.concatenate(dst)
+
+
+def force_directed_layout(n_nodes: int = 4000, n_groups: int = 16, intra: int = 5000,
+                          inter: int = 5000, iterations: int = 60, extent: int = 1 << 16,
+                          diameter: float = 64.0, seed: int = 0) -> Layout:
+    """A community-structured graph of the size of the paper's smallest
+    dataset (4,000 nodes, 16 groups, 85,000 edges by default) drawn by
+    Fruchterman-Reingold: groups become clusters, most edges are short, as in
+    layouts meant for reading."""
+    rng = np.random.default_rng(seed)
+    s, d = community_edges(rng, n_nodes, n_groups, intra, inter)
+    x, y = force_directed_coords(rng, n_nodes, s, d, iterations, extent)
+    return _finish(x, y, s, d, diameter=diameter,
+                   name=f"fr_groups{n_groups}_V{n_nodes}_E{s.shape[0]}",
+                   meta=dict(seed=seed, extent=extent, iterations=iterations))
+
+
 # ---------------------------------------------------------------- hand cases
 
 def convex_k4() -> Layout:

@@ -77,3 +77,14 @@ def test_clustered_and_workspace_growth(torch_mod):
         say(f"[enhanced] width={width} pieces={pieces} count={cnt}")
         assert cnt == rc
         assert dev == pytest.approx(rdev, rel=1e-9, abs=1e-12)
+
+
+def test_force_directed_layout(torch_mod):
+    from paper_2411_09809_amd import metrics
+    L = gen.force_directed_layout(n_nodes=1000, n_groups=8, intra=1200, inter=500, seed=3)
+    D = metrics.DeviceLayout.from_host(L)
+    for width, hz in ((65, False), (33, True), (1024, False)):
+        eca, cnt, dev, _ = metrics.enhanced_crossing(D.x, D.y, D.src, D.dst, width, hz)
+        rc, rdev = oracle.enhanced_crossing(L.x, L.y, L.src, L.dst, width, hz, IDEAL)
+        assert cnt == rc
+        assert dev == pytest.approx(rdev, rel=1e-9, abs=1e-12)

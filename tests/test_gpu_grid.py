@@ -202,3 +202,16 @@ def test_pruned_full_size(torch_mod, name):
     say(f"[pruned] {name}: E_c={brute[1]} E_ca={brute[0]:.12f} pruned E_ca={pruned[0]:.12f}")
     _same(brute, pruned)
     assert again == pruned                      # deterministic
+
+
+def test_pruned_and_grid_on_force_directed_layout(torch_mod):
+    """A Fruchterman-Reingold layout of a community graph (short edges)."""
+    from paper_2411_09809_amd import metrics
+    L = gen.force_directed_layout(n_nodes=1000, n_groups=8, intra=1200, inter=500, seed=3)
+    D = metrics.DeviceLayout.from_host(L)
+    brute, pruned = _both(metrics, D)
+    eca, cnt, dev = oracle.crossing_angle(L.x, L.y, L.src, L.dst, gen.IDEAL_ANGLE)
+    assert brute[1] == cnt
+    _same(brute, pruned)
+    for d in (64.0, 700.0):
+        assert metrics.node_occlusion_grid(D.x, D.y, d) == oracle.node_occlusion(L.x, L.y, d)

@@ -532,6 +532,19 @@ def test_random_segments_cross_with_probability_25_over_108(orc):
     assert c - p < 10                  # touching pairs are rare on a 2^20 grid
 
 
+def test_force_directed_layout_is_reproducible():
+    """The Fruchterman-Reingold input generator is deterministic (a pinned
+    digest) and produces a proper layout: integer coordinates filling the
+    canvas, distinct non-loop edges."""
+    L = gen.force_directed_layout(n_nodes=1000, n_groups=8, intra=1200, inter=500, seed=3)
+    assert L.digest() == gen.force_directed_layout(n_nodes=1000, n_groups=8, intra=1200,
+                                                   inter=500, seed=3).digest()
+    assert L.x.min() == 0 and L.x.max() == (1 << 16) - 1
+    assert (L.src != L.dst).all()
+    pairs = set(zip(np.minimum(L.src, L.dst), np.maximum(L.src, L.dst)))
+    assert len(pairs) == L.n_edges == 8 * 1200 + 500
+
+
 def test_bad_inputs_are_rejected(orc):
     with pytest.raises(orc.OracleError):
         orc.node_occlusion([0.5, 1.0], [0.0, 0.0], 1.0)
