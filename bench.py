@@ -13,7 +13,8 @@ comes from HIP events recorded by librb on the launch stream.
 ``cpu_baseline`` times the CPU oracle on a bounded sample of the same layout.
 Further sections: ``batched`` (512 layouts, one hipGraph replay against 512
 plain launch sets), ``fwd_bwd`` (loss and gradient against the forward
-alone, and a 100-step descent), ``pruned`` (the grid-pruned exact paths
+alone, and a 100-step descent), ``optimise`` (100 descent steps from a
+force-directed layout, all metrics before and after), ``pruned`` (the grid-pruned exact paths
 against the brute-force sweeps), ``approx`` (error and time of the strip
 approximation of Sections 3.2.2 / 3.2.3) and ``largest`` (one pass over the
 1,000,000-node / 3,000,000-edge layout).
@@ -276,6 +277,33 @@ def bench_approx(torch):
     return out
 
 
+def bench_optimise(torch, steps: int):
+    """End-to-end layout optimisation: the Fruchterman-Reingold layout of the
+    4,000-node community graph, `steps` gradient steps on
+    (1 - E_ca) + M_l with the pruned loss and gradient, all five metrics
+    evaluated exactly before and after."""
+    from paper_2411_09809_amd import gen, metrics, optim
+
+    L = gen.force_directed_layout(seed=0)
+    D = metrics.DeviceLayout.from_host(L)
+    before = metrics.evaluate(D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, ys, hist = optim.descend(D.x, D.y, D.src, D.dst, steps=steps, step_size=64.0,
+                                 extent=1 << 16, pruned=True)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    D2 = metrics.DeviceLayout(xs.contiguous(), ys.contiguous(), D.src, D.dst, D.diameter,
+                              D.ideal_angle)
+    after = metrics.evaluate(D2)
+    keep = ("node_occlusion", "edge_crossing", "crossing_angle", "min_angle",
+            "edge_length_variation")
+    return {"workload": f"{L.name}: Fruchterman-Reingold layout in [0,2^16)^2, diameter 64",
+            "steps": steps, "seconds": secs, "ms_per_step": secs * 1e3 / steps,
+            "loss_first_last": [hist[0][0], hist[-1][0]],
+            "before": {k: before[k] for k in keep}, "after": {k: after[k] for k in keep}}
+
+
 def bench_largest(torch):
     """The 1,000,000-node / 3,000,000-edge power-law layout: one pass of each
     sweep (4.5e12 edge pairs, 5.0e11 node pairs) plus the two small metrics,
@@ -350,6 +378,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward part")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the grid-pruned paths")
+    ap.add_argument("--no-optimise", action="store_true",
+                    help="skip the end-to-end layout optimisation")
     ap.add_argument("--no-approx", action="store_true",
                     help="skip the error study of the strip approximation")
     ap.add_argument("--no-largest", action="store_true",
@@ -490,6 +520,9 @@ def main():
     if not args.no_pruned:
         log("[bench] grid-pruned paths ...")
         rec["pruned"] = bench_pruned(torch, max(3, args.steps // 4))
+    if not args.no_optimise:
+        log("[bench] layout optimisation ...")
+        rec["optimise"] = bench_optimise(torch, 100)
     if not args.no_approx:
         log("[bench] strip approximation error ...")
         rec["approx"] = bench_approx(torch)
