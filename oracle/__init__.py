@@ -48,6 +48,8 @@ def lib():
         L.oracle_node_occlusion_rows.argtypes = [_dp, _dp, _i64, C.c_double, _i64, _i64, _u64p]
         L.oracle_enhanced_crossing.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64, C.c_int,
                                                C.c_double, _u64p, _dp]
+        L.oracle_min_angle_term.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, C.c_double, _dp,
+                                             _dp, _dp]
         L.oracle_crossing_pairs.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64, _i64p]
         L.oracle_loss.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64p, _i64, C.c_double,
                                   C.c_double, C.c_double, _dp]
@@ -198,19 +200,37 @@ def crossing_pairs(x, y, src, dst) -> np.ndarray:
     return out[:n.value]
 
 
-def loss(x, y, src, dst, pairs, ideal_angle, w_angle=1.0, w_length=1.0) -> float:
-    """w_a (1 - E_ca) + w_l M_l at (possibly non-integer) coordinates, with
-    the crossing set frozen to ``pairs``."""
+def min_angle_term(x, y, src, dst, w_min_angle=1.0, grad=False):
+    """w_m (1 - M_a) at (possibly non-integer) coordinates; with grad, also
+    its gradient (dT/dx, dT/dy)."""
+    x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
+    out = C.c_double()
+    gx = np.zeros(x.shape[0]) if grad else None
+    gy = np.zeros(x.shape[0]) if grad else None
+    _check(lib().oracle_min_angle_term(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
+                                       _p(d, _i32p), s.shape[0], float(w_min_angle),
+                                       C.byref(out), _p(gx, _dp) if grad else None,
+                                       _p(gy, _dp) if grad else None), "min_angle_term")
+    return (float(out.value), gx, gy) if grad else float(out.value)
+
+
+def loss(x, y, src, dst, pairs, ideal_angle, w_angle=1.0, w_length=1.0,
+         w_min_angle=0.0) -> float:
+    """w_a (1 - E_ca) + w_l M_l + w_m (1 - M_a) at (possibly non-integer)
+    coordinates, with the crossing set frozen to ``pairs``."""
     x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
     P = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
     out = C.c_double()
     _check(lib().oracle_loss(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p), _p(d, _i32p),
                              s.shape[0], _p(P, _i64p), P.shape[0], float(ideal_angle),
                              float(w_angle), float(w_length), C.byref(out)), "loss")
-    return float(out.value)
+    f = float(out.value)
+    if w_min_angle:
+        f += min_angle_term(x, y, s, d, w_min_angle)
+    return f
 
 
-def loss_grad(x, y, src, dst, pairs, ideal_angle, w_angle=1.0, w_length=1.0):
+def loss_grad(x, y, src, dst, pairs, ideal_angle, w_angle=1.0, w_length=1.0, w_min_angle=0.0):
     """(loss, dL/dx, dL/dy) -- the analytic gradient of ``loss``."""
     x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
     P = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
@@ -221,7 +241,11 @@ def loss_grad(x, y, src, dst, pairs, ideal_angle, w_angle=1.0, w_length=1.0):
                                   _p(d, _i32p), s.shape[0], _p(P, _i64p), P.shape[0],
                                   float(ideal_angle), float(w_angle), float(w_length),
                                   C.byref(out), _p(gx, _dp), _p(gy, _dp)), "loss_grad")
-    return float(out.value), gx, gy
+    f = float(out.value)
+    if w_min_angle:
+        t, tx, ty = min_angle_term(x, y, s, d, w_min_angle, grad=True)
+        f, gx, gy = f + t, gx + tx, gy + ty
+    return f, gx, gy
 
 
 def all_metrics(L) -> dict:

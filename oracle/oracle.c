@@ -651,3 +651,83 @@ int oracle_enhanced_crossing(const double *x, const double *y, int64_t n,
     if (out_dev_sum) *out_dev_sum = nsum_get(&tot);
     return 0;
 }
+
+/* ------------------------------ minimum-angle term of the optimisation loss
+ *
+ * T = w_m (1 - M_a) at (possibly non-integer) coordinates, with M_a of
+ * Algorithm 2 (mean over vertices of degree >= 1, readings R9, R10):
+ * 1 - M_a = 1 - (1/N) sum_v phi_v deg_v / (2 pi), phi_v the smallest gap
+ * between the sorted directions v -> u of v's edges (2 pi for degree 1).
+ * phi_v moves with the two directions that bound that gap, so
+ *     dT/d alpha_next = -dT/d alpha_prev = -w_m deg_v / (2 pi N),
+ * and a direction alpha of v -> u turns with u as (-dy, dx) / l^2 (and with v
+ * as the opposite).  Kinks contribute 0: a smallest gap attained twice, a
+ * zero gap (two edges in one direction) or a zero-length edge bounding it.
+ * The gradient (if gx, gy are given) is added to gx, gy. */
+typedef struct { double a; int32_t u; } dir_t;
+
+static int cmp_dir(const void *p, const void *q) {
+    double a = ((const dir_t *)p)->a, b = ((const dir_t *)q)->a;
+    return (a > b) - (a < b);
+}
+
+int oracle_min_angle_term(const double *x, const double *y, int64_t n, const int32_t *src,
+                          const int32_t *dst, int64_t m, double w_m, double *out_term,
+                          double *gx, double *gy) {
+    if (n < 0 || m < 0 || !out_term) return 1;
+    if (check_edges(src, dst, m, n)) return 3;
+    const double two_pi = 2.0 * M_PI;
+    int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < m; ++e) { deg[src[e]]++; deg[dst[e]]++; }
+    int64_t *start = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t v = 0; v < n; ++v) start[v + 1] = start[v] + deg[v];
+    int64_t *fill = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+    for (int64_t e = 0; e < m; ++e) {
+        nbr[start[src[e]] + fill[src[e]]++] = dst[e];
+        nbr[start[dst[e]] + fill[dst[e]]++] = src[e];
+    }
+    int64_t used = 0;
+    for (int64_t v = 0; v < n; ++v) used += deg[v] > 0;
+    nsum tot = {0.0, 0.0};
+    dir_t *dir = (dir_t *)malloc(sizeof(dir_t) * (size_t)(2 * m + 1));
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t k = deg[v];
+        if (k == 0) continue;
+        for (int64_t i = 0; i < k; ++i) {
+            const int32_t u = nbr[start[v] + i];
+            double a = atan2(y[u] - y[v], x[u] - x[v]);
+            if (a < 0.0) a += two_pi;                                  /* R10 */
+            dir[i].a = a;
+            dir[i].u = u;
+        }
+        qsort(dir, (size_t)k, sizeof(dir_t), cmp_dir);
+        /* gaps: dir[i] -> dir[i+1], and the wrap dir[k-1] -> dir[0] */
+        double phi = two_pi;
+        int64_t at = -1, ties = 0;
+        if (k >= 2) {
+            for (int64_t i = 0; i < k; ++i) {
+                const double g = i + 1 < k ? dir[i + 1].a - dir[i].a
+                                           : two_pi - dir[k - 1].a + dir[0].a;
+                if (g < phi) { phi = g; at = i; ties = 1; }
+                else if (g == phi) ties++;
+            }
+        }
+        nsum_add(&tot, phi * (double)k / two_pi);
+        if (!gx || !gy || k < 2 || ties != 1 || !(phi > 0.0)) continue;
+        const double c = -w_m * (double)k / (two_pi * (double)used);   /* dT / d phi_v */
+        const dir_t p = dir[at], q = dir[at + 1 < k ? at + 1 : 0];
+        const double pdx = x[p.u] - x[v], pdy = y[p.u] - y[v];
+        const double qdx = x[q.u] - x[v], qdy = y[q.u] - y[v];
+        const double pl2 = pdx * pdx + pdy * pdy, ql2 = qdx * qdx + qdy * qdy;
+        if (pl2 == 0.0 || ql2 == 0.0) continue;
+        /* phi = alpha_q - alpha_p: +1 through q, -1 through p */
+        gx[q.u] += c * -qdy / ql2;  gy[q.u] += c * qdx / ql2;
+        gx[v] -= c * -qdy / ql2;    gy[v] -= c * qdx / ql2;
+        gx[p.u] -= c * -pdy / pl2;  gy[p.u] -= c * pdx / pl2;
+        gx[v] += c * -pdy / pl2;    gy[v] += c * pdx / pl2;
+    }
+    *out_term = used ? w_m * (1.0 - nsum_get(&tot) / (double)used) : 0.0;
+    free(dir); free(deg); free(start); free(fill); free(nbr);
+    return 0;
+}

@@ -46,4 +46,7 @@ int oracle_enhanced_crossing(const double *x, const double *y, int64_t n,
                              const int32_t *src, const int32_t *dst, int64_t m,
                              int64_t width, int horizontal, double ideal_angle,
                              uint64_t *out_count, double *out_dev_sum);
+int oracle_min_angle_term(const double *x, const double *y, int64_t n, const int32_t *src,
+                          const int32_t *dst, int64_t m, double w_m, double *out_term,
+                          double *gx, double *gy);
 #endif

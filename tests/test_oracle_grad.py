@@ -102,3 +102,63 @@ def test_kinks_contribute_zero(orc):
     y = np.zeros(4)
     f, gx, gy = orc.loss_grad(x, y, [0, 2], [1, 3], [[0, 1]], IDEAL, 1.0, 0.0)
     assert f == pytest.approx(1.0) and np.abs(gx).max() == 0.0 and np.abs(gy).max() == 0.0
+
+
+# ---------------------------------------------------- the minimum-angle term
+
+def test_min_angle_term_at_integer_points_is_one_minus_the_metric(orc):
+    for seed in (1, 2):
+        L = gen.uniform_layout(500, 1400, extent=3000, seed=seed)
+        ma, _, _ = orc.min_angle(L.x, L.y, L.src, L.dst)
+        assert orc.min_angle_term(L.x, L.y, L.src, L.dst, 1.0) == pytest.approx(1 - ma, rel=1e-12)
+        assert orc.min_angle_term(L.x, L.y, L.src, L.dst, 2.5) == pytest.approx(2.5 * (1 - ma),
+                                                                              rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_min_angle_gradient_matches_central_differences(orc, seed):
+    L, S, x, y = jittered(seed, n=60, m=150)
+    t0, gx, gy = orc.min_angle_term(x, y, L.src, L.dst, 1.0, grad=True)
+    h = 1e-6
+    scale = max(np.abs(gx).max(), np.abs(gy).max())
+    assert scale > 0
+    for v in range(L.n_nodes):
+        for arr, g in ((x, gx), (y, gy)):
+            old = arr[v]
+            arr[v] = old + h
+            fp = orc.min_angle_term(x, y, L.src, L.dst, 1.0)
+            arr[v] = old - h
+            fm = orc.min_angle_term(x, y, L.src, L.dst, 1.0)
+            arr[v] = old
+            assert abs((fp - fm) / (2 * h) - g[v]) <= 1e-6 * scale, (v, (fp - fm) / (2 * h), g[v])
+
+
+def test_min_angle_gradient_symmetry_identities(orc):
+    L, S, x, y = jittered(6, n=300, m=900, extent=3000)
+    _, gx, gy = orc.min_angle_term(x, y, L.src, L.dst, 1.0, grad=True)
+    mag = np.abs(gx).sum() + np.abs(gy).sum()
+    r = np.abs(x).max() + np.abs(y).max()
+    assert mag > 0
+    assert abs(gx.sum()) <= 1e-12 * mag and abs(gy.sum()) <= 1e-12 * mag
+    assert abs((x * gy - y * gx).sum()) <= 1e-12 * mag * r
+    assert abs((x * gx + y * gy).sum()) <= 1e-12 * mag * r
+
+
+def test_min_angle_term_rotating_one_edge_closed_form(orc):
+    """Node 0 with neighbours at angle 0 (node 1) and 60 degrees (node 2):
+    phi = pi/3, 1 - M_a = 1 - (1/3)(phi*2/(2 pi) + 1 + 1).  Turning node 2
+    about node 0 by +dphi widens phi by dphi: dT/dphi = -2/(2 pi * 3)."""
+    x = np.array([0.0, 10.0, 5.0])
+    y = np.array([0.0, 0.0, 5.0 * math.sqrt(3.0)])
+    src, dst = np.array([0, 0]), np.array([1, 2])
+    t, gx, gy = orc.min_angle_term(x, y, src, dst, 1.0, grad=True)
+    assert t == pytest.approx(1 - (1 / 3) * (1 / 3 + 2), rel=1e-12)
+    # rotation of node 2 about node 0: d(x2, y2)/dphi = (-y2, x2)
+    dphi = gx[2] * -y[2] + gy[2] * x[2]
+    assert dphi == pytest.approx(-2.0 / (2 * math.pi * 3), rel=1e-12)
+    # kinks give no gradient: a tie (neighbours at 0 and 180 degrees, two gaps
+    # of exactly pi) and a zero gap (two neighbours in one direction)
+    for xs, ys in (([0.0, 10.0, -7.0], [0.0, 0.0, 0.0]), ([0.0, 10.0, 4.0], [0.0, 5.0, 2.0])):
+        _, gx, gy = orc.min_angle_term(np.array(xs), np.array(ys), np.array([0, 0]),
+                                       np.array([1, 2]), 1.0, grad=True)
+        assert np.abs(gx).max() == 0.0 and np.abs(gy).max() == 0.0
