@@ -138,8 +138,9 @@ rb_status rb_crossing_angle_pruned(const float *x, const float *y, int64_t n_nod
 rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
                               const int32_t *src, const int32_t *dst, int64_t n_edges,
                               double ideal_angle, double w_angle, double w_length,
-                              double *out_loss, double *out_grad_x, double *out_grad_y,
-                              uint64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+                              double w_min_angle, double *out_loss, double *out_grad_x,
+                              double *out_grad_y, uint64_t *out_count, void *ws,
+                              size_t ws_bytes, void *stream);
 
 /* Approximate mode: the strip method of the enhanced edge-crossing and
  * crossing-angle algorithms (Sections 3.2.2 and 3.2.3).  The plane is cut
@@ -213,21 +214,26 @@ rb_status rb_edge_length_variation(const float *x, const float *y, int64_t n_nod
 
 /* Layout-optimisation loss and its gradient (the application the paper's
  * Conclusion names; the loss is this library's choice, built from the
- * Algorithm 5 and Algorithm 3 metrics):
- *     L = w_angle (1 - E_ca) + w_length M_l
+ * Algorithm 5, Algorithm 3 and Algorithm 2 metrics):
+ *     L = w_angle (1 - E_ca) + w_length M_l + w_min_angle (1 - M_a)
  * with the crossing set S of the current layout held fixed, and
  * d L / d(x, y) of every node, computed exactly as the chain rule through
- * each crossing pair's acute angle and each edge's length.  Kinks (a pair
- * at exactly the ideal angle, perpendicular or parallel lines, equal edge
- * lengths, zero-length edges) contribute 0.  The coordinates must satisfy
- * the layout preconditions (the crossing set is exact on integers).
+ * each crossing pair's acute angle, each edge's length and, at each vertex,
+ * the two edge directions that bound its smallest gap (M_a averages
+ * phi_v deg_v / 2 pi over the vertices of degree >= 1; the term is 0 when
+ * there are none).  Kinks (a pair at exactly the ideal angle, perpendicular
+ * or parallel lines, equal edge lengths, zero-length edges, a smallest gap
+ * that is zero or attained more than once) contribute 0.  w_min_angle = 0
+ * skips the M_a passes.  The coordinates must satisfy the layout
+ * preconditions (the crossing set is exact on integers).  Weights finite.
  * out_loss: device double[1]; out_grad_x, out_grad_y: device double[n_nodes]
  * (overwritten); out_count: device uint64[1] or NULL -- |S| = E_c. */
 rb_status rb_loss_grad(const float *x, const float *y, int64_t n_nodes,
                        const int32_t *src, const int32_t *dst, int64_t n_edges,
                        double ideal_angle, double w_angle, double w_length,
-                       double *out_loss, double *out_grad_x, double *out_grad_y,
-                       uint64_t *out_count, void *ws, size_t ws_bytes, void *stream);
+                       double w_min_angle, double *out_loss, double *out_grad_x,
+                       double *out_grad_y, uint64_t *out_count, void *ws, size_t ws_bytes,
+                       void *stream);
 
 /* Checks the layout preconditions listed above on the GPU and waits for the
  * result (this call synchronises `stream`).  Returns RB_OK or RB_EDOMAIN;

@@ -44,8 +44,8 @@ _SIGS = {
     "rb_node_occlusion_grid": ([_vp, _vp, _i64, _f64, _vp, _vp, _sz, _vp], C.c_int),
     "rb_crossing_angle_pruned": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _vp, _vp, _vp, _vp, _sz,
                                   _vp], C.c_int),
-    "rb_loss_grad_pruned": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, _f64, _vp, _vp, _vp,
-                             _vp, _vp, _sz, _vp], C.c_int),
+    "rb_loss_grad_pruned": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, _f64, _f64, _vp, _vp,
+                             _vp, _vp, _vp, _sz, _vp], C.c_int),
     "rb_enhanced_workspace_size": ([_i64, C.c_uint64], _sz),
     "rb_enhanced_crossing": ([_vp, _vp, _i64, _vp, _vp, _i64, _i64, C.c_int, _f64, _vp, _vp, _vp,
                               C.POINTER(C.c_uint64), _vp, _sz, _vp], C.c_int),
@@ -54,8 +54,8 @@ _SIGS = {
                                 C.c_int),
     "rb_node_occlusion_shard": ([_vp, _vp, _i64, _f64, _i64, _i64, _vp, C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), _vp, _sz, _vp], C.c_int),
-    "rb_loss_grad": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, _f64, _vp, _vp, _vp, _vp, _vp,
-                      _sz, _vp], C.c_int),
+    "rb_loss_grad": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, _f64, _f64, _vp, _vp, _vp, _vp,
+                      _vp, _sz, _vp], C.c_int),
     "rb_autotune": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, C.c_int, C.POINTER(C.c_double),
                      _vp, _sz, _vp], C.c_int),
     "rb_tune_set": ([C.c_int, C.c_int, _i64, C.c_int], C.c_int),

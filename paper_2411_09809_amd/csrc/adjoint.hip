@@ -298,15 +298,21 @@ int g_adj_list_grid = 0;
 
 hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                             const int32_t *dst, int64_t n_edges, double ideal, double w_a,
-                            double w_l, double *out_loss, double *gx, double *gy,
+                            double w_l, double w_m, double *out_loss, double *gx, double *gy,
                             unsigned long long *out_count, const WsLayout &L, char *w,
                             hipStream_t st) {
     EdgeRec *rec = (EdgeRec *)(w + L.edge_rec);
     Scalars *sc = (Scalars *)(w + L.scalars);
     int *kacc = (int *)(w + L.kacc);
-    unsigned long long *fw_count = (unsigned long long *)(w + L.fwd);
-    double *fw_eca = (double *)(w + L.fwd) + 1;
-    double *fw_ml = (double *)(w + L.fwd) + 2;
+    Fwd *fw = (Fwd *)(w + L.fwd);
+    unsigned long long *fw_count = &fw->count;
+    double *fw_eca = &fw->eca;
+    double *fw_ml = &fw->ml;
+    const MinAngleBufs mab = min_angle_bufs(L, w);
+    // M_a first: its pass starts by clearing the scalar block
+    if (w_m != 0.0)
+        RB_TRY(launch_min_angle(x, y, n_nodes, src, dst, n_edges, mab, &fw->ma, &fw->sum_dv,
+                                &fw->n_used, st));
     // one sweep gives the forward terms (crossing count, deviation sum) and
     // the integer adjoint counts per edge; M_l and the mean length come from
     // the edge-length pass
@@ -344,23 +350,32 @@ hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, con
     RB_TRY(hipGetLastError());
     hipLaunchKernelGGL(edge_grad_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, rec, kacc,
                        n_edges, n_edges, sc, ideal, w_a, w_l, gx, gy, out_loss);
-    return hipGetLastError();
+    RB_TRY(hipGetLastError());
+    if (w_m == 0.0) return hipSuccess;
+    return launch_min_angle_grad(x, y, n_nodes, src, dst, n_edges, mab, w_m, &fw->ma, &fw->n_used,
+                                 &fw->big_count, out_loss, gx, gy, st);
 }
 
 hipError_t launch_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
                                    const int32_t *src, const int32_t *dst, int64_t n_edges,
-                                   double ideal, double w_a, double w_l, double *out_loss,
-                                   double *gx, double *gy, unsigned long long *out_count,
-                                   const GridWs &G, char *w, hipStream_t st) {
+                                   double ideal, double w_a, double w_l, double w_m,
+                                   double *out_loss, double *gx, double *gy,
+                                   unsigned long long *out_count, const GridWs &G, char *w,
+                                   hipStream_t st) {
+    Fwd *fw = (Fwd *)(w + G.fwd);
+    const MinAngleBufs mab = min_angle_bufs(G, w);
+    if (w_m != 0.0)
+        RB_TRY(launch_min_angle(x, y, n_nodes, src, dst, n_edges, mab, &fw->ma, &fw->sum_dv,
+                                &fw->n_used, st));
     // the pruned plan (records in Hilbert order, unit list of 2-row tiles),
     // then the same fused sweep over the kept units only
     RB_TRY(launch_prune_plan(x, y, n_nodes, src, dst, n_edges, kAdjRows, G, w, st));
     const EdgeRec *rec = (const EdgeRec *)(w + G.rec);
     Scalars *sc = (Scalars *)(w + G.scalars);
     int *kacc = (int *)(w + G.kacc);
-    unsigned long long *fw_count = (unsigned long long *)(w + G.fwd);
-    double *fw_eca = (double *)(w + G.fwd) + 1;
-    double *fw_ml = (double *)(w + G.fwd) + 2;
+    unsigned long long *fw_count = &fw->count;
+    double *fw_eca = &fw->eca;
+    double *fw_ml = &fw->ml;
     RB_TRY(launch_zero_scalars(sc, st));
     RB_TRY(launch_elv(x, y, src, dst, n_nodes, n_edges, (double *)(w + G.partial), sc, fw_ml,
                       nullptr, st));
@@ -392,7 +407,10 @@ hipError_t launch_loss_grad_pruned(const float *x, const float *y, int64_t n_nod
     RB_TRY(hipGetLastError());
     hipLaunchKernelGGL(edge_grad_kernel, dim3(grid_for(G.n_edge_pad)), dim3(256), 0, st, rec,
                        kacc, G.n_edge_pad, n_edges, sc, ideal, w_a, w_l, gx, gy, out_loss);
-    return hipGetLastError();
+    RB_TRY(hipGetLastError());
+    if (w_m == 0.0) return hipSuccess;
+    return launch_min_angle_grad(x, y, n_nodes, src, dst, n_edges, mab, w_m, &fw->ma, &fw->n_used,
+                                 &fw->big_count, out_loss, gx, gy, st);
 }
 
 }  // namespace rb

@@ -162,11 +162,12 @@ bool ws_layout(int64_t n_nodes, int64_t n_edges, WsLayout *L) {
     L->cursor = take(sizeof(uint32_t) * (size_t)V);
     L->offs = take(sizeof(uint32_t) * (size_t)(V + 1));
     L->angles = take(sizeof(double) * (size_t)(2 * E));
+    L->nbr = take(sizeof(int32_t) * (size_t)(2 * E));
     L->dv = take(sizeof(double) * (size_t)V);
     L->big_list = take(sizeof(int32_t) * (size_t)V);
     L->hash = take(sizeof(unsigned long long) * (size_t)h);
     L->kacc = take(sizeof(int32_t) * (size_t)L->n_edge_pad);
-    L->fwd = take(sizeof(double) * 4);
+    L->fwd = take(sizeof(Fwd));
     L->total = off;
     return true;
 }
@@ -466,9 +467,9 @@ rb_status rb_min_angle(const float *x, const float *y, int64_t n_nodes, const in
     if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
-    hipError_t e = launch_min_angle(x, y, n_nodes, src, dst, n_edges, L, (char *)ws, out_metric,
-                                    out_sum_dv, (unsigned long long *)out_n_used,
-                                    (hipStream_t)stream);
+    hipError_t e = launch_min_angle(x, y, n_nodes, src, dst, n_edges,
+                                    min_angle_bufs(L, (char *)ws), out_metric, out_sum_dv,
+                                    (unsigned long long *)out_n_used, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "min_angle launch");
     return RB_OK;
 }
@@ -493,8 +494,9 @@ rb_status rb_edge_length_variation(const float *x, const float *y, int64_t n_nod
 
 rb_status rb_loss_grad(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                        const int32_t *dst, int64_t n_edges, double ideal_angle, double w_angle,
-                       double w_length, double *out_loss, double *out_grad_x, double *out_grad_y,
-                       uint64_t *out_count, void *ws, size_t ws_bytes, void *stream) {
+                       double w_length, double w_min_angle, double *out_loss, double *out_grad_x,
+                       double *out_grad_y, uint64_t *out_count, void *ws, size_t ws_bytes,
+                       void *stream) {
     g_err.clear();
     rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
     if (s) return s;
@@ -502,12 +504,12 @@ rb_status rb_loss_grad(const float *x, const float *y, int64_t n_nodes, const in
         return fail(RB_EINVAL, "out_loss, out_grad_x or out_grad_y is NULL");
     if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
         return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
-    if (!std::isfinite(w_angle) || !std::isfinite(w_length))
+    if (!std::isfinite(w_angle) || !std::isfinite(w_length) || !std::isfinite(w_min_angle))
         return fail(RB_EINVAL, "weights must be finite");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
     hipError_t e = launch_loss_grad(x, y, n_nodes, src, dst, n_edges, ideal_angle, w_angle,
-                                    w_length, out_loss, out_grad_x, out_grad_y,
+                                    w_length, w_min_angle, out_loss, out_grad_x, out_grad_y,
                                     (unsigned long long *)out_count, L, (char *)ws,
                                     (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rb_loss_grad launch");
@@ -517,8 +519,9 @@ rb_status rb_loss_grad(const float *x, const float *y, int64_t n_nodes, const in
 rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
                               const int32_t *src, const int32_t *dst, int64_t n_edges,
                               double ideal_angle, double w_angle, double w_length,
-                              double *out_loss, double *out_grad_x, double *out_grad_y,
-                              uint64_t *out_count, void *ws, size_t ws_bytes, void *stream) {
+                              double w_min_angle, double *out_loss, double *out_grad_x,
+                              double *out_grad_y, uint64_t *out_count, void *ws, size_t ws_bytes,
+                              void *stream) {
     g_err.clear();
     rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
     if (s) return s;
@@ -526,7 +529,7 @@ rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
         return fail(RB_EINVAL, "out_loss, out_grad_x or out_grad_y is NULL");
     if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
         return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
-    if (!std::isfinite(w_angle) || !std::isfinite(w_length))
+    if (!std::isfinite(w_angle) || !std::isfinite(w_length) || !std::isfinite(w_min_angle))
         return fail(RB_EINVAL, "weights must be finite");
     if (n_edges > kMaxPrunedEdges)
         return fail(RB_EINVAL, "n_edges = %lld above the pruned path's limit 2^24",
@@ -538,7 +541,8 @@ rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
     if (ws_bytes < G.total)
         return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, G.total);
     hipError_t e = launch_loss_grad_pruned(x, y, n_nodes, src, dst, n_edges, ideal_angle,
-                                           w_angle, w_length, out_loss, out_grad_x, out_grad_y,
+                                           w_angle, w_length, w_min_angle, out_loss, out_grad_x,
+                                           out_grad_y,
                                            (unsigned long long *)out_count, G, (char *)ws,
                                            (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rb_loss_grad_pruned launch");

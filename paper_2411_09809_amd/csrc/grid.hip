@@ -465,7 +465,15 @@ bool grid_ws_layout(int64_t n_nodes, int64_t n_edges, GridWs *G) {
     G->list = take(sizeof(int32_t) * std::max<int64_t>(G->max_units, 1));
     G->kacc = take(sizeof(int32_t) * G->n_edge_pad);
     G->scalars = take(sizeof(Scalars));
-    G->fwd = take(sizeof(double) * 4);
+    G->fwd = take(sizeof(Fwd));
+    const int64_t V = std::max<int64_t>(n_nodes, 1);
+    G->deg = take(sizeof(uint32_t) * V);
+    G->cursor = take(sizeof(uint32_t) * V);
+    G->offs = take(sizeof(uint32_t) * (V + 1));
+    G->angles = take(sizeof(double) * 2 * me);
+    G->nbr = take(sizeof(int32_t) * 2 * me);
+    G->dv = take(sizeof(double) * V);
+    G->big_list = take(sizeof(int32_t) * V);
     G->n_sort_blocks = nb;
     G->total = off;
     return true;

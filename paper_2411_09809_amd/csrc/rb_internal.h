@@ -88,7 +88,7 @@ SweepVariant occl_variant(int v);
 // Layout of the caller's workspace for one layout (byte offsets, 256-aligned).
 struct WsLayout {
     size_t edge_rec, node_rec, partial, scalars;
-    size_t deg, cursor, offs, angles, dv, big_list, hash, kacc, fwd;
+    size_t deg, cursor, offs, angles, nbr, dv, big_list, hash, kacc, fwd;
     size_t total;
     int64_t n_edge_pad, n_node_pad, hash_size;
 };
@@ -105,6 +105,7 @@ struct GridWs {
     size_t params, keys, vals, keys2, vals2, pos, hist, hist_off, scan_tile, partial;
     size_t rec, box, tile_cnt, tile_off, list;   // pruned edge sweep
     size_t kacc, scalars, fwd;                    // pruned loss and gradient
+    size_t deg, cursor, offs, angles, nbr, dv, big_list;   // minimum-angle term
     size_t total;
     int64_t n_sort_blocks, n_edge_pad, max_units;
 };
@@ -124,6 +125,38 @@ struct __align__(16) Scalars {
     int32_t flags;
     int32_t pad;
 };
+
+// Forward results kept between the passes of the loss-and-gradient calls
+// (the call's `fwd` region, 8 words).
+struct Fwd {
+    unsigned long long count;   // E_c
+    double eca, ml, ma;         // E_ca, M_l, M_a
+    unsigned long long n_used;  // vertices of degree >= 1
+    unsigned long long big_count;
+    double sum_dv;
+    double pad;
+};
+
+// Buffers of the minimum-angle pass: per-node degree, fill cursor, CSR
+// offsets, per-half-edge direction angle and far end, per-node d_v, the
+// queue of high-degree nodes, the scalar block and the reduction partials.
+struct MinAngleBufs {
+    uint32_t *deg, *cursor, *offs;
+    double *ang, *dv;
+    int32_t *nbr, *big;
+    Scalars *sc;
+    double *partial;
+};
+inline MinAngleBufs min_angle_bufs(const WsLayout &L, char *w) {
+    return {(uint32_t *)(w + L.deg),  (uint32_t *)(w + L.cursor), (uint32_t *)(w + L.offs),
+            (double *)(w + L.angles), (double *)(w + L.dv),       (int32_t *)(w + L.nbr),
+            (int32_t *)(w + L.big_list), (Scalars *)(w + L.scalars), (double *)(w + L.partial)};
+}
+inline MinAngleBufs min_angle_bufs(const GridWs &G, char *w) {
+    return {(uint32_t *)(w + G.deg),  (uint32_t *)(w + G.cursor), (uint32_t *)(w + G.offs),
+            (double *)(w + G.angles), (double *)(w + G.dv),       (int32_t *)(w + G.nbr),
+            (int32_t *)(w + G.big_list), (Scalars *)(w + G.scalars), (double *)(w + G.partial)};
+}
 
 // ------------------------------------------------------------------ plans
 struct SweepPlan {
@@ -168,8 +201,17 @@ hipError_t launch_elv(const float *x, const float *y, const int32_t *src, const 
 
 hipError_t launch_min_angle(const float *x, const float *y, int64_t n_nodes,
                             const int32_t *src, const int32_t *dst, int64_t n_edges,
-                            const WsLayout &L, char *ws, double *out_metric,
-                            double *out_sum_dv, unsigned long long *out_n_used, hipStream_t st);
+                            const MinAngleBufs &B, double *out_metric, double *out_sum_dv,
+                            unsigned long long *out_n_used, hipStream_t st);
+// Loss term w_m (1 - M_a) and its gradient, after launch_min_angle wrote M_a
+// to *ma and the used-vertex count to *n_used: adds the term to *out_loss and
+// scatters its gradient into gx, gy (which already hold the other terms).
+hipError_t launch_min_angle_grad(const float *x, const float *y, int64_t n_nodes,
+                                 const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                 const MinAngleBufs &B, double w_m, const double *ma,
+                                 const unsigned long long *n_used,
+                                 unsigned long long *big_count, double *out_loss, double *gx,
+                                 double *gy, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
@@ -182,7 +224,7 @@ hipError_t launch_min_angle_nodes(const uint32_t *deg, const uint32_t *offs, dou
                                   int64_t n_nodes, double *dv, int32_t *big, Scalars *sc,
                                   hipStream_t st);
 
-// loss w_a (1 - E_ca) + w_l M_l and its gradient with respect to x, y
+// loss w_a (1 - E_ca) + w_l M_l + w_m (1 - M_a) and its gradient with respect to x, y
 hipError_t launch_radix_sort(uint32_t *keys, int32_t *vals, uint32_t *keys2, int32_t *vals2,
                              int64_t n, uint32_t *hist, uint32_t *hist_off,
                              unsigned long long *scan_tile, hipStream_t st);
@@ -201,9 +243,10 @@ hipError_t launch_prune_plan(const float *x, const float *y, int64_t n_nodes,
                              const GridWs &G, char *w, hipStream_t st);
 hipError_t launch_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
                                    const int32_t *src, const int32_t *dst, int64_t n_edges,
-                                   double ideal, double w_a, double w_l, double *out_loss,
-                                   double *gx, double *gy, unsigned long long *out_count,
-                                   const GridWs &G, char *w, hipStream_t st);
+                                   double ideal, double w_a, double w_l, double w_m,
+                                   double *out_loss, double *gx, double *gy,
+                                   unsigned long long *out_count, const GridWs &G, char *w,
+                                   hipStream_t st);
 hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_nodes,
                                   const int32_t *src, const int32_t *dst, int64_t n_edges,
                                   double ideal, const GridWs &G, char *w, int variant,
@@ -225,7 +268,7 @@ hipError_t launch_occlusion_grid(const float *x, const float *y, int64_t n, doub
                                  hipStream_t st);
 hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                             const int32_t *dst, int64_t n_edges, double ideal, double w_a,
-                            double w_l, double *out_loss, double *gx, double *gy,
+                            double w_l, double w_m, double *out_loss, double *gx, double *gy,
                             unsigned long long *out_count, const WsLayout &L, char *w,
                             hipStream_t st);
 

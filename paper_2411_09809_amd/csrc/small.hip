@@ -181,7 +181,8 @@ __global__ __launch_bounds__(256) void fill_angles_kernel(const float *__restric
                                                           int64_t n_nodes, int64_t n_edges,
                                                           const uint32_t *__restrict__ offs,
                                                           uint32_t *cursor,
-                                                          double *__restrict__ ang) {
+                                                          double *__restrict__ ang,
+                                                          int32_t *__restrict__ nbr) {
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n_edges; e += (int64_t)gridDim.x * 256) {
         const int32_t s = src[e], t = dst[e];
         if (!valid_ids(s, t, n_nodes)) continue;
@@ -195,6 +196,10 @@ __global__ __launch_bounds__(256) void fill_angles_kernel(const float *__restric
         const double rdy = (double)y[s] - (double)y[t];
         ang[ps] = direction_angle(dx, dy);       // at s, towards t
         ang[pt] = direction_angle(rdx, rdy);     // at t, towards s
+        if (nbr) {                               // the far end of each half-edge
+            nbr[ps] = t;
+            nbr[pt] = s;
+        }
     }
 }
 
@@ -299,6 +304,209 @@ __global__ __launch_bounds__(256) void min_angle_big_kernel(
         if (threadIdx.x == 0) dv[v] = dv_of(red[0], d);
         __syncthreads();
     }
+}
+
+// ------------------------------------------------ minimum-angle gradient
+//
+// Term T = w_m (1 - M_a), 1 - M_a = 1 - (1/N) sum_v phi_v deg_v / (2 pi) over
+// the N vertices of degree >= 1.  phi_v, the smallest gap between v's sorted
+// directions, moves with the two directions p -> q that bound it:
+// dT/dphi_v = -w_m deg_v / (2 pi N); a direction of v -> u turns as
+// (-dy, dx) / l^2 with u (and the opposite with v).  A vertex contributes only
+// if its smallest gap is attained once, is nonzero and both bounding edges
+// have nonzero length (the kinks contribute 0).  Gaps are formed exactly as
+// in the sorted sweep of Algorithm 2: a_next - a, and (2 pi - a_last) + a_first.
+
+__device__ __forceinline__ void ma_scatter(const float *x, const float *y, int32_t v, int32_t up,
+                                           int32_t uq, double c, double *gx, double *gy) {
+    const double pdx = (double)x[up] - (double)x[v], pdy = (double)y[up] - (double)y[v];
+    const double qdx = (double)x[uq] - (double)x[v], qdy = (double)y[uq] - (double)y[v];
+    const double pl2 = fma(pdx, pdx, pdy * pdy), ql2 = fma(qdx, qdx, qdy * qdy);
+    if (pl2 == 0.0 || ql2 == 0.0) return;
+    // phi = alpha_q - alpha_p
+    const double qx = c * -qdy / ql2, qy = c * qdx / ql2;
+    const double px = c * -pdy / pl2, py = c * pdx / pl2;
+    atomicAdd(&gx[uq], qx);
+    atomicAdd(&gy[uq], qy);
+    atomicAdd(&gx[up], -px);
+    atomicAdd(&gy[up], -py);
+    atomicAdd(&gx[v], px - qx);
+    atomicAdd(&gy[v], py - qy);
+}
+
+// degree 2 .. kSmallDeg: one thread per vertex.  Directions are taken in
+// (angle, slot) order; the gap after direction i runs to its successor in
+// that order, the gap after the last direction wraps to the first.
+__global__ __launch_bounds__(256) void ma_grad_small_kernel(
+    const float *__restrict__ x, const float *__restrict__ y, const uint32_t *__restrict__ deg,
+    const uint32_t *__restrict__ offs, const double *__restrict__ ang,
+    const int32_t *__restrict__ nbr, int64_t n_nodes, double w_m,
+    const unsigned long long *__restrict__ n_used, int32_t *__restrict__ big,
+    unsigned long long *big_count, double *gx, double *gy) {
+    const unsigned long long N = *n_used;
+    if (N == 0) return;
+    const double c0 = -w_m / ((double)N * kTwoPi);
+    for (int64_t v = blockIdx.x * 256 + threadIdx.x; v < n_nodes; v += (int64_t)gridDim.x * 256) {
+        const uint32_t d = deg[v];
+        if (d < 2) continue;
+        if (d > (uint32_t)kSmallDeg) {
+            big[atomicAdd(big_count, 1ull)] = (int32_t)v;
+            continue;
+        }
+        const uint32_t o = offs[v];
+        double a[kSmallDeg];
+#pragma unroll
+        for (int i = 0; i < kSmallDeg; ++i) a[i] = (uint32_t)i < d ? ang[o + i] : 0.0;
+        // first and last directions in (angle, slot) order
+        double alo = a[0], ahi = a[0];
+        int lo = 0;
+#pragma unroll
+        for (int i = 1; i < kSmallDeg; ++i) {
+            if ((uint32_t)i < d) {
+                if (a[i] < alo) {
+                    alo = a[i];
+                    lo = i;
+                }
+                if (a[i] >= ahi) ahi = a[i];
+            }
+        }
+        double phi = kTwoPi;
+        int at_p = -1, at_q = -1, ties = 0;
+#pragma unroll
+        for (int i = 0; i < kSmallDeg; ++i) {
+            if ((uint32_t)i >= d) continue;
+            int nx = -1;                     // successor of (a_i, i)
+            double an = 0.0;
+#pragma unroll
+            for (int j = 0; j < kSmallDeg; ++j) {
+                if ((uint32_t)j >= d || j == i) continue;
+                const bool after = j > i ? a[j] >= a[i] : a[j] > a[i];
+                if (after && (nx < 0 || a[j] < an)) {
+                    nx = j;
+                    an = a[j];
+                }
+            }
+            const double g = nx >= 0 ? an - a[i] : (kTwoPi - ahi) + alo;
+            if (nx < 0) nx = lo;
+            if (g < phi) {
+                phi = g;
+                at_p = i;
+                at_q = nx;
+                ties = 1;
+            } else if (g == phi) {
+                ++ties;
+            }
+        }
+        if (ties != 1 || !(phi > 0.0)) continue;
+        ma_scatter(x, y, (int32_t)v, nbr[o + at_p], nbr[o + at_q], c0 * (double)d, gx, gy);
+    }
+}
+
+// (angle, slot) pairs sorted together by the bitonic network of block_sort
+__device__ void block_sort_pairs(double *a, int32_t *p, uint32_t n) {
+    uint32_t P = 1;
+    while (P < n) P <<= 1;
+    const uint32_t half = P >> 1;
+    auto cmpx = [&](uint32_t i, uint32_t j) {
+        const double u = a[i], w = a[j];
+        if (w < u || (w == u && p[j] < p[i])) {
+            a[i] = w; a[j] = u;
+            const int32_t t = p[i]; p[i] = p[j]; p[j] = t;
+        }
+    };
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        const uint32_t hk = k >> 1;
+        for (uint32_t q = threadIdx.x; q < half; q += blockDim.x) {
+            const uint32_t i = (q / hk) * k + (q % hk);
+            const uint32_t j = i ^ (k - 1);
+            if (j < n) cmpx(i, j);
+        }
+        __syncthreads();
+        for (uint32_t s = hk >> 1; s > 0; s >>= 1) {
+            for (uint32_t q = threadIdx.x; q < half; q += blockDim.x) {
+                const uint32_t i = (q / s) * (2 * s) + (q % s);
+                const uint32_t j = i + s;
+                if (j < n) cmpx(i, j);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// degree > kSmallDeg: one block per vertex; sorts the vertex's (angle,
+// neighbour) pairs in LDS, or in place in the arrays beyond kLdsDeg
+__global__ __launch_bounds__(256) void ma_grad_big_kernel(
+    const float *__restrict__ x, const float *__restrict__ y, const uint32_t *__restrict__ deg,
+    const uint32_t *__restrict__ offs, double *ang, int32_t *nbr,
+    const int32_t *__restrict__ big, const unsigned long long *big_count, double w_m,
+    const unsigned long long *__restrict__ n_used, double *gx, double *gy) {
+    __shared__ double sa[kLdsDeg];
+    __shared__ int32_t sp[kLdsDeg];
+    __shared__ double rv[256];
+    __shared__ int32_t ri[256];
+    __shared__ uint32_t rt[256];
+    const unsigned long long n_big = *big_count, N = *n_used;
+    const double c0 = N ? -w_m / ((double)N * kTwoPi) : 0.0;
+    for (unsigned long long k = blockIdx.x; k < n_big; k += gridDim.x) {
+        const int32_t v = big[k];
+        const uint32_t d = deg[v];
+        double *a = ang + offs[v];
+        int32_t *p = nbr + offs[v];
+        if (d <= (uint32_t)kLdsDeg) {
+            for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) {
+                sa[i] = a[i];
+                sp[i] = p[i];
+            }
+            a = sa;
+            p = sp;
+        }
+        __syncthreads();
+        block_sort_pairs(a, p, d);
+        // smallest gap, its first position, and how many gaps attain it
+        double best = kTwoPi;
+        int32_t at = -1;
+        for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) {
+            const double g = i + 1 < d ? a[i + 1] - a[i] : (kTwoPi - a[d - 1]) + a[0];
+            if (g < best) { best = g; at = (int32_t)i; }
+        }
+        rv[threadIdx.x] = best;
+        ri[threadIdx.x] = at;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s) {
+                const double o = rv[threadIdx.x + s];
+                if (o < rv[threadIdx.x]) {
+                    rv[threadIdx.x] = o;
+                    ri[threadIdx.x] = ri[threadIdx.x + s];
+                }
+            }
+            __syncthreads();
+        }
+        const double phi = rv[0];
+        const int32_t at0 = ri[0];
+        uint32_t ties = 0;
+        for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) {
+            const double g = i + 1 < d ? a[i + 1] - a[i] : (kTwoPi - a[d - 1]) + a[0];
+            ties += g == phi ? 1u : 0u;
+        }
+        rt[threadIdx.x] = ties;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (threadIdx.x < s) rt[threadIdx.x] += rt[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && rt[0] == 1 && phi > 0.0 && at0 >= 0) {
+            const uint32_t q = (uint32_t)at0 + 1 < d ? (uint32_t)at0 + 1 : 0u;
+            ma_scatter(x, y, v, p[at0], p[q], c0 * (double)d, gx, gy);
+        }
+        __syncthreads();
+    }
+}
+
+// loss += w_m (1 - M_a) over the vertices of degree >= 1
+__global__ void ma_loss_kernel(double *out_loss, double w_m, const double *ma,
+                               const unsigned long long *n_used) {
+    if (threadIdx.x == 0 && *n_used) *out_loss += w_m * (1.0 - *ma);
 }
 
 __global__ __launch_bounds__(256) void dv_sum_kernel(const uint32_t *__restrict__ deg,
@@ -493,41 +701,62 @@ hipError_t launch_min_angle_nodes(const uint32_t *deg, const uint32_t *offs, dou
 }
 
 hipError_t launch_min_angle(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
-                            const int32_t *dst, int64_t n_edges, const WsLayout &L, char *ws,
+                            const int32_t *dst, int64_t n_edges, const MinAngleBufs &B,
                             double *out_metric, double *out_sum_dv,
                             unsigned long long *out_n_used, hipStream_t st) {
-    uint32_t *deg = (uint32_t *)(ws + L.deg);
-    uint32_t *cursor = (uint32_t *)(ws + L.cursor);
-    uint32_t *offs = (uint32_t *)(ws + L.offs);
-    double *ang = (double *)(ws + L.angles);
-    double *dv = (double *)(ws + L.dv);
-    int32_t *big = (int32_t *)(ws + L.big_list);
-    Scalars *sc = (Scalars *)(ws + L.scalars);
-    double *partial = (double *)(ws + L.partial);
-    unsigned long long *used = (unsigned long long *)(ws + L.partial) + kRedGrid;
-    unsigned long long *tile = (unsigned long long *)dv;   // dv is written only later
+    unsigned long long *used = (unsigned long long *)B.partial + kRedGrid;
+    unsigned long long *tile = (unsigned long long *)B.dv;   // dv is written only later
 
     const int64_t V = n_nodes > 0 ? n_nodes : 1;
-    RB_TRY(launch_zero_scalars(sc, st));
-    RB_TRY(launch_fill_u32(deg, V, 0u, st));
-    RB_TRY(launch_fill_u32(cursor, V, 0u, st));
+    RB_TRY(launch_zero_scalars(B.sc, st));
+    RB_TRY(launch_fill_u32(B.deg, V, 0u, st));
+    RB_TRY(launch_fill_u32(B.cursor, V, 0u, st));
     if (n_edges > 0) {
         hipLaunchKernelGGL(degree_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, src, dst,
-                           n_nodes, n_edges, deg);
+                           n_nodes, n_edges, B.deg);
         RB_LAUNCHED();
     }
-    RB_TRY(launch_scan(deg, V, tile, offs, st));
+    RB_TRY(launch_scan(B.deg, V, tile, B.offs, st));
     if (n_edges > 0) {
         hipLaunchKernelGGL(fill_angles_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, x, y,
-                           src, dst, n_nodes, n_edges, offs, cursor, ang);
+                           src, dst, n_nodes, n_edges, B.offs, B.cursor, B.ang,
+                           (int32_t *)nullptr);
         RB_LAUNCHED();
     }
-    RB_TRY(launch_min_angle_nodes(deg, offs, ang, n_nodes, dv, big, sc, st));
+    RB_TRY(launch_min_angle_nodes(B.deg, B.offs, B.ang, n_nodes, B.dv, B.big, B.sc, st));
     const int g = grid_for(n_nodes, kRedGrid);
-    hipLaunchKernelGGL(dv_sum_kernel, dim3(g), dim3(256), 0, st, deg, dv, n_nodes, partial, used);
+    hipLaunchKernelGGL(dv_sum_kernel, dim3(g), dim3(256), 0, st, B.deg, B.dv, n_nodes, B.partial,
+                       used);
     RB_LAUNCHED();
-    hipLaunchKernelGGL(dv_final_kernel, dim3(1), dim3(256), 0, st, partial, used, g, out_metric,
+    hipLaunchKernelGGL(dv_final_kernel, dim3(1), dim3(256), 0, st, B.partial, used, g, out_metric,
                        out_sum_dv, out_n_used);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_angle_grad(const float *x, const float *y, int64_t n_nodes,
+                                 const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                 const MinAngleBufs &B, double w_m, const double *ma,
+                                 const unsigned long long *n_used,
+                                 unsigned long long *big_count, double *out_loss, double *gx,
+                                 double *gy, hipStream_t st) {
+    if (out_loss) {
+        hipLaunchKernelGGL(ma_loss_kernel, dim3(1), dim3(64), 0, st, out_loss, w_m, ma, n_used);
+        RB_LAUNCHED();
+    }
+    if (n_edges <= 0 || n_nodes <= 0) return hipSuccess;
+    // the forward pass left the degrees and offsets; the directions are
+    // filled again, now with the far end of every half-edge
+    RB_TRY(launch_fill_u32(B.cursor, n_nodes, 0u, st));
+    RB_TRY(launch_fill_u64(big_count, 1, 0ull, st));
+    hipLaunchKernelGGL(fill_angles_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, x, y, src,
+                       dst, n_nodes, n_edges, B.offs, B.cursor, B.ang, B.nbr);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(ma_grad_small_kernel, dim3(grid_for(n_nodes)), dim3(256), 0, st, x, y,
+                       B.deg, B.offs, B.ang, B.nbr, n_nodes, w_m, n_used, B.big, big_count, gx,
+                       gy);
+    RB_LAUNCHED();
+    hipLaunchKernelGGL(ma_grad_big_kernel, dim3(1024), dim3(256), 0, st, x, y, B.deg, B.offs,
+                       B.ang, B.nbr, B.big, big_count, w_m, n_used, gx, gy);
     return hipGetLastError();
 }
 

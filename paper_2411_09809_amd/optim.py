@@ -1,7 +1,7 @@
 """Layout optimisation with the readability loss (rb_loss_grad of rb.h).
 
 ``CrossingAngleLengthLoss`` is a ``torch.autograd.Function`` for
-    L = w_angle (1 - E_ca) + w_length M_l
+    L = w_angle (1 - E_ca) + w_length M_l + w_min_angle (1 - M_a)
 (crossing set frozen at the evaluated layout): its forward and backward are
 both computed by librb's kernels in one call.  ``descend`` runs gradient
 descent on a float32 master copy of the coordinates, evaluating loss,
@@ -20,10 +20,11 @@ from .metrics import (IDEAL_ANGLE, _check_coords, _check_edges, _stream, _ws_arg
 
 
 def loss_grad(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, w_angle: float = 1.0,
-              w_length: float = 1.0, pruned: bool = False):
+              w_length: float = 1.0, pruned: bool = False, w_min_angle: float = 0.0):
     """(loss, dL/dx, dL/dy, crossing count) as device tensors (float64,
     float64[V], float64[V], int64).  ``pruned`` uses rb_loss_grad_pruned,
-    which skips the tiles of edges whose bounding boxes cannot meet."""
+    which skips the tiles of edges whose bounding boxes cannot meet;
+    ``w_min_angle`` weighs the minimum-angle term 1 - M_a (0 skips it)."""
     _check_coords(x, y)
     _check_edges(x, src, dst)
     dev = x.device
@@ -37,19 +38,22 @@ def loss_grad(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, w_angle: float =
     fn, name = ((lib().rb_loss_grad_pruned, "rb_loss_grad_pruned") if pruned
                 else (lib().rb_loss_grad, "rb_loss_grad"))
     check(fn(x.data_ptr(), y.data_ptr(), n, src.data_ptr(), dst.data_ptr(), src.numel(),
-             float(ideal_angle), float(w_angle), float(w_length), loss.data_ptr(), gx.data_ptr(),
-             gy.data_ptr(), cnt.data_ptr(), w, wb, _stream(dev)), name)
+             float(ideal_angle), float(w_angle), float(w_length), float(w_min_angle),
+             loss.data_ptr(), gx.data_ptr(), gy.data_ptr(), cnt.data_ptr(), w, wb, _stream(dev)),
+          name)
     return loss[0], gx[:n], gy[:n], cnt[0]
 
 
 class CrossingAngleLengthLoss(torch.autograd.Function):
-    """L(x, y) = w_angle (1 - E_ca) + w_length M_l on integer-valued float32
-    coordinates; gradients come back in the coordinates' dtype."""
+    """L(x, y) = w_angle (1 - E_ca) + w_length M_l + w_min_angle (1 - M_a) on
+    integer-valued float32 coordinates; gradients come back in the
+    coordinates' dtype."""
 
     @staticmethod
     def forward(ctx, x, y, src, dst, ideal_angle=IDEAL_ANGLE, w_angle=1.0, w_length=1.0,
-                pruned=False):
-        loss, gx, gy, cnt = loss_grad(x, y, src, dst, ideal_angle, w_angle, w_length, pruned)
+                pruned=False, w_min_angle=0.0):
+        loss, gx, gy, cnt = loss_grad(x, y, src, dst, ideal_angle, w_angle, w_length, pruned,
+                                      w_min_angle)
         ctx.save_for_backward(gx, gy)
         ctx.dtype = x.dtype
         ctx.mark_non_differentiable(cnt)
@@ -59,12 +63,12 @@ class CrossingAngleLengthLoss(torch.autograd.Function):
     def backward(ctx, g_loss, g_cnt):
         gx, gy = ctx.saved_tensors
         return ((g_loss * gx).to(ctx.dtype), (g_loss * gy).to(ctx.dtype), None, None, None, None,
-                None, None)
+                None, None, None)
 
 
 def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
             extent: int = 1 << 16, ideal_angle: float = IDEAL_ANGLE, w_angle: float = 1.0,
-            w_length: float = 1.0, log=None, pruned: bool = False):
+            w_length: float = 1.0, log=None, pruned: bool = False, w_min_angle: float = 0.0):
     """Gradient descent on the readability loss.
 
     A float32 master copy of the coordinates moves by ``step_size`` grid
@@ -80,7 +84,7 @@ def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
         xi = torch.clamp(torch.round(mx), 0, extent - 1).requires_grad_(True)
         yi = torch.clamp(torch.round(my), 0, extent - 1).requires_grad_(True)
         loss, cnt = CrossingAngleLengthLoss.apply(xi, yi, src, dst, ideal_angle, w_angle,
-                                                  w_length, pruned)
+                                                  w_length, pruned, w_min_angle)
         loss.backward()
         with torch.no_grad():
             scale = torch.maximum(xi.grad.abs().max(), yi.grad.abs().max()).clamp_min(1e-300)
