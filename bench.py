@@ -150,9 +150,13 @@ def bench_adjoint(torch, reps: int, gd_steps: int):
     def fwd_bwd_pruned():
         optim.loss_grad(D.x, D.y, D.src, D.dst, pruned=True)
 
+    def fwd_bwd_ma():
+        optim.loss_grad(D.x, D.y, D.src, D.dst, w_min_angle=1.0)
+
     out = {}
     for name, fn in (("forward_ms", fwd), ("forward_backward_ms", fwd_bwd),
-                     ("forward_backward_pruned_ms", fwd_bwd_pruned)):
+                     ("forward_backward_pruned_ms", fwd_bwd_pruned),
+                     ("forward_backward_with_min_angle_ms", fwd_bwd_ma)):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -280,8 +284,9 @@ def bench_approx(torch):
 def bench_optimise(torch, steps: int):
     """End-to-end layout optimisation: the Fruchterman-Reingold layout of the
     4,000-node community graph, `steps` gradient steps on
-    (1 - E_ca) + M_l with the pruned loss and gradient, all five metrics
-    evaluated exactly before and after."""
+    (1 - E_ca) + M_l, and again on (1 - E_ca) + M_l + (1 - M_a), with the
+    pruned loss and gradient, all five metrics evaluated exactly before and
+    after."""
     from paper_2411_09809_amd import gen, metrics, optim
 
     L = gen.force_directed_layout(seed=0)
@@ -296,12 +301,24 @@ def bench_optimise(torch, steps: int):
     D2 = metrics.DeviceLayout(xs.contiguous(), ys.contiguous(), D.src, D.dst, D.diameter,
                               D.ideal_angle)
     after = metrics.evaluate(D2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xm, ym, hist_m = optim.descend(D.x, D.y, D.src, D.dst, steps=steps, step_size=64.0,
+                                   extent=1 << 16, pruned=True, w_min_angle=1.0)
+    torch.cuda.synchronize()
+    secs_m = time.perf_counter() - t0
+    D3 = metrics.DeviceLayout(xm.contiguous(), ym.contiguous(), D.src, D.dst, D.diameter,
+                              D.ideal_angle)
+    after_m = metrics.evaluate(D3)
     keep = ("node_occlusion", "edge_crossing", "crossing_angle", "min_angle",
             "edge_length_variation")
     return {"workload": f"{L.name}: Fruchterman-Reingold layout in [0,2^16)^2, diameter 64",
             "steps": steps, "seconds": secs, "ms_per_step": secs * 1e3 / steps,
             "loss_first_last": [hist[0][0], hist[-1][0]],
-            "before": {k: before[k] for k in keep}, "after": {k: after[k] for k in keep}}
+            "before": {k: before[k] for k in keep}, "after": {k: after[k] for k in keep},
+            "with_min_angle": {"ms_per_step": secs_m * 1e3 / steps,
+                               "loss_first_last": [hist_m[0][0], hist_m[-1][0]],
+                               "after": {k: after_m[k] for k in keep}}}
 
 
 def bench_largest(torch):
