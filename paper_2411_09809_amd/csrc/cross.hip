@@ -39,6 +39,20 @@ __device__ __forceinline__ uint32_t popc_ballot(bool p) {
     return (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
 }
 
+// acc += |v| in the lanes of `mask` only.  The lane mask of the crossing
+// compare selects the lanes through EXEC, which takes two scalar
+// instructions instead of a vector select of an indicator; EXEC is restored
+// within the block.
+__device__ __forceinline__ void add_abs_masked(double &acc, double v, uint64_t mask) {
+    uint64_t saved;
+    __asm__("s_and_saveexec_b64 %1, %2\n\t"
+            "v_add_f64 %0, %0, |%3|\n\t"
+            "s_mov_b64 exec, %1"
+            : "+v"(acc), "=&s"(saved)
+            : "s"(mask), "v"(v)
+            : "scc");
+}
+
 __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
     return I * nC - (int64_t)K * I * (I - 1) / 2;
 }
@@ -52,7 +66,7 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
                                             int tid, int64_t row0, int64_t col0, double ideal,
                                             double angc, uint32_t &n_proper, uint32_t &n_touch,
                                             double &acc) {
-#pragma unroll 2
+#pragma unroll 4
     for (int j = 0; j < kChunk; ++j) {
         const double cX = col[j].x, cY = col[j].y;
         const double cDX = col[j].dx, cDY = col[j].dy;
@@ -73,11 +87,11 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
             const bool in_tri = !DIAG || (col0 + j > row0 + (int64_t)r * kBlock);
             const bool prop = (m < 0.0) & in_tri;
             zr[r] = (m == 0.0) & in_tri;
-            n_proper += popc_ballot(prop);
+            const uint64_t pmask = __builtin_amdgcn_ballot_w64(prop);
+            n_proper += (uint32_t)__popcll(pmask);
             if (ANGLE) {
                 const double u = fabs(rTH[r] - cTH) - kHalfPi;
-                const double v = angc + fabs(u);
-                acc = fma(prop ? 1.0 : 0.0, fabs(v), acc);
+                add_abs_masked(acc, angc + fabs(u), pmask);
             }
             any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
         }
