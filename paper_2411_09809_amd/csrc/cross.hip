@@ -96,17 +96,18 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
             any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
         }
         if (__builtin_expect(any_zero != 0, 0)) {
+            // most such pairs share an end id (the incident edges of a hub):
+            // the id test comes first and the rest runs only for the others
             double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC, fth = cTH;
             __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc), "+v"(fth));
             const int2 fid = make_int2(col[j].s, col[j].t);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 bool ok = false;
-                if (zr[r]) {
+                if (zr[r] && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
                     double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
                     __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
-                    ok = dev::touching_pair(ex, ey, edx, edy, ec, rid[r * kBlock + tid], fx, fy, fdx,
-                                       fdy, fc, fid);
+                    ok = dev::touching_apart(ex, ey, edx, edy, ec, fx, fy, fdx, fdy, fc);
                     if (ANGLE && ok) {
                         // parallel lines or a zero-length edge: a = 0
                         const double crs = fma(-edy, fdx, edx * fdy);
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(256) void cross_finalize_kernel(
     }
 }
 
-constexpr SweepVariant kCross[kCrossVariants] = {{1, 7}, {2, 5}, {4, 4}, {4, 3}};
+constexpr SweepVariant kCross[kCrossVariants] = {{1, 8}, {2, 7}, {4, 4}, {4, 3}};
 
 template <int V>
 struct CrossV {

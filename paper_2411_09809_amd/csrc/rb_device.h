@@ -48,24 +48,34 @@ __device__ __noinline__ inline bool boxes_meet(double rx, double ry, double rdx,
     return (fmax(ax0, bx0) <= fmin(ax1, bx1)) && (fmax(ay0, by0) <= fmin(ay1, by1));
 }
 
-// Decision for an edge pair (row edge P + t D, column edge F + s G, with line
-// constants c = D x P) whose larger orientation product is zero.  Pairs
-// sharing an end id are never crossings (incident edges always have both
-// products zero); otherwise a negative product means the segments meet at an
-// end point of one of them, and two zero products need the box test.
+// Pairs whose larger orientation product is zero.  Edges that share an end
+// id are never crossings (incident edges always have both products zero).
+__device__ __forceinline__ bool incident_ids(int2 a, int2 b) {
+    return (a.x == b.x) | (a.x == b.y) | (a.y == b.x) | (a.y == b.y);
+}
+
+// Decision for a pair of edges that share no end id (row edge P + t D,
+// column edge F + s G, with line constants c = D x P) whose larger
+// orientation product is zero: a negative product means the segments meet
+// at an end point of one of them, and two zero products need the box test.
 // Callers pass register copies the compiler cannot see through, which keeps
 // this arithmetic out of their common path.
-__device__ __forceinline__ bool touching_pair(double rx, double ry, double rdx, double rdy,
-                                              double rc, int2 rid, double fx, double fy,
-                                              double fdx, double fdy, double fc, int2 fid) {
-    const bool incident = (rid.x == fid.x) | (rid.x == fid.y) | (rid.y == fid.x) | (rid.y == fid.y);
+__device__ __forceinline__ bool touching_apart(double rx, double ry, double rdx, double rdy,
+                                               double rc, double fx, double fy, double fdx,
+                                               double fdy, double fc) {
     const double o1 = fma(-rdy, fx, fma(rdx, fy, -rc));
     const double o3 = fma(-fdy, rx, fma(fdx, ry, -fc));
     const double cr = fma(-rdy, fdx, rdx * fdy);
     const double p12 = o1 * (o1 + cr), p34 = o3 * (o3 - cr);
-    bool ok = !incident && fmin(p12, p34) < 0.0;
-    if (!incident && p12 == 0.0 && p34 == 0.0) ok = boxes_meet(rx, ry, rdx, rdy, fx, fy, fdx, fdy);
+    bool ok = fmin(p12, p34) < 0.0;
+    if (p12 == 0.0 && p34 == 0.0) ok = boxes_meet(rx, ry, rdx, rdy, fx, fy, fdx, fdy);
     return ok;
+}
+
+__device__ __forceinline__ bool touching_pair(double rx, double ry, double rdx, double rdy,
+                                              double rc, int2 rid, double fx, double fy,
+                                              double fdx, double fdy, double fc, int2 fid) {
+    return !incident_ids(rid, fid) && touching_apart(rx, ry, rdx, rdy, rc, fx, fy, fdx, fdy, fc);
 }
 
 // sum over the block (blockDim.x a power of two <= 1024); sh has blockDim.x slots
