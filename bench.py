@@ -37,7 +37,8 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # other's line, 2 for the cross product of the directions (the other ends'
 # orientations follow by one add each), 2 muls and 2 adds for the two sign
 # products, 1 max, 2 classifying compares, and 4 for the angle term
-# (difference of line angles, fold, deviation, indicator FMA).
+# (difference of line angles, fold, deviation, accumulate under the crossing
+# mask).
 OPS_PER_EDGE_PAIR = 17
 # per node pair of the occlusion test: 2 FMA + 1 max (the exact count runs
 # only for the rare chunks that hold an occluding pair)
@@ -46,8 +47,8 @@ OPS_PER_NODE_PAIR = 3
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy: x2.000 and
 # x1.000), by (rows per thread, waves per SIMD).  Valid only for the kernel
 # source they were measured on (first 16 hex digits of its sha256).
-MEASURED_TRAFFIC = {"source_sha": "315e8b1da38d1aa4",
-                    "bytes": {(4, 3): 345.1e6, (4, 4): 347.0e6, (2, 5): 622.3e6, (1, 7): 1133.6e6}}
+MEASURED_TRAFFIC = {"source_sha": "e0f52f22b6176bda",
+                    "bytes": {(4, 3): 358.8e6, (4, 4): 358.9e6, (2, 7): 598.4e6, (1, 8): 1143.4e6}}
 
 
 def measured_traffic(rows, waves):
