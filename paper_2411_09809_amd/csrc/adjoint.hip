@@ -36,6 +36,29 @@ __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
     return I * nC - (int64_t)K * I * (I - 1) / 2;
 }
 
+// acc += |v| in the lanes of `mask` only (EXEC restored within the block).
+__device__ __forceinline__ void add_abs_masked(double &acc, double v, uint64_t mask) {
+    uint64_t saved;
+    __asm__("s_and_saveexec_b64 %1, %2\n\t"
+            "v_add_f64 %0, %0, |%3|\n\t"
+            "s_mov_b64 exec, %1"
+            : "+v"(acc), "=&s"(saved)
+            : "s"(mask), "v"(v)
+            : "scc");
+}
+
+// k + [lane in plus] - [lane in minus]: the masks enter as the carry-in and
+// borrow-in of one add and one subtract
+__device__ __forceinline__ int add_mask_bits(int k, uint64_t plus, uint64_t minus) {
+    int out;
+    uint64_t c0, c1;
+    __asm__("v_addc_co_u32_e64 %0, %1, 0, %3, %4\n\t"
+            "v_subbrev_co_u32_e64 %0, %2, 0, %0, %5"
+            : "=&v"(out), "=&s"(c0), "=&s"(c1)
+            : "v"(k), "s"(plus), "s"(minus));
+    return out;
+}
+
 template <int K, bool DIAG>
 __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                                               const int2 *__restrict__ rid,
@@ -47,6 +70,7 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                                               double angc, uint32_t &n_proper,
                                               uint32_t &n_touch, double &acc) {
     const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll 2
     for (int j = 0; j < kChunk; ++j) {
         const double cX = col[j].x, cY = col[j].y;
         const double cDX = col[j].dx, cDY = col[j].dy;
@@ -69,14 +93,15 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             const double v = angc + fabs(u);
             const double dot = fma(rDX[r], cDX, rDY[r] * cDY);
             const double s = (v * dot) * cr;
-            const bool pos = closed & (s > 0.0);
-            const bool neg = closed & (s < 0.0);
-            kr[r] += (int)pos - (int)neg;
-            colsum += (int)__popcll(__builtin_amdgcn_ballot_w64(pos)) -
-                      (int)__popcll(__builtin_amdgcn_ballot_w64(neg));
+            // lane masks of the crossing pairs and of their q = +1 / -1
+            const uint64_t cmask = __builtin_amdgcn_ballot_w64(closed);
+            const uint64_t pmask = __builtin_amdgcn_ballot_w64(s > 0.0) & cmask;
+            const uint64_t nmask = __builtin_amdgcn_ballot_w64(s < 0.0) & cmask;
+            colsum += (int)__popcll(pmask) - (int)__popcll(nmask);
+            kr[r] = add_mask_bits(kr[r], pmask, nmask);
             // forward terms of the same pair: the count and |ideal - a|
-            n_proper += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(closed));
-            acc = fma(closed ? 1.0 : 0.0, fabs(v), acc);
+            n_proper += (uint32_t)__popcll(cmask);
+            add_abs_masked(acc, v, cmask);
             any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
         }
         if (__builtin_expect(any_zero != 0, 0)) {
@@ -87,11 +112,11 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 bool pos = false, neg = false, ok = false;
-                if (zr[r]) {
+                // incident pairs (the common case here) are settled by their ids
+                if (zr[r] && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
                     double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
                     __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
-                    ok = dev::touching_pair(ex, ey, edx, edy, ec, rid[r * kBlock + tid], fx, fy,
-                                            fdx, fdy, fc, fid);
+                    ok = dev::touching_apart(ex, ey, edx, edy, ec, fx, fy, fdx, fdy, fc);
                     if (ok) {
                         const double cr = fma(-edy, fdx, edx * fdy);
                         const double v = angc + fabs(fabs(rTH[r] - fth) - kHalfPi);
