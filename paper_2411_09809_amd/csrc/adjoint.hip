@@ -49,14 +49,14 @@ __device__ __forceinline__ void add_abs_masked(double &acc, double v, uint64_t m
 
 // k + [lane in plus] - [lane in minus]: the masks enter as the carry-in and
 // borrow-in of one add and one subtract
+// (in place, so lanes outside EXEC keep their value)
 __device__ __forceinline__ int add_mask_bits(int k, uint64_t plus, uint64_t minus) {
-    int out;
     uint64_t c0, c1;
-    __asm__("v_addc_co_u32_e64 %0, %1, 0, %3, %4\n\t"
-            "v_subbrev_co_u32_e64 %0, %2, 0, %0, %5"
-            : "=&v"(out), "=&s"(c0), "=&s"(c1)
-            : "v"(k), "s"(plus), "s"(minus));
-    return out;
+    __asm__("v_addc_co_u32_e64 %0, %1, 0, %0, %3\n\t"
+            "v_subbrev_co_u32_e64 %0, %2, 0, %0, %4"
+            : "+v"(k), "=&s"(c0), "=&s"(c1)
+            : "s"(plus), "s"(minus));
+    return k;
 }
 
 template <int K, bool DIAG>
