@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void cross_finalize_kernel(
     }
 }
 
-constexpr SweepVariant kCross[kCrossVariants] = {{1, 8}, {2, 7}, {4, 4}, {4, 3}};
+constexpr SweepVariant kCross[kCrossVariants] = {{1, 8}, {2, 7}, {3, 6}, {4, 5}};
 
 template <int V>
 struct CrossV {
