@@ -192,7 +192,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
         if (!rows_loaded) {
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = rec[I * R + (int64_t)r * kBlock + tid];
+                const EdgeRec e = edge_row(rec, I * R + (int64_t)r * kBlock + tid,
+                                           lay.n_chunks * kChunk);
                 rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
                 rC[r] = e.c; rTH[r] = e.th;
                 rid[r * kBlock + tid] = make_int2(e.s, e.t);

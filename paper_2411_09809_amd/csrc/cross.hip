@@ -194,7 +194,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
         if (!rows_loaded) {
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = rec[lay.rec_off + I * R + (int64_t)r * kBlock + tid];
+                const EdgeRec e = edge_row(rec + lay.rec_off, I * R + (int64_t)r * kBlock + tid,
+                                           lay.n_chunks * kChunk);
                 rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
                 rC[r] = e.c; rTH[r] = e.th;
                 rid[r * kBlock + tid] = make_int2(e.s, e.t);
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
 template <int K, int WAVES, bool ANGLE>
 __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     const EdgeRec *__restrict__ rec, const int32_t *__restrict__ list,
-    const uint32_t *__restrict__ tile_off, int64_t n_tiles, double ideal,
+    const uint32_t *__restrict__ tile_off, int64_t n_tiles, int64_t n_rec, double ideal,
     CrossPartial *__restrict__ part) {
     __shared__ EdgeRec col[kChunk];
     __shared__ int2 rid[kBlock * K];
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
         if (!rows_loaded) {
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = rec[I * R + (int64_t)r * kBlock + tid];
+                const EdgeRec e = edge_row(rec, I * R + (int64_t)r * kBlock + tid, n_rec);
                 rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
                 rC[r] = e.c; rTH[r] = e.th;
                 rid[r * kBlock + tid] = make_int2(e.s, e.t);
@@ -428,12 +429,13 @@ int cross_list_grid(int v) {
 }
 
 hipError_t launch_cross_list(int v, const EdgeRec *rec, const int32_t *list,
-                             const uint32_t *tile_off, int64_t n_tiles, int grid, double ideal,
-                             CrossPartial *part, hipStream_t st) {
+                             const uint32_t *tile_off, int64_t n_tiles, int64_t n_rec, int grid,
+                             double ideal, CrossPartial *part, hipStream_t st) {
 #define RB_LCASE(V)                                                                       \
     case V:                                                                               \
         hipLaunchKernelGGL((cross_list_kernel<CrossV<V>::K, CrossV<V>::W, true>), dim3(grid), \
-                           dim3(kBlock), 0, st, rec, list, tile_off, n_tiles, ideal, part);  \
+                           dim3(kBlock), 0, st, rec, list, tile_off, n_tiles, n_rec, ideal,   \
+                           part);                                                         \
         break;
     switch (v) {
         RB_LCASE(0)

@@ -560,9 +560,10 @@ hipError_t launch_crossing_pruned(const float *x, const float *y, int64_t n_node
     RB_TRY(launch_prune_plan(x, y, n_nodes, src, dst, m, K, G, w, st));
     const int grid = cross_list_grid(variant);
     CrossPartial *part = (CrossPartial *)(w + G.partial);
+    const SweepLayout lay = sweep_layout(m, K, 0, 0);
     RB_TRY(launch_cross_list(variant, (const EdgeRec *)(w + G.rec), (const int32_t *)(w + G.list),
-                             (const uint32_t *)(w + G.tile_off), sweep_layout(m, K, 0, 0).n_row_tiles,
-                             grid, ideal, part, st));
+                             (const uint32_t *)(w + G.tile_off), lay.n_row_tiles,
+                             lay.n_chunks * kChunk, grid, ideal, part, st));
     return launch_cross_finalize(part, grid, ideal, out_count, nullptr, out_metric, out_dev_sum,
                                  st);
 }

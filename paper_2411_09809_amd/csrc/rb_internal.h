@@ -25,6 +25,16 @@ struct __align__(16) EdgeRec {
 };
 static_assert(sizeof(EdgeRec) == 64, "edge record is 64 bytes");
 
+// Record i of a layout segment of n records, or a padding edge at and past
+// its end: a row tile (256 * rows records) need not divide the segment.
+__device__ __forceinline__ EdgeRec edge_row(const EdgeRec *__restrict__ seg, int64_t i, int64_t n) {
+    if (i < n) return seg[i];
+    EdgeRec r;
+    r.x = 0.0; r.y = 0.0; r.dx = 0.0; r.dy = 0.0; r.c = -1.0; r.th = 0.0;
+    r.s = -1; r.t = -1; r.pad0 = 0; r.pad1 = 0;
+    return r;
+}
+
 // Per-node record for the occlusion sweep.  With n = x^2 + y^2 and T the
 // largest integer below d^2, the test |p_u - p_v|^2 <= T is rewritten as
 //     x_u x_v + y_u y_v + q_v >= h_u,   q = -n/2,  h = (n - T)/2,
@@ -231,11 +241,11 @@ hipError_t launch_radix_sort(uint32_t *keys, int32_t *vals, uint32_t *keys2, int
 hipError_t launch_grid_bounds(const float *x, const float *y, int64_t n, GridParams *gp,
                               int min_shift, int axis_bits, hipStream_t st);
 // Sweep over an explicit unit list: tile I meets chunks list[tile_off[I] ..
-// tile_off[I+1]) (cross.hip).
+// tile_off[I+1]); rows at and past n_rec are padding (cross.hip).
 int cross_list_grid(int variant);
 hipError_t launch_cross_list(int variant, const EdgeRec *rec, const int32_t *list,
-                             const uint32_t *tile_off, int64_t n_tiles, int grid, double ideal,
-                             CrossPartial *part, hipStream_t st);
+                             const uint32_t *tile_off, int64_t n_tiles, int64_t n_rec, int grid,
+                             double ideal, CrossPartial *part, hipStream_t st);
 // Plan of the pruned edge sweep: records in Hilbert order, chunk boxes and the
 // unit list of tiles of 256*K edges (grid.hip).
 hipError_t launch_prune_plan(const float *x, const float *y, int64_t n_nodes,

@@ -205,3 +205,37 @@ def test_autotune_single_layout(torch_mod):
     for k in ("node_occlusion", "edge_crossing", "min_angle_n_used"):
         assert after[k] == before[k]
     assert after["crossing_angle"] == pytest.approx(before["crossing_angle"], rel=1e-12)
+
+
+@pytest.mark.parametrize("E", [769, 4095, 4096, 8192])
+def test_every_variant_at_record_segment_ends(torch_mod, E, tmp_path):
+    """A row tile of 3 rows per thread (768 edges) does not divide the
+    4096-record segment of a layout: the last tile's rows past the segment
+    must be padding, in single-layout, pruned and batched sweeps alike."""
+    from paper_2411_09809_amd import _lib, metrics
+    from paper_2411_09809_amd.batch import Batch
+    lib = _lib.lib()
+    layouts = [gen.uniform_layout(max(200, E // 3), E, extent=2000, seed=E + k) for k in range(3)]
+    want = [oracle.crossing_angle(L.x, L.y, L.src, L.dst, IDEAL) for L in layouts]
+    D = metrics.DeviceLayout.from_host(layouts[0])
+    try:
+        for v in range(4):
+            say(f"[segment-end] E={E} variant {v}")
+            for kind in (1, 3):
+                _lib.check(lib.rb_tune_set(kind, 0, E, v), "rb_tune_set")
+            r = metrics.crossing_angle(D.x, D.y, D.src, D.dst, IDEAL)
+            p = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, IDEAL)
+            for got in (r, p):
+                assert got[1] == want[0][1]
+                assert got[0] == pytest.approx(want[0][0], rel=1e-9, abs=1e-12)
+            _lib.check(lib.rb_tune_set(1, 1, E, v), "rb_tune_set")
+            B = Batch(layouts)
+            B.evaluate()
+            R = B.results()
+            for i in range(3):
+                assert R["edge_crossing"][i] == want[i][1], (v, i)
+                assert R["crossing_angle"][i] == pytest.approx(want[i][0], rel=1e-9, abs=1e-12)
+    finally:
+        empty = tmp_path / "tune.txt"
+        empty.write_text("")
+        _lib.check(lib.rb_tune_load(str(empty).encode()), "rb_tune_load")   # built-in defaults
