@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void occl_finalize_kernel(const OcclPartial *_
     if (tid == 0) *out_count = s[0];
 }
 
-constexpr SweepVariant kOccl[kOcclVariants] = {{8, 4}, {16, 2}, {4, 6}};
+constexpr SweepVariant kOccl[kOcclVariants] = {{8, 4}, {2, 8}, {4, 6}};
 
 template <int V>
 struct OcclV {

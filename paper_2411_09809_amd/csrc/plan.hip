@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kClasses = 40;
 constexpr int kKinds = 4;   // 0 crossing, 1 crossing + angle, 2 occlusion, 3 pruned crossing
-constexpr int kDefault[kKinds] = {1, 1, 0, 0};
+constexpr int kDefault[kKinds] = {1, 1, 2, 0};
 
 struct Table {
     std::mutex mu;
