@@ -2,7 +2,9 @@
 
 One step = one evaluation of all five metrics (node occlusion, crossing
 count + crossing angle, minimum angle, edge length variation) of one layout
-already resident in GPU memory.  Default workload: preferential-attachment
+already resident in GPU memory: the edge-pair sweep on the current stream,
+the other metrics on a second stream that overlaps it (``--serial`` runs
+them one after another on one stream).  Default workload: preferential-attachment
 graph, |V| = 50,000, |E| = 149,994, 64 Gaussian clusters in [0,2^20)^2,
 diameter 64, ideal crossing angle 70 degrees.
 
@@ -396,6 +398,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward part")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the grid-pruned paths")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the five metrics of a step one after another on one stream")
     ap.add_argument("--no-optimise", action="store_true",
                     help="skip the end-to-end layout optimisation")
     ap.add_argument("--no-approx", action="store_true",
@@ -454,10 +458,13 @@ def main():
         variant[name] = {"rows_per_thread": rows.value, "waves_per_simd": waves.value}
 
     def step():
-        return [metrics.node_occlusion(D.x, D.y, D.diameter, async_=True),
-                metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True),
-                metrics.min_angle(D.x, D.y, D.src, D.dst, async_=True),
-                metrics.edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)]
+        if args.serial:
+            return [metrics.node_occlusion(D.x, D.y, D.diameter, async_=True),
+                    metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True),
+                    metrics.min_angle(D.x, D.y, D.src, D.dst, async_=True),
+                    metrics.edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)]
+        # the edge sweep on this stream, the other metrics on a second one
+        return list(metrics.evaluate_async(D))
 
     for _ in range(args.warmup):
         out = step()

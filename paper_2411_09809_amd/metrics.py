@@ -18,7 +18,14 @@ from ._lib import check, lib
 
 IDEAL_ANGLE = 70.0 * math.pi / 180.0
 
-_ws_cache: dict[int, torch.Tensor] = {}
+# Workspaces are cached per (device, stream): calls enqueued on different
+# streams may run at the same time and must not share scratch memory.
+_ws_cache: dict[tuple, torch.Tensor] = {}
+
+
+def _ws_key(dev: torch.device) -> tuple:
+    index = dev.index if dev.index is not None else torch.cuda.current_device()
+    return index, torch.cuda.current_stream(torch.device("cuda", index)).cuda_stream
 
 
 def _ptr(t):
@@ -35,7 +42,7 @@ def workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
     if need == 0:
         raise ValueError(f"layout size out of range: {n_nodes} nodes, {n_edges} edges")
     dev = torch.device(device)
-    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    key = _ws_key(dev)
     ws = _ws_cache.get(key)
     if ws is None or ws.numel() < need:
         _ws_cache.pop(key, None)
@@ -44,7 +51,7 @@ def workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
     return ws
 
 
-_grid_ws_cache: dict[int, torch.Tensor] = {}
+_grid_ws_cache: dict[tuple, torch.Tensor] = {}
 
 
 def grid_workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
@@ -53,7 +60,7 @@ def grid_workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
     if need == 0:
         raise ValueError(f"layout size out of range: {n_nodes} nodes, {n_edges} edges")
     dev = torch.device(device)
-    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    key = _ws_key(dev)
     ws = _grid_ws_cache.get(key)
     if ws is None or ws.numel() < need:
         _grid_ws_cache.pop(key, None)
@@ -305,12 +312,44 @@ class DeviceLayout:
                    t(L.dst, torch.int32), float(L.diameter), float(L.ideal_angle))
 
 
+_side_streams: dict[int, torch.cuda.Stream] = {}
+
+
+def _side_stream(dev: torch.device) -> torch.cuda.Stream:
+    index = dev.index if dev.index is not None else torch.cuda.current_device()
+    st = _side_streams.get(index)
+    if st is None:                      # default priority, like every stream here
+        st = _side_streams[index] = torch.cuda.Stream(device=torch.device("cuda", index))
+    return st
+
+
+def evaluate_async(D: DeviceLayout):
+    """All five metrics of one device layout, enqueued without a host wait:
+    the edge-pair sweep on the current stream, and the node sweep, minimum
+    angle and edge lengths on a second stream (its own workspace), so they
+    run in the resources the edge sweep leaves idle.  The current stream
+    waits for both.  Returns the device tensors of node_occlusion,
+    crossing_angle, min_angle and edge_length_variation (``async_=True``)."""
+    dev = D.x.device
+    main = torch.cuda.current_stream(dev)
+    side = _side_stream(dev)
+    side.wait_stream(main)
+    for t in (D.x, D.y, D.src, D.dst):  # read on the side stream too
+        t.record_stream(side)
+    with torch.cuda.stream(side):
+        occ = node_occlusion(D.x, D.y, D.diameter, async_=True)
+        ma = min_angle(D.x, D.y, D.src, D.dst, async_=True)
+        ml = edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)
+    ang = crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True)
+    main.wait_stream(side)
+    for t in (occ, ma, ml):             # made on the side stream, read on this one
+        t.record_stream(main)
+    return occ, ang, ma, ml
+
+
 def evaluate(D: DeviceLayout) -> dict:
     """All five metrics of one device layout (one pass of the hot path)."""
-    occ = node_occlusion(D.x, D.y, D.diameter, async_=True)
-    ang = crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True)
-    ma = min_angle(D.x, D.y, D.src, D.dst, async_=True)
-    ml = edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)
+    occ, ang, ma, ml = evaluate_async(D)
     occ, ang, ma, ml = occ.cpu(), ang.cpu(), ma.cpu(), ml.cpu()
     return dict(node_occlusion=int(occ[0]), crossing_angle=float(ang[0]),
                 edge_crossing=int(ang.view(torch.int64)[1]), crossing_dev_sum=float(ang[2]),

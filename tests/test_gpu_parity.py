@@ -241,3 +241,46 @@ def test_full_size_workloads(rb, name):
     L = build()
     assert L.digest() == want["digest"], "generator output changed; rerun make_golden.py"
     compare_all(rb, L, want)
+
+
+def test_overlapped_evaluate_matches_oracle(rb):
+    """evaluate() runs the edge sweep on the current stream and the other
+    metrics on a second stream with its own workspace; repeated, and mixed
+    with single calls on the current stream, it gives the oracle's values."""
+    import torch
+    L = gen.uniform_layout(3000, 8000, extent=1500, diameter=9.0, seed=12)
+    D = dev(L)
+    want = oracle.all_metrics(L)
+    for rep in range(3):
+        say(f"[evaluate] repeat {rep}")
+        got = rb.evaluate(D)
+        assert got["node_occlusion"] == want["node_occlusion"]
+        assert got["edge_crossing"] == want["edge_crossing"]
+        assert got["min_angle_n_used"] == want["min_angle_n_used"]
+        for k in ("crossing_angle", "min_angle", "edge_length_variation"):
+            assert rel_ok(got[k], want[k]), (k, got[k], want[k])
+        assert rb.node_occlusion(D.x, D.y, L.diameter) == want["node_occlusion"]
+    torch.cuda.synchronize()
+
+
+def test_two_streams_do_not_share_a_workspace(rb):
+    """Calls enqueued on two streams at once use separate workspaces."""
+    import torch
+    A = gen.uniform_layout(2000, 6000, extent=2048, seed=21)
+    B = gen.uniform_layout(2500, 6000, extent=1024, seed=22)
+    DA, DB = dev(A), dev(B)
+    wa = oracle.crossing_angle(A.x, A.y, A.src, A.dst, IDEAL)
+    wb = oracle.crossing_angle(B.x, B.y, B.src, B.dst, IDEAL)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for rep in range(3):
+        with torch.cuda.stream(s1):
+            oa = rb.crossing_angle(DA.x, DA.y, DA.src, DA.dst, IDEAL, async_=True)
+        with torch.cuda.stream(s2):
+            ob = rb.crossing_angle(DB.x, DB.y, DB.src, DB.dst, IDEAL, async_=True)
+        outs.append((oa, ob))
+    torch.cuda.synchronize()
+    for oa, ob in outs:
+        ga, gb = oa.cpu(), ob.cpu()
+        assert int(ga.view(torch.int64)[1]) == wa[1] and int(gb.view(torch.int64)[1]) == wb[1]
+        assert rel_ok(float(ga[0]), wa[0]) and rel_ok(float(gb[0]), wb[0])
