@@ -33,6 +33,17 @@ struct rb_batch {
            o_ang = 0, o_dv = 0, o_big = 0, o_sc = 0, total = 0;
     int64_t n_nodes = 0, n_edges = 0;
     const void *uploaded = nullptr;               // workspace holding the current tables
+    // second stream (default priority) for the metrics that overlap the edge
+    // sweep, and the fork / join events; made on first use, on the device of
+    // that call
+    mutable hipStream_t side = nullptr;
+    mutable hipEvent_t fork = nullptr, join = nullptr;
+    mutable int side_device = -1;
+    ~rb_batch() {
+        if (join) (void)hipEventDestroy(join);
+        if (fork) (void)hipEventDestroy(fork);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 struct rb_graph {
@@ -320,12 +331,38 @@ hipError_t enqueue_prep(const rb_batch *b, char *w, const BatchIO &io, hipStream
     return hipGetLastError();
 }
 
-hipError_t enqueue_all(const rb_batch *b, char *w, const BatchIO &io, hipStream_t st) {
+hipError_t side_stream(const rb_batch *b, hipStream_t *out) {
+    int dev = 0;
+    RB_TRY(hipGetDevice(&dev));
+    if (b->side && b->side_device != dev) return hipErrorInvalidDevice;
+    if (!b->side) {
+        RB_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        RB_TRY(hipEventCreateWithFlags(&b->join, hipEventDisableTiming));
+        RB_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+        b->side_device = dev;
+    }
+    *out = b->side;
+    return hipSuccess;
+}
+
+// With `overlap`, the edge sweep runs on `main` and the node sweep, edge
+// lengths and minimum angle on the batch's second stream, forked from
+// `main` after the record prep and joined back at the end; their workspace
+// regions are disjoint.  Without it (graph capture, where a replay of the
+// forked graph measured slower than the one-stream graph) everything runs
+// on `main` in that order.
+hipError_t enqueue_all(const rb_batch *b, char *w, const BatchIO &io, hipStream_t main,
+                       bool overlap) {
     const int64_t *noff = (const int64_t *)(w + b->o_noff);
     const int64_t *eoff = (const int64_t *)(w + b->o_eoff);
     const bool need_cross = io.cross || io.angle;
-    RB_TRY(enqueue_prep(b, w, io, st));
-    if (need_cross) RB_TRY(enqueue_cross(b, w, io, true, st));
+    RB_TRY(enqueue_prep(b, w, io, main));
+    hipStream_t st = main;
+    if (overlap) {
+        RB_TRY(side_stream(b, &st));
+        RB_TRY(hipEventRecord(b->fork, main));
+        RB_TRY(hipStreamWaitEvent(st, b->fork, 0));
+    }
     if (io.occl) RB_TRY(enqueue_occl(b, w, io, true, st));
     if (io.elv) {
         hipLaunchKernelGGL(batch_elv_kernel, dim3((unsigned)b->B), dim3(256), 0, st, io.x, io.y,
@@ -361,7 +398,10 @@ hipError_t enqueue_all(const rb_batch *b, char *w, const BatchIO &io, hipStream_
                            io.min_angle);
         RB_TRY(hipGetLastError());
     }
-    return hipSuccess;
+    if (need_cross) RB_TRY(enqueue_cross(b, w, io, true, main));
+    if (!overlap) return hipSuccess;
+    RB_TRY(hipEventRecord(b->join, st));
+    return hipStreamWaitEvent(main, b->join, 0);
 }
 
 void carve(rb_batch *b) {
@@ -518,7 +558,7 @@ rb_status rb_batch_evaluate(const rb_batch *b, const float *x, const float *y, c
                (unsigned long long *)out_crossings, out_crossing_angle, out_min_angle, out_elv};
     rb_status s = check_io(b, io, ws, ws_bytes);
     if (s) return s;
-    hipError_t e = enqueue_all(b, (char *)ws, io, (hipStream_t)stream);
+    hipError_t e = enqueue_all(b, (char *)ws, io, (hipStream_t)stream, true);
     if (e != hipSuccess) return (rb_status)hip_error(e, "rb_batch_evaluate");
     return RB_OK;
 }
@@ -613,7 +653,7 @@ rb_status rb_batch_graph_create(const rb_batch *b, const float *x, const float *
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e2 = enqueue_all(b, (char *)ws, io, cs);
+        hipError_t e2 = enqueue_all(b, (char *)ws, io, cs, false);
         e = hipStreamEndCapture(cs, &graph);
         if (e2 != hipSuccess) e = e2;
     }
