@@ -482,6 +482,15 @@ def main():
     ms, n = C.c_double(), C.c_int64()
     _lib.check(R.rb_timing_read(0, C.byref(ms), C.byref(n)), "rb_timing_read")
     cross_ms = ms.value / max(n.value, 1)
+    R.rb_timing_reset()
+
+    # the node-pair sweep on its own: inside a step it shares the GPU with the
+    # edge sweep, so its launch duration there is not its cost
+    R.rb_timing_enable(1)
+    for _ in range(args.steps):
+        metrics.node_occlusion(D.x, D.y, D.diameter, async_=True)
+    torch.cuda.synchronize()
+    R.rb_timing_enable(0)
     _lib.check(R.rb_timing_read(1, C.byref(ms), C.byref(n)), "rb_timing_read")
     occl_ms = ms.value / max(n.value, 1)
     R.rb_timing_reset()
