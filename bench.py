@@ -167,6 +167,9 @@ def bench_adjoint(torch, reps: int, gd_steps: int):
             fn()
         torch.cuda.synchronize()
         out[name] = (time.perf_counter() - t0) * 1e3 / reps
+    for pruned in (False, True):        # first-use costs (autograd, events) stay out
+        optim.descend(D.x, D.y, D.src, D.dst, steps=2, step_size=2.0, pruned=pruned)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, _, hist = optim.descend(D.x, D.y, D.src, D.dst, steps=gd_steps, step_size=2.0)
     torch.cuda.synchronize()

@@ -10,8 +10,6 @@ every step.
 """
 from __future__ import annotations
 
-import time
-
 import torch
 
 from ._lib import check, lib
@@ -75,12 +73,15 @@ def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
     units along -g / max|g| each step; loss, gradient and the exact crossing
     count are evaluated on the master rounded to integers and clamped to
     [0, extent).  Returns (x, y, history) with history = list of
-    (loss, crossings, seconds) per step."""
+    (loss, crossings, seconds) per step, seconds being the step's GPU time.
+    The steps are enqueued without waiting for the GPU unless ``log`` is
+    given (it is called with each step's entry as soon as it is known)."""
     mx = x.detach().clone().to(torch.float32)
     my = y.detach().clone().to(torch.float32)
-    hist = []
+    marks = [torch.cuda.Event(enable_timing=True)]
+    marks[0].record()
+    vals, hist = [], []
     for k in range(steps):
-        t0 = time.perf_counter()
         xi = torch.clamp(torch.round(mx), 0, extent - 1).requires_grad_(True)
         yi = torch.clamp(torch.round(my), 0, extent - 1).requires_grad_(True)
         loss, cnt = CrossingAngleLengthLoss.apply(xi, yi, src, dst, ideal_angle, w_angle,
@@ -90,8 +91,17 @@ def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
             scale = torch.maximum(xi.grad.abs().max(), yi.grad.abs().max()).clamp_min(1e-300)
             mx -= step_size * xi.grad / scale
             my -= step_size * yi.grad / scale
-        hist.append((float(loss.detach()), int(cnt), time.perf_counter() - t0))
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        marks.append(ev)
+        vals.append((loss.detach(), cnt))
         if log:
+            ev.synchronize()
+            hist.append((float(loss), int(cnt), marks[-2].elapsed_time(ev) * 1e-3))
             log(k, hist[-1])
+    if not log:
+        marks[-1].synchronize()
+        hist = [(float(l), int(c), marks[i].elapsed_time(marks[i + 1]) * 1e-3)
+                for i, (l, c) in enumerate(vals)]
     return (torch.clamp(torch.round(mx), 0, extent - 1), torch.clamp(torch.round(my), 0, extent - 1),
             hist)
