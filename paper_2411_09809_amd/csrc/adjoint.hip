@@ -36,17 +36,6 @@ __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
     return I * nC - (int64_t)K * I * (I - 1) / 2;
 }
 
-// acc += |v| in the lanes of `mask` only (EXEC restored within the block).
-__device__ __forceinline__ void add_abs_masked(double &acc, double v, uint64_t mask) {
-    uint64_t saved;
-    __asm__("s_and_saveexec_b64 %1, %2\n\t"
-            "v_add_f64 %0, %0, |%3|\n\t"
-            "s_mov_b64 exec, %1"
-            : "+v"(acc), "=&s"(saved)
-            : "s"(mask), "v"(v)
-            : "scc");
-}
-
 // k + [lane in plus] - [lane in minus]: the masks enter as the carry-in and
 // borrow-in of one add and one subtract
 // (in place, so lanes outside EXEC keep their value)
@@ -101,7 +90,7 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             kr[r] = add_mask_bits(kr[r], pmask, nmask);
             // forward terms of the same pair: the count and |ideal - a|
             n_proper += (uint32_t)__popcll(cmask);
-            add_abs_masked(acc, v, cmask);
+            dev::add_abs_masked(acc, v, cmask);
             any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
         }
         if (__builtin_expect(any_zero != 0, 0)) {

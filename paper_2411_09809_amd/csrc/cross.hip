@@ -39,20 +39,6 @@ __device__ __forceinline__ uint32_t popc_ballot(bool p) {
     return (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
 }
 
-// acc += |v| in the lanes of `mask` only.  The lane mask of the crossing
-// compare selects the lanes through EXEC, which takes two scalar
-// instructions instead of a vector select of an indicator; EXEC is restored
-// within the block.
-__device__ __forceinline__ void add_abs_masked(double &acc, double v, uint64_t mask) {
-    uint64_t saved;
-    __asm__("s_and_saveexec_b64 %1, %2\n\t"
-            "v_add_f64 %0, %0, |%3|\n\t"
-            "s_mov_b64 exec, %1"
-            : "+v"(acc), "=&s"(saved)
-            : "s"(mask), "v"(v)
-            : "scc");
-}
-
 __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
     return I * nC - (int64_t)K * I * (I - 1) / 2;
 }
@@ -91,7 +77,7 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
             n_proper += (uint32_t)__popcll(pmask);
             if (ANGLE) {
                 const double u = fabs(rTH[r] - cTH) - kHalfPi;
-                add_abs_masked(acc, angc + fabs(u), pmask);
+                dev::add_abs_masked(acc, angc + fabs(u), pmask);
             }
             any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
         }

@@ -48,6 +48,19 @@ __device__ __noinline__ inline bool boxes_meet(double rx, double ry, double rdx,
     return (fmax(ax0, bx0) <= fmin(ax1, bx1)) && (fmax(ay0, by0) <= fmin(ay1, by1));
 }
 
+// acc += |v| in the lanes of `mask` only.  A compare's lane mask selects the
+// lanes through EXEC, which takes two scalar instructions instead of a vector
+// select of an indicator; EXEC is restored within the block.
+__device__ __forceinline__ void add_abs_masked(double &acc, double v, uint64_t mask) {
+    uint64_t saved;
+    __asm__("s_and_saveexec_b64 %1, %2\n\t"
+            "v_add_f64 %0, %0, |%3|\n\t"
+            "s_mov_b64 exec, %1"
+            : "+v"(acc), "=&s"(saved)
+            : "s"(mask), "v"(v)
+            : "scc");
+}
+
 // Pairs whose larger orientation product is zero.  Edges that share an end
 // id are never crossings (incident edges always have both products zero).
 __device__ __forceinline__ bool incident_ids(int2 a, int2 b) {
