@@ -23,9 +23,24 @@ IDEAL_ANGLE = 70.0 * math.pi / 180.0
 _ws_cache: dict[tuple, torch.Tensor] = {}
 
 
+_WS_KEEP = 8       # cached workspaces per kind; the oldest goes first
+
+
 def _ws_key(dev: torch.device) -> tuple:
     index = dev.index if dev.index is not None else torch.cuda.current_device()
     return index, torch.cuda.current_stream(torch.device("cuda", index)).cuda_stream
+
+
+def _ws_get(cache: dict, key: tuple, need: int, dev: torch.device) -> torch.Tensor:
+    # a workspace belongs to the memory pool of the stream it was made on, so
+    # dropping one never hands its memory to work queued on another stream
+    ws = cache.pop(key, None)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    cache[key] = ws                     # most recently used last
+    while len(cache) > _WS_KEEP:
+        cache.pop(next(iter(cache)))
+    return ws
 
 
 def _ptr(t):
@@ -42,13 +57,7 @@ def workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
     if need == 0:
         raise ValueError(f"layout size out of range: {n_nodes} nodes, {n_edges} edges")
     dev = torch.device(device)
-    key = _ws_key(dev)
-    ws = _ws_cache.get(key)
-    if ws is None or ws.numel() < need:
-        _ws_cache.pop(key, None)
-        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
-        _ws_cache[key] = ws
-    return ws
+    return _ws_get(_ws_cache, _ws_key(dev), need, dev)
 
 
 _grid_ws_cache: dict[tuple, torch.Tensor] = {}
@@ -60,13 +69,7 @@ def grid_workspace(n_nodes: int, n_edges: int, device) -> torch.Tensor:
     if need == 0:
         raise ValueError(f"layout size out of range: {n_nodes} nodes, {n_edges} edges")
     dev = torch.device(device)
-    key = _ws_key(dev)
-    ws = _grid_ws_cache.get(key)
-    if ws is None or ws.numel() < need:
-        _grid_ws_cache.pop(key, None)
-        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
-        _grid_ws_cache[key] = ws
-    return ws
+    return _ws_get(_grid_ws_cache, _ws_key(dev), need, dev)
 
 
 def _ws_args(ws: torch.Tensor):
