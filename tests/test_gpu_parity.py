@@ -241,6 +241,13 @@ def test_full_size_workloads(rb, name):
     L = build()
     assert L.digest() == want["digest"], "generator output changed; rerun make_golden.py"
     compare_all(rb, L, want)
+    # the benchmark's launch configuration: the edge sweep and the other
+    # metrics overlapped on two streams
+    got = rb.evaluate(dev(L))
+    for k in ("node_occlusion", "edge_crossing", "min_angle_n_used"):
+        assert got[k] == want[k], (k, got[k], want[k])
+    for k in ("crossing_angle", "min_angle", "edge_length_variation"):
+        assert rel_ok(got[k], want[k]), (k, got[k], want[k])
 
 
 def test_overlapped_evaluate_matches_oracle(rb):
