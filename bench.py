@@ -414,7 +414,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
 
