@@ -89,3 +89,46 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(_lib.RBError):
         _lib.lib()
+
+
+def test_argument_errors_of_the_other_entry_points_need_no_gpu(L):
+    fake = 0x1000                     # never dereferenced: checks fail first
+    ws = fake * 256
+    need = L.rb_workspace_size(10, 5)
+    gneed = L.rb_grid_workspace_size(10, 5)
+    ideal = 1.2217304763960306
+    nan = float("nan")
+    # loss and gradient: weights must be finite, the ideal angle in (0, pi/2]
+    for fn in (L.rb_loss_grad, L.rb_loss_grad_pruned):
+        ws_bytes = need if fn is L.rb_loss_grad else gneed
+        assert fn(fake, fake, 10, fake, fake, 5, ideal, 1.0, 1.0, nan, fake, fake, fake, None,
+                  ws, ws_bytes, None) == _lib.RB_EINVAL
+        assert "finite" in _err(L)
+        assert fn(fake, fake, 10, fake, fake, 5, 0.0, 1.0, 1.0, 0.0, fake, fake, fake, None,
+                  ws, ws_bytes, None) == _lib.RB_EINVAL
+        assert fn(fake, fake, 10, fake, fake, 5, ideal, 1.0, 1.0, 0.0, None, fake, fake, None,
+                  ws, ws_bytes, None) == _lib.RB_EINVAL
+    # the pruned edge sweep indexes its unit list in 32 bits
+    big = (1 << 24) + 1
+    assert L.rb_loss_grad_pruned(fake, fake, 10, fake, fake, big, ideal, 1.0, 1.0, 0.0, fake,
+                                 fake, fake, None, ws, gneed, None) == _lib.RB_EINVAL
+    assert "2^24" in _err(L)
+    # shards: 0 <= shard < n_shards
+    lo, hi = C.c_int64(), C.c_int64()
+    assert L.rb_crossing_angle_shard(fake, fake, 10, fake, fake, 5, ideal, 3, 3, fake, None,
+                                     C.byref(lo), C.byref(hi), ws, need,
+                                     None) == _lib.RB_EINVAL
+    assert "shard" in _err(L)
+    assert L.rb_node_occlusion_shard(fake, fake, 10, 8.0, -1, 2, fake, C.byref(lo), C.byref(hi),
+                                     ws, need, None) == _lib.RB_EINVAL
+    # grid paths: a workspace shorter than rb_grid_workspace_size
+    assert L.rb_node_occlusion_grid(fake, fake, 10, 8.0, fake, ws, gneed - 256,
+                                    None) == _lib.RB_EWORKSPACE
+    assert L.rb_crossing_angle_pruned(fake, fake, 10, fake, fake, 5, ideal, fake, None, None, ws,
+                                      gneed - 256, None) == _lib.RB_EWORKSPACE
+    # strips: integer width in [1, 2^22]
+    pieces = C.c_uint64(7)
+    assert L.rb_enhanced_crossing(fake, fake, 10, fake, fake, 5, 0, 0, ideal, fake, None, None,
+                                  C.byref(pieces), ws, L.rb_enhanced_workspace_size(5, 0),
+                                  None) == _lib.RB_EINVAL
+    assert "width" in _err(L)
