@@ -11,7 +11,9 @@ diameter 64, ideal crossing angle 70 degrees.
 Prints one JSON line.  ``value`` is edge-pair tests per second of the whole
 step: C(|E|,2) per step / step time.  ``roofline`` reports the edge-pair
 sweep kernel (the dominant kernel) against the VALU issue peak; its duration
-comes from HIP events recorded by librb on the launch stream.
+comes from HIP events recorded by librb on the launch stream.  Beside that
+nominal peak it gives the attainable one, the FP64 FMA rate that independent
+FMA chains reach on the device (``attainable``, ``frac_of_attainable``).
 ``cpu_baseline`` times the CPU oracle on a bounded sample of the same layout.
 Further sections: ``batched`` (512 layouts, one hipGraph replay against 512
 plain launch sets), ``fwd_bwd`` (loss and gradient against the forward
@@ -80,6 +82,21 @@ def cpu_baseline(L, budget_pairs: float):
             "kind": "oracle",
             "sample": f"crossing + crossing-angle test over the first {S} edges "
                       f"({math.comb(S, 2):.3e} pairs) of the same layout, {dt:.1f} s"}
+
+
+def valu_probe(torch, iters=4096, repeats=20):
+    """FP64 FMA lane-operations per second that independent FMA chains reach
+    on this device: the clock the sweeps run at under FP64 load times the
+    lanes, an attainable ceiling beside the nominal one."""
+    import ctypes as C
+    from paper_2411_09809_amd import _lib
+    R = _lib.lib()
+    sink = torch.zeros(1, dtype=torch.float64, device="cuda")
+    rate = C.c_double()
+    _lib.check(R.rb_valu_probe(iters, repeats, C.byref(rate), C.c_void_p(sink.data_ptr()),
+                               C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "rb_valu_probe")
+    return rate.value
 
 
 def bench_batch(torch, steps: int):
@@ -510,6 +527,8 @@ def main():
     grid_ms = ms.value / max(n.value, 1)
     R.rb_timing_reset()
 
+    attainable = valu_probe(torch)
+
     vals = [o.cpu() for o in out]
     if grid_occ != int(vals[0][0]):
         raise RuntimeError(f"grid occlusion {grid_occ} != brute force {int(vals[0][0])}")
@@ -539,6 +558,8 @@ def main():
                                                  variant["cross_angle"]["waves_per_simd"]),
                      "kernel": "cross_sweep_kernel (crossing + angle)",
                      "ops_per_pair": OPS_PER_EDGE_PAIR, "kernel_ms": cross_ms,
+                     "attainable": attainable / 1e12,
+                     "frac_of_attainable": achieved / attainable,
                      "variant": variant["cross_angle"]},
         "kernels": {"edge_pair_sweep_ms": cross_ms,
                     "edge_pair_sweep_pairs_per_s": pairs / (cross_ms * 1e-3),

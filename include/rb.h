@@ -329,6 +329,15 @@ rb_status rb_tune_load(const char *path);
  * kind: 0 = edge-pair sweep (crossing / crossing angle), 1 = node-pair
  * sweep (occlusion), 2 = grid occlusion (all its kernels), 3 = pruned
  * edge-pair path (all its kernels).  rb_timing_reset clears the sums.     */
+/* Attainable FP64 FMA rate of the current device, the practical ceiling the
+ * sweeps are measured against: one untimed and `repeats` timed launches of
+ * a kernel of independent FMA chains (`iters` FMAs per chain) on `stream`,
+ * timed with HIP events; the call synchronizes.  *out_lane_ops_per_s (host)
+ * receives FMA lane-operations per second; sink is a device double the
+ * kernel never writes in practice (it keeps the chains from being removed).
+ * iters in [1, 2^24], repeats in [1, 1000].                               */
+rb_status rb_valu_probe(int iters, int repeats, double *out_lane_ops_per_s, double *sink,
+                        void *stream);
 rb_status rb_timing_enable(int enable);
 rb_status rb_timing_reset(void);
 rb_status rb_timing_read(int kernel, double *total_ms, int64_t *launches);

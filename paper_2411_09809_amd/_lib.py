@@ -58,6 +58,7 @@ _SIGS = {
                       _vp, _sz, _vp], C.c_int),
     "rb_autotune": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _f64, C.c_int, C.POINTER(C.c_double),
                      _vp, _sz, _vp], C.c_int),
+    "rb_valu_probe": ([C.c_int, C.c_int, C.POINTER(C.c_double), _vp, _vp], C.c_int),
     "rb_tune_set": ([C.c_int, C.c_int, _i64, C.c_int], C.c_int),
     "rb_tune_query": ([C.c_int, C.c_int, _i64, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "rb_tune_save": ([C.c_char_p], C.c_int),

@@ -760,6 +760,31 @@ rb_status rb_timing_reset(void) {
     return RB_OK;
 }
 
+rb_status rb_valu_probe(int iters, int repeats, double *out_lane_ops_per_s, double *sink,
+                        void *stream) {
+    g_err.clear();
+    if (iters < 1 || iters > (1 << 24) || repeats < 1 || repeats > 1000)
+        return fail(RB_EINVAL, "iters must be in [1, 2^24] and repeats in [1, 1000]");
+    if (!out_lane_ops_per_s || !sink) return fail(RB_EINVAL, "out_lane_ops_per_s or sink is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double ops = 0.0;
+    hipError_t e = launch_valu_probe(iters, sink, &ops, st);          // untimed first launch
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < repeats && e == hipSuccess; ++r) e = launch_valu_probe(iters, sink, nullptr, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "rb_valu_probe");
+    *out_lane_ops_per_s = ms > 0.f ? ops * repeats / (ms * 1e-3) : 0.0;
+    return RB_OK;
+}
+
 rb_status rb_timing_read(int kernel, double *total_ms, int64_t *launches) {
     g_err.clear();
     if (kernel < 0 || kernel >= kTimedKinds)

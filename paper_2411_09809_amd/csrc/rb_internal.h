@@ -288,6 +288,10 @@ hipError_t launch_validate(const float *x, const float *y, int64_t n_nodes,
 
 int device_cu_count();
 
+// FP64 FMA issue-rate probe (probe.hip): one launch of independent FMA
+// chains; *out_lane_ops receives the FMA lane-operations it performs.
+hipError_t launch_valu_probe(int iters, double *sink, double *out_lane_ops, hipStream_t st);
+
 // Error text of the calling host thread (api.hip); set_error and hip_error
 // return the status they were given (RB_EHIP for hip_error).
 int set_error(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
