@@ -251,8 +251,8 @@ rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes,
  * src, dst the edges likewise, with end ids LOCAL to their layout
  * (0 <= id < nodes of that layout).  node_off / edge_off (host int64,
  * n_layouts + 1 entries, starting at 0, nondecreasing) give each layout's
- * range.  Each all-pairs sweep runs as ONE persistent launch over the unit
- * lists of all layouts; per-layout results are combined in a fixed order.
+ * range.  Each all-pairs sweep runs as ONE launch over the unit lists of
+ * all layouts; per-layout results are combined in a fixed order.
  *
  * rb_batch_create builds the host plan (diameters: host double[n_layouts]).
  * rb_batch_upload writes the plan's tables into the workspace (at least

@@ -145,6 +145,14 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     const int64_t u_end = block_first_unit(U, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
+    if (LIST && u_begin == u_end) {            // more blocks than kept units
+        if (tid == 0) {
+            CrossPartial P;
+            P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
+            part[b] = P;
+        }
+        return;
+    }
     int64_t lo = 0, hi = (LIST ? n_tiles : lay.n_row_tiles) - 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
@@ -300,7 +308,6 @@ int grid_for(int64_t n) {
 }
 
 constexpr int kAdjRows = 2, kAdjWaves = 4;
-int g_adj_grid = 0;
 int g_adj_list_grid = 0;
 
 #define RB_TRY(expr)                          \
@@ -338,16 +345,7 @@ hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, con
     RB_TRY(launch_fill_u32((uint32_t *)kacc, L.n_edge_pad, 0u, st));
     const SweepLayout lay = sweep_layout(n_edges, kAdjRows, 0, 0);
     const int64_t U = sweep_units(n_edges, kAdjRows);
-    if (g_adj_grid == 0) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, adjoint_sweep_kernel<kAdjRows, kAdjWaves, false>, kBlock, 0) !=
-                hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        g_adj_grid = std::min(per_cu * device_cu_count(), kMaxPartials);
-    }
-    const int grid = (int)std::min<int64_t>(U, g_adj_grid);
+    const int grid = (int)std::min<int64_t>(U, kMaxPartials);
     CrossPartial *part = (CrossPartial *)(w + L.partial);
     hipLaunchKernelGGL((adjoint_sweep_kernel<kAdjRows, kAdjWaves, false>), dim3(grid),
                        dim3(kBlock), 0, st, rec, lay, U, nullptr, nullptr, (int64_t)0, ideal, kacc,
@@ -402,7 +400,7 @@ hipError_t launch_loss_grad_pruned(const float *x, const float *y, int64_t n_nod
                 hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        g_adj_list_grid = std::min(per_cu * device_cu_count(), kMaxPartials);
+        g_adj_list_grid = std::min(per_cu * device_cu_count() * kListBlocksPerSlot, kMaxPartials);
     }
     const int grid = g_adj_list_grid;
     const SweepLayout lay = sweep_layout(n_edges, kAdjRows, 0, 0);

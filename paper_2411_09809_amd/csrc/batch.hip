@@ -1,12 +1,13 @@
 // Batched evaluation: the five metrics of many layouts of uneven size with
-// one persistent launch per all-pairs sweep, capturable into a hipGraph.
+// one launch per all-pairs sweep, capturable into a hipGraph.
 //
 // The layouts are concatenated (node and edge arrays with offsets; edge ends
 // stay local to their layout).  Every layout gets a record segment padded to
 // kRecPad, and the units of all layouts' pair triangles form one list
-// (SweepLayout table in the workspace), which a single persistent grid
-// splits into equal contiguous ranges.  Per-layout results are combined
-// from per-(block, layout) partial slots in a fixed order.
+// (SweepLayout table in the workspace), which one launch splits into equal
+// contiguous ranges, one per block.  Per-layout results are combined from
+// per-(block, layout) partial slots in a fixed order, one finalize block per
+// layout.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -24,7 +25,7 @@ struct rb_batch {
     std::vector<int64_t> erec_off, nrec_off;      // B + 1, record segments
     std::vector<double> T;                        // occlusion threshold per layout
     int cross_var = 1, occl_var = 0;
-    // set by upload: unit counts and persistent grid sizes of the two sweeps
+    // set by upload: unit counts and grid sizes of the two sweeps
     int64_t cross_units = 0, occl_units = 0;
     int cross_grid_n = 1, occl_grid_n = 1;
     // workspace carve (byte offsets, 256-aligned)
@@ -123,35 +124,60 @@ __global__ __launch_bounds__(256) void batch_node_prep_kernel(
     }
 }
 
+// One block per layout: the slots of the blocks whose ranges meet the
+// layout's units, summed strided per thread and then as a tree (a fixed order).
 __global__ __launch_bounds__(256) void batch_cross_finalize_kernel(
-    const CrossPartial *__restrict__ part, const SweepLayout *__restrict__ tab, int64_t B,
-    int64_t U, int64_t G, double ideal, unsigned long long *out_count, double *out_metric) {
-    const int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (L >= B) return;
-    const int64_t b0 = block_of_unit(U, G, tab[L].unit_off);
-    const int64_t b1 = block_of_unit(U, G, tab[L + 1].unit_off - 1);
-    unsigned long long p = 0, t = 0;
+    const CrossPartial *__restrict__ part, const SweepLayout *__restrict__ tab, int64_t U,
+    int64_t G, double ideal, unsigned long long *out_count, double *out_metric) {
+    __shared__ unsigned long long sc[256];
+    __shared__ double sd[256];
+    const int64_t L = blockIdx.x;
+    const int tid = threadIdx.x;
+    unsigned long long c = 0;
     double d = 0.0;
-    for (int64_t b = b0; b <= b1; ++b) {
-        p += part[b + L].proper;
-        t += part[b + L].touch;
-        d += part[b + L].dev;
+    if (tab[L + 1].unit_off > tab[L].unit_off) {
+        const int64_t b0 = block_of_unit(U, G, tab[L].unit_off);
+        const int64_t b1 = block_of_unit(U, G, tab[L + 1].unit_off - 1);
+        for (int64_t b = b0 + tid; b <= b1; b += 256) {
+            c += part[b + L].proper + part[b + L].touch;
+            d += part[b + L].dev;
+        }
     }
-    const unsigned long long count = p + t;
-    if (out_count) out_count[L] = count;
-    if (out_metric) out_metric[L] = count ? 1.0 - (d / ideal) / (double)count : 1.0;
+    sc[tid] = c;
+    sd[tid] = d;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            sc[tid] += sc[tid + s];
+            sd[tid] += sd[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (out_count) out_count[L] = sc[0];
+        if (out_metric) out_metric[L] = sc[0] ? 1.0 - (sd[0] / ideal) / (double)sc[0] : 1.0;
+    }
 }
 
 __global__ __launch_bounds__(256) void batch_occl_finalize_kernel(
-    const OcclPartial *__restrict__ part, const SweepLayout *__restrict__ tab, int64_t B,
-    int64_t U, int64_t G, unsigned long long *out_count) {
-    const int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (L >= B) return;
-    const int64_t b0 = block_of_unit(U, G, tab[L].unit_off);
-    const int64_t b1 = block_of_unit(U, G, tab[L + 1].unit_off - 1);
+    const OcclPartial *__restrict__ part, const SweepLayout *__restrict__ tab, int64_t U,
+    int64_t G, unsigned long long *out_count) {
+    __shared__ unsigned long long sc[256];
+    const int64_t L = blockIdx.x;
+    const int tid = threadIdx.x;
     unsigned long long c = 0;
-    for (int64_t b = b0; b <= b1; ++b) c += part[b + L].count;
-    out_count[L] = c;
+    if (tab[L + 1].unit_off > tab[L].unit_off) {
+        const int64_t b0 = block_of_unit(U, G, tab[L].unit_off);
+        const int64_t b1 = block_of_unit(U, G, tab[L + 1].unit_off - 1);
+        for (int64_t b = b0 + tid; b <= b1; b += 256) c += part[b + L].count;
+    }
+    sc[tid] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) sc[tid] += sc[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) out_count[L] = sc[0];
 }
 
 // Algorithm 3 for one layout per block: mean, then the spread about it.
@@ -293,8 +319,8 @@ hipError_t enqueue_cross(const rb_batch *b, char *w, const BatchIO &io, bool wit
     RB_TRY(launch_cross_sweep(b->cross_var, true, (const EdgeRec *)(w + b->o_erec), a, grid,
                               io.ideal, part, st));
     if (!with_finalize) return hipSuccess;
-    hipLaunchKernelGGL(batch_cross_finalize_kernel, dim3(grid_for(b->B)), dim3(256), 0, st, part,
-                       a.table, b->B, U, (int64_t)grid, io.ideal, io.cross, io.angle);
+    hipLaunchKernelGGL(batch_cross_finalize_kernel, dim3(b->B), dim3(256), 0, st, part, a.table,
+                       U, (int64_t)grid, io.ideal, io.cross, io.angle);
     return hipGetLastError();
 }
 
@@ -312,8 +338,8 @@ hipError_t enqueue_occl(const rb_batch *b, char *w, const BatchIO &io, bool with
     a.unit_base = 0;
     RB_TRY(launch_occl_sweep(b->occl_var, (const NodeRec *)(w + b->o_nrec), a, grid, part, st));
     if (!with_finalize) return hipSuccess;
-    hipLaunchKernelGGL(batch_occl_finalize_kernel, dim3(grid_for(b->B)), dim3(256), 0, st, part,
-                       a.table, b->B, U, (int64_t)grid, io.occl);
+    hipLaunchKernelGGL(batch_occl_finalize_kernel, dim3(b->B), dim3(256), 0, st, part, a.table, U,
+                       (int64_t)grid, io.occl);
     return hipGetLastError();
 }
 

@@ -6,11 +6,13 @@
 // threads of a block keeps K edge records in registers) against a chunk of
 // 256 column edges staged in LDS.  Row tile I meets chunks c >= I*K (the
 // first K of them overlap the tile itself and keep only pairs with column
-// index > row index).  The units of all layouts form one list; a persistent
-// grid takes equal contiguous ranges of it, so a block keeps its row
-// registers across consecutive units and every block does the same number
-// of units (+-1).  A block writes one partial result per layout it touches,
-// into slot block + layout, so the final sums run in a fixed order.
+// index > row index).  The units of all layouts form one list, cut into
+// equal contiguous ranges, one per block, with many more blocks than the chip
+// holds at once (the dispatcher starts each block when a slot frees up, so
+// blocks that meet costly units or slower compute units do not hold back the
+// end of the launch).  A block keeps its row registers across the
+// consecutive units of its range and writes one partial result per layout it
+// touches, into slot block + layout, so the final sums run in a fixed order.
 //
 // Per pair (row edge e, column edge f), all in exact double arithmetic:
 //   o1 = L_e(P_f),  o2 = o1 + cross,   o3 = L_f(P_e),  o4 = o3 - cross,
@@ -239,6 +241,14 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     const int64_t u_end = block_first_unit(U, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
+    if (u_begin == u_end) {                    // more blocks than kept units
+        if (tid == 0) {
+            CrossPartial P;
+            P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
+            part[b] = P;
+        }
+        return;
+    }
 
     // tile of the first unit: the largest I with tile_off[I] <= u_begin
     int64_t lo = 0, hi = n_tiles - 1;
@@ -355,37 +365,11 @@ void launch_v(const EdgeRec *rec, const SweepArgs &a, int grid, double ideal, Cr
                        dim3(grid), dim3(kBlock), 0, st, rec, a, ideal, part);
 }
 
-template <int V>
-const void *kernel_ptr(bool angle) {
-    return angle ? (const void *)cross_sweep_kernel<CrossV<V>::K, CrossV<V>::W, true, false>
-                 : (const void *)cross_sweep_kernel<CrossV<V>::K, CrossV<V>::W, false, false>;
-}
-
-int g_cross_grid[kCrossVariants][2];
-
 }  // namespace
 
 SweepVariant cross_variant(int v) { return kCross[v]; }
 
-int cross_grid(int v, bool angle) {
-    int &g = g_cross_grid[v][angle ? 1 : 0];
-    if (g == 0) {
-        const void *k = nullptr;
-        switch (v) {
-            case 0: k = kernel_ptr<0>(angle); break;
-            case 1: k = kernel_ptr<1>(angle); break;
-            case 2: k = kernel_ptr<2>(angle); break;
-            default: k = kernel_ptr<3>(angle); break;
-        }
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        g = per_cu * device_cu_count();
-        if (g > kMaxPartials) g = kMaxPartials;
-    }
-    return g;
-}
+int cross_grid(int, bool) { return kMaxPartials; }
 
 int g_list_grid[kCrossVariants];
 
@@ -408,8 +392,7 @@ int cross_list_grid(int v) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        g = per_cu * device_cu_count();
-        if (g > kMaxPartials) g = kMaxPartials;
+        g = std::min(per_cu * device_cu_count() * kListBlocksPerSlot, kMaxPartials);
     }
     return g;
 }

@@ -3,8 +3,8 @@
 //
 // Same decomposition as the edge sweep: a row tile of R = 256*K nodes held in
 // registers against chunks of 256 nodes staged in LDS, over the upper
-// triangle of each layout, by a persistent grid taking equal contiguous
-// ranges of the unit list of all layouts.  The exact integer test
+// triangle of each layout, one block per equal contiguous range of the unit
+// list of all layouts (many more blocks than the chip holds at once).  The exact integer test
 // |p_u - p_v|^2 <= T (T = largest integer < d^2) is evaluated as
 // g = x_u x_v + (y_u y_v + q_v) >= h_u (see NodeRec).
 //
@@ -188,27 +188,11 @@ void launch_v(const NodeRec *rec, const SweepArgs &a, int grid, OcclPartial *par
                        dim3(kBlock), 0, st, rec, a, part);
 }
 
-int g_occl_grid[kOcclVariants];
-
 }  // namespace
 
 SweepVariant occl_variant(int v) { return kOccl[v]; }
 
-int occl_grid(int v) {
-    int &g = g_occl_grid[v];
-    if (g == 0) {
-        const void *k = v == 0   ? (const void *)occl_sweep_kernel<OcclV<0>::K, OcclV<0>::W, false>
-                        : v == 1 ? (const void *)occl_sweep_kernel<OcclV<1>::K, OcclV<1>::W, false>
-                                 : (const void *)occl_sweep_kernel<OcclV<2>::K, OcclV<2>::W, false>;
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        g = per_cu * device_cu_count();
-        if (g > kMaxPartials) g = kMaxPartials;
-    }
-    return g;
-}
+int occl_grid(int) { return kMaxPartials; }
 
 hipError_t launch_occl_sweep(int v, const NodeRec *rec, const SweepArgs &a, int grid,
                              OcclPartial *part, hipStream_t st) {

@@ -60,7 +60,16 @@ constexpr int kBlock = 256;          // threads per sweep block (4 waves)
 constexpr int kChunk = 256;          // column records staged in LDS per unit
 constexpr int kMaxRows = 16;         // largest rows-per-thread of any variant
 constexpr int kRecPad = kBlock * kMaxRows;   // record segments padded to this
-constexpr int kMaxPartials = 16384;  // partial slots per single-layout sweep
+// Blocks of one sweep launch, each with its own partial-result slot.  A sweep
+// cuts its unit list into min(units, kMaxPartials) equal contiguous ranges,
+// one per block: far more blocks than fit on the chip at once, so the
+// hardware dispatcher hands ranges to compute units as they free up, which
+// evens out uneven unit costs and clocks.
+constexpr int kMaxPartials = 131072;
+// A sweep over a unit list whose length only the device knows (the pruned
+// paths) launches this many blocks per resident block slot, capped at
+// kMaxPartials; blocks whose range is empty write a zero partial and exit.
+constexpr int kListBlocksPerSlot = 8;
 constexpr int kSmallDeg = 16;        // min-angle: thread-per-node up to this degree
 constexpr int kLdsDeg = 2048;        // min-angle: block sort in LDS up to this degree
 
