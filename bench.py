@@ -51,8 +51,8 @@ OPS_PER_NODE_PAIR = 3
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy: x2.000 and
 # x1.000), by (rows per thread, waves per SIMD).  Valid only for the kernel
 # source they were measured on (first 16 hex digits of its sha256).
-MEASURED_TRAFFIC = {"source_sha": "4d71189eef1a6b0c",
-                    "bytes": {(4, 5): 363.2e6, (3, 6): 490.8e6, (2, 7): 596.7e6, (1, 8): 1149.2e6}}
+MEASURED_TRAFFIC = {"source_sha": "8d982da9b29db078",
+                    "bytes": {(4, 5): 141.2e6, (3, 6): 791.9e6, (2, 7): 165.5e6, (1, 8): 1051.1e6}}
 
 
 def measured_traffic(rows, waves):

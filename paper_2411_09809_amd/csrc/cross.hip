@@ -317,8 +317,42 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     }
 }
 
+// Block i adds slots [i kFoldSpan, (i+1) kFoldSpan) in a fixed order and
+// leaves the total in the span's first slot.
+__global__ __launch_bounds__(256) void cross_fold_kernel(CrossPartial *__restrict__ part,
+                                                         int n_part) {
+    __shared__ unsigned long long sp[256], st[256];
+    __shared__ double sd[256];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kFoldSpan;
+    const int64_t end = std::min<int64_t>(n_part, base + kFoldSpan);
+    unsigned long long p = 0, t = 0;
+    double d = 0.0;
+    for (int64_t i = base + tid; i < end; i += 256) {
+        p += part[i].proper;
+        t += part[i].touch;
+        d += part[i].dev;
+    }
+    sp[tid] = p; st[tid] = t; sd[tid] = d;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            sp[tid] += sp[tid + s];
+            st[tid] += st[tid + s];
+            sd[tid] += sd[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        part[base].proper = sp[0];
+        part[base].touch = st[0];
+        part[base].dev = sd[0];
+    }
+}
+
+// Sum of n slots part[0], part[stride], ..., then the outputs.
 __global__ __launch_bounds__(256) void cross_finalize_kernel(
-    const CrossPartial *__restrict__ part, int n_part, double ideal,
+    const CrossPartial *__restrict__ part, int n, int stride, double ideal,
     unsigned long long *out_count, unsigned long long *out_proper, double *out_metric,
     double *out_dev_sum) {
     __shared__ unsigned long long sp[256], st[256];
@@ -326,10 +360,11 @@ __global__ __launch_bounds__(256) void cross_finalize_kernel(
     const int tid = threadIdx.x;
     unsigned long long p = 0, t = 0;
     double d = 0.0;
-    for (int i = tid; i < n_part; i += 256) {
-        p += part[i].proper;
-        t += part[i].touch;
-        d += part[i].dev;
+    for (int i = tid; i < n; i += 256) {
+        const CrossPartial &q = part[(int64_t)i * stride];
+        p += q.proper;
+        t += q.touch;
+        d += q.dev;
     }
     sp[tid] = p; st[tid] = t; sd[tid] = d;
     __syncthreads();
@@ -441,10 +476,18 @@ hipError_t launch_cross_sweep(int v, bool angle, const EdgeRec *rec, const Sweep
     return hipGetLastError();
 }
 
-hipError_t launch_cross_finalize(const CrossPartial *part, int n_part, double ideal,
+hipError_t launch_cross_finalize(CrossPartial *part, int n_part, double ideal,
                                  unsigned long long *out_count, unsigned long long *out_proper,
                                  double *out_metric, double *out_dev_sum, hipStream_t st) {
-    hipLaunchKernelGGL(cross_finalize_kernel, dim3(1), dim3(256), 0, st, part, n_part, ideal,
+    int n = n_part, stride = 1;
+    if (n_part > kFoldSpan) {
+        n = (n_part + kFoldSpan - 1) / kFoldSpan;
+        stride = kFoldSpan;
+        hipLaunchKernelGGL(cross_fold_kernel, dim3(n), dim3(256), 0, st, part, n_part);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(cross_finalize_kernel, dim3(1), dim3(256), 0, st, part, n, stride, ideal,
                        out_count, out_proper, out_metric, out_dev_sum);
     return hipGetLastError();
 }

@@ -158,13 +158,33 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
     if (seg_units > 0) flush(BATCH ? b + L : b);
 }
 
+// Block i adds slots [i kFoldSpan, (i+1) kFoldSpan) and leaves the total in
+// the span's first slot.
+__global__ __launch_bounds__(256) void occl_fold_kernel(OcclPartial *__restrict__ part,
+                                                        int n_part) {
+    __shared__ unsigned long long s[256];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kFoldSpan;
+    const int64_t end = std::min<int64_t>(n_part, base + kFoldSpan);
+    unsigned long long c = 0;
+    for (int64_t i = base + tid; i < end; i += 256) c += part[i].count;
+    s[tid] = c;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (tid < k) s[tid] += s[tid + k];
+        __syncthreads();
+    }
+    if (tid == 0) part[base].count = s[0];
+}
+
+// Sum of n slots part[0], part[stride], ...
 __global__ __launch_bounds__(256) void occl_finalize_kernel(const OcclPartial *__restrict__ part,
-                                                            int n_part,
+                                                            int n, int stride,
                                                             unsigned long long *out_count) {
     __shared__ unsigned long long s[256];
     const int tid = threadIdx.x;
     unsigned long long c = 0;
-    for (int i = tid; i < n_part; i += 256) c += part[i].count;
+    for (int i = tid; i < n; i += 256) c += part[(int64_t)i * stride].count;
     s[tid] = c;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
@@ -206,9 +226,18 @@ hipError_t launch_occl_sweep(int v, const NodeRec *rec, const SweepArgs &a, int 
     return hipGetLastError();
 }
 
-hipError_t launch_occl_finalize(const OcclPartial *part, int n_part,
-                                unsigned long long *out_count, hipStream_t st) {
-    hipLaunchKernelGGL(occl_finalize_kernel, dim3(1), dim3(256), 0, st, part, n_part, out_count);
+hipError_t launch_occl_finalize(OcclPartial *part, int n_part, unsigned long long *out_count,
+                                hipStream_t st) {
+    int n = n_part, stride = 1;
+    if (n_part > kFoldSpan) {
+        n = (n_part + kFoldSpan - 1) / kFoldSpan;
+        stride = kFoldSpan;
+        hipLaunchKernelGGL(occl_fold_kernel, dim3(n), dim3(256), 0, st, part, n_part);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(occl_finalize_kernel, dim3(1), dim3(256), 0, st, part, n, stride,
+                       out_count);
     return hipGetLastError();
 }
 

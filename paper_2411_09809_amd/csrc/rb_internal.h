@@ -206,13 +206,18 @@ hipError_t launch_node_prep(const float *x, const float *y, int64_t n_nodes, int
 
 hipError_t launch_cross_sweep(int variant, bool angle, const EdgeRec *rec, const SweepArgs &a,
                               int grid, double ideal, CrossPartial *part, hipStream_t st);
-hipError_t launch_cross_finalize(const CrossPartial *part, int n_part, double ideal,
+// The finalize calls sum n_part slots in a fixed order.  Above kFoldSpan
+// slots a first kernel folds each span of kFoldSpan slots into its first
+// slot (in place: the slots' contents are consumed), then one block adds
+// the span totals.
+constexpr int kFoldSpan = 2048;
+hipError_t launch_cross_finalize(CrossPartial *part, int n_part, double ideal,
                                  unsigned long long *out_count, unsigned long long *out_proper,
                                  double *out_metric, double *out_dev_sum, hipStream_t st);
 hipError_t launch_occl_sweep(int variant, const NodeRec *rec, const SweepArgs &a, int grid,
                              OcclPartial *part, hipStream_t st);
-hipError_t launch_occl_finalize(const OcclPartial *part, int n_part,
-                                unsigned long long *out_count, hipStream_t st);
+hipError_t launch_occl_finalize(OcclPartial *part, int n_part, unsigned long long *out_count,
+                                hipStream_t st);
 
 hipError_t launch_elv(const float *x, const float *y, const int32_t *src, const int32_t *dst,
                       int64_t n_nodes, int64_t n_edges, double *partial, Scalars *sc,
