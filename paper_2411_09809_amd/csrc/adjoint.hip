@@ -140,9 +140,12 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     __shared__ double red_d[kBlock / 64];
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
+    // with a list, the first min(U, G) blocks take one equal range each, so
+    // blocks with work are dispatched before the empty ones
     const int64_t U = LIST ? (int64_t)tile_off[n_tiles] : n_units;
-    const int64_t u_begin = block_first_unit(U, G, b);
-    const int64_t u_end = block_first_unit(U, G, b + 1);
+    const int64_t n_items = std::min<int64_t>(U, G);
+    const int64_t u_begin = b < n_items ? block_first_unit(U, n_items, b) : 0;
+    const int64_t u_end = b < n_items ? block_first_unit(U, n_items, b + 1) : 0;
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
     if (LIST && u_begin == u_end) {            // more blocks than kept units

@@ -236,9 +236,12 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
 
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
+    // the first min(U, G) blocks take one equal range each, so blocks with
+    // work are dispatched before the empty ones
     const int64_t U = tile_off[n_tiles];
-    const int64_t u_begin = block_first_unit(U, G, b);
-    const int64_t u_end = block_first_unit(U, G, b + 1);
+    const int64_t n_items = std::min<int64_t>(U, G);
+    const int64_t u_begin = b < n_items ? block_first_unit(U, n_items, b) : 0;
+    const int64_t u_end = b < n_items ? block_first_unit(U, n_items, b + 1) : 0;
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
     if (u_begin == u_end) {                    // more blocks than kept units
