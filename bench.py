@@ -47,12 +47,16 @@ OPS_PER_EDGE_PAIR = 17
 # per node pair of the occlusion test: 2 FMA + 1 max (the exact count runs
 # only for the rare chunks that hold an occluding pair)
 OPS_PER_NODE_PAIR = 3
+# per edge pair of the fused forward + adjoint sweep: the 17 above, then the
+# dot product of the directions (2), the sign product (v dot) cross (2), two
+# compares for q = +1 / -1 and the masked +-1 into the row's integer sum (2)
+OPS_PER_ADJOINT_PAIR = 25
 # HBM bytes per launch of the crossing + angle sweep on this workload, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy: x2.000 and
 # x1.000), by (rows per thread, waves per SIMD).  Valid only for the kernel
 # source they were measured on (first 16 hex digits of its sha256).
-MEASURED_TRAFFIC = {"source_sha": "8d982da9b29db078",
-                    "bytes": {(4, 5): 141.2e6, (3, 6): 791.9e6, (2, 7): 165.5e6, (1, 8): 1051.1e6}}
+MEASURED_TRAFFIC = {"source_sha": "ab5d2f79d670990a",
+                    "bytes": {(4, 5): 142.2e6, (3, 6): 796.1e6, (2, 7): 165.6e6, (1, 8): 1050.8e6}}
 
 
 def measured_traffic(rows, waves):
@@ -184,6 +188,9 @@ def bench_adjoint(torch, reps: int, gd_steps: int):
             fn()
         torch.cuda.synchronize()
         out[name] = (time.perf_counter() - t0) * 1e3 / reps
+    adj_ms = time_kind(torch, 4, fwd_bwd, reps)
+    out["adjoint_sweep_ms"] = adj_ms
+    out["adjoint_sweep_valu_frac"] = OPS_PER_ADJOINT_PAIR * pairs / (adj_ms * 1e-3) / VALU_PEAK_OPS
     for pruned in (False, True):        # first-use costs (autograd, events) stay out
         optim.descend(D.x, D.y, D.src, D.dst, steps=2, step_size=2.0, pruned=pruned)
     torch.cuda.synchronize()

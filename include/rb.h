@@ -322,13 +322,6 @@ rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *wa
 rb_status rb_tune_save(const char *path);
 rb_status rb_tune_load(const char *path);
 
-/* Kernel timing for measurement.  While enabled, the library records a HIP
- * event pair on the caller's stream around each launch of its all-pairs
- * sweep kernels.  rb_timing_read waits for the recorded events and returns
- * the summed duration in milliseconds and the number of launches of one
- * kind: 0 = edge-pair sweep (crossing / crossing angle), 1 = node-pair
- * sweep (occlusion), 2 = grid occlusion (all its kernels), 3 = pruned
- * edge-pair path (all its kernels).  rb_timing_reset clears the sums.     */
 /* Attainable FP64 FMA rate of the current device, the practical ceiling the
  * sweeps are measured against: one untimed and `repeats` timed launches of
  * a kernel of independent FMA chains (`iters` FMAs per chain) on `stream`,
@@ -338,6 +331,16 @@ rb_status rb_tune_load(const char *path);
  * iters in [1, 2^24], repeats in [1, 1000].                               */
 rb_status rb_valu_probe(int iters, int repeats, double *out_lane_ops_per_s, double *sink,
                         void *stream);
+
+/* Kernel timing for measurement.  While enabled, the library records a HIP
+ * event pair on the caller's stream around each launch of its all-pairs
+ * sweep kernels.  rb_timing_read waits for the recorded events and returns
+ * the summed duration in milliseconds and the number of launches of one
+ * kind: 0 = edge-pair sweep (crossing / crossing angle), 1 = node-pair
+ * sweep (occlusion), 2 = grid occlusion (all its kernels), 3 = pruned
+ * edge-pair path (all its kernels), 4 = the fused forward + adjoint
+ * edge-pair sweep of rb_loss_grad (that kernel only).  rb_timing_reset
+ * clears the sums.                                                        */
 rb_status rb_timing_enable(int enable);
 rb_status rb_timing_reset(void);
 rb_status rb_timing_read(int kernel, double *total_ms, int64_t *launches);

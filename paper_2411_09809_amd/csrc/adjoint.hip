@@ -350,9 +350,11 @@ hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, con
     const int64_t U = sweep_units(n_edges, kAdjRows);
     const int grid = (int)std::min<int64_t>(U, kMaxPartials);
     CrossPartial *part = (CrossPartial *)(w + L.partial);
+    TimedEvents te = timed_begin(4, st);
     hipLaunchKernelGGL((adjoint_sweep_kernel<kAdjRows, kAdjWaves, false>), dim3(grid),
                        dim3(kBlock), 0, st, rec, lay, U, nullptr, nullptr, (int64_t)0, ideal, kacc,
                        part);
+    timed_end(te);
     RB_TRY(hipGetLastError());
     RB_TRY(launch_cross_finalize(part, grid, ideal, fw_count, nullptr, fw_eca, nullptr, st));
     hipLaunchKernelGGL(stash_kernel, dim3(1), dim3(64), 0, st, sc, fw_count, fw_eca, fw_ml,

@@ -39,8 +39,9 @@ constexpr int64_t kMaxEdges = 1LL << 30;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Timing of the sweep kernels (rb_timing_*): 0 edge-pair sweep, 1 node-pair
-// sweep, 2 grid occlusion, 3 pruned edge sweep.
-constexpr int kTimedKinds = 4;
+// sweep, 2 grid occlusion, 3 pruned edge sweep, 4 fused forward + adjoint
+// sweep.
+constexpr int kTimedKinds = 5;
 struct Timing {
     std::mutex mu;
     bool on = false;
@@ -70,6 +71,30 @@ struct TimedLaunch {
         a = b = nullptr;
     }
 };
+
+}  // namespace
+
+TimedEvents timed_begin(int kind, hipStream_t st) {
+    TimedEvents t{kind, st, nullptr, nullptr};
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    if (!g_timing.on || kind < 0 || kind >= kTimedKinds) return t;
+    if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess) {
+        t.a = t.b = nullptr;
+        return t;
+    }
+    (void)hipEventRecord(t.a, st);
+    return t;
+}
+
+void timed_end(TimedEvents &t) {
+    if (!t.a) return;
+    (void)hipEventRecord(t.b, t.st);
+    std::lock_guard<std::mutex> g(g_timing.mu);
+    g_timing.ev[t.kind].emplace_back(t.a, t.b);
+    t.a = t.b = nullptr;
+}
+
+namespace {
 
 rb_status check_sizes(int64_t n_nodes, int64_t n_edges) {
     if (n_nodes < 0 || n_nodes > kMaxNodes)

@@ -304,6 +304,15 @@ int device_cu_count();
 
 // FP64 FMA issue-rate probe (probe.hip): one launch of independent FMA
 // chains; *out_lane_ops receives the FMA lane-operations it performs.
+// rb_timing_* hooks for launches made outside the entry-point file: while
+// timing is on, an event pair around the launch is kept for rb_timing_read.
+struct TimedEvents {
+    int kind;
+    hipStream_t st;
+    hipEvent_t a, b;
+};
+TimedEvents timed_begin(int kind, hipStream_t st);
+void timed_end(TimedEvents &t);
 hipError_t launch_valu_probe(int iters, double *sink, double *out_lane_ops, hipStream_t st);
 
 // Error text of the calling host thread (api.hip); set_error and hip_error
