@@ -82,6 +82,18 @@ def test_argument_errors_need_no_gpu(L):
                               None) == _lib.RB_EWORKSPACE
     assert "needed" in _err(L)
     assert L.rb_timing_read(7, None, None) == _lib.RB_EINVAL
+    assert L.rb_timing_read(5, None, None) == _lib.RB_EINVAL
+    # kind 4 (the fused forward + adjoint sweep) exists; nothing is recorded yet
+    import ctypes as C
+    ms, n = C.c_double(-1.0), C.c_int64(-1)
+    assert L.rb_timing_reset() == 0
+    assert L.rb_timing_read(4, C.byref(ms), C.byref(n)) == 0
+    assert ms.value == 0.0 and n.value == 0
+    # the FMA probe checks its arguments before touching the device
+    rate = C.c_double()
+    assert L.rb_valu_probe(0, 1, C.byref(rate), fake, None) == _lib.RB_EINVAL
+    assert L.rb_valu_probe(16, 1, None, fake, None) == _lib.RB_EINVAL
+    assert L.rb_valu_probe(16, 1, C.byref(rate), None, None) == _lib.RB_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
