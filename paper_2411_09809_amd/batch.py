@@ -2,8 +2,7 @@
 
 ``Batch`` concatenates a list of layouts on the GPU, builds and uploads the
 plan once, and then evaluates all five metrics of every layout with one
-persistent launch per all-pairs sweep -- eagerly, or by replaying a captured
-hipGraph.  Results are device tensors of one entry per layout.
+launch per all-pairs sweep -- eagerly, or by replaying a captured hipGraph.  Results are device tensors of one entry per layout.
 """
 from __future__ import annotations
 

@@ -188,7 +188,8 @@ struct SweepPlan {
 // Unit list of one layout of n_items records for a variant.
 SweepLayout sweep_layout(int64_t n_items, int rows, int64_t unit_off, int64_t rec_off);
 int64_t sweep_units(int64_t n_items, int rows);
-// Persistent grid size (blocks) of a variant on the current device.
+// Largest grid (blocks) of a sweep variant; a launch uses min(units, this),
+// one equal contiguous range of the unit list per block.
 int cross_grid(int variant, bool angle);
 int occl_grid(int variant);
 
