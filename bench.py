@@ -75,17 +75,35 @@ def log(*a):
 
 def cpu_baseline(L, budget_pairs: float):
     """Time the oracle's crossing + crossing-angle test on the first S edges
-    of the layout (S chosen so the sample has ~budget_pairs pairs)."""
+    of the layout (S chosen so the sample has ~budget_pairs pairs), on all
+    OpenMP threads, and on one thread over a sample 16 times smaller."""
+    import ctypes as C
     import oracle
-    S = min(L.n_edges, int(math.sqrt(2 * budget_pairs)))
-    t0 = time.perf_counter()
-    oracle.crossing_angle(L.x, L.y, L.src[:S], L.dst[:S], L.ideal_angle)
-    dt = time.perf_counter() - t0
+
+    def run(n_pairs):
+        S = min(L.n_edges, int(math.sqrt(2 * n_pairs)))
+        t0 = time.perf_counter()
+        oracle.crossing_angle(L.x, L.y, L.src[:S], L.dst[:S], L.ideal_angle)
+        return S, time.perf_counter() - t0
+
+    S, dt = run(budget_pairs)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": math.comb(S, 2) / dt, "unit": "edge-pair tests/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"crossing + crossing-angle test over the first {S} edges "
-                      f"({math.comb(S, 2):.3e} pairs) of the same layout, {dt:.1f} s"}
+    out = {"value": math.comb(S, 2) / dt, "unit": "edge-pair tests/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"crossing + crossing-angle test over the first {S} edges "
+                     f"({math.comb(S, 2):.3e} pairs) of the same layout, {dt:.1f} s"}
+    try:                                  # the oracle's OpenMP runtime
+        gomp = C.CDLL("libgomp.so.1")
+    except OSError:
+        return out
+    gomp.omp_set_num_threads(1)
+    try:
+        S1, dt1 = run(budget_pairs / 16)
+    finally:
+        gomp.omp_set_num_threads(threads)
+    out["value_1_thread"] = math.comb(S1, 2) / dt1
+    out["sample_1_thread"] = (f"first {S1} edges ({math.comb(S1, 2):.3e} pairs), {dt1:.1f} s")
+    return out
 
 
 def valu_probe(torch, iters=4096, repeats=20):
