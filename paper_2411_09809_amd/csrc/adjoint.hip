@@ -310,7 +310,7 @@ int grid_for(int64_t n) {
     return (int)g;
 }
 
-constexpr int kAdjRows = 1, kAdjWaves = 8;
+constexpr int kAdjRows = 1, kAdjWaves = 7;
 int g_adj_list_grid = 0;
 
 #define RB_TRY(expr)                          \
