@@ -371,24 +371,20 @@ hipError_t side_stream(const rb_batch *b, hipStream_t *out) {
     return hipSuccess;
 }
 
-// With `overlap`, the edge sweep runs on `main` and the node sweep, edge
-// lengths and minimum angle on the batch's second stream, forked from
-// `main` after the record prep and joined back at the end; their workspace
-// regions are disjoint.  Without it (graph capture, where a replay of the
-// forked graph measured slower than the one-stream graph) everything runs
-// on `main` in that order.
-hipError_t enqueue_all(const rb_batch *b, char *w, const BatchIO &io, hipStream_t main,
-                       bool overlap) {
+// The edge sweep runs on `main` and the node sweep, edge lengths and
+// minimum angle on the batch's second stream, forked from `main` after the
+// record prep and joined back at the end; their workspace regions are
+// disjoint.  A graph captured from `main` holds the same fork as two
+// branches.
+hipError_t enqueue_all(const rb_batch *b, char *w, const BatchIO &io, hipStream_t main) {
     const int64_t *noff = (const int64_t *)(w + b->o_noff);
     const int64_t *eoff = (const int64_t *)(w + b->o_eoff);
     const bool need_cross = io.cross || io.angle;
     RB_TRY(enqueue_prep(b, w, io, main));
     hipStream_t st = main;
-    if (overlap) {
-        RB_TRY(side_stream(b, &st));
-        RB_TRY(hipEventRecord(b->fork, main));
-        RB_TRY(hipStreamWaitEvent(st, b->fork, 0));
-    }
+    RB_TRY(side_stream(b, &st));
+    RB_TRY(hipEventRecord(b->fork, main));
+    RB_TRY(hipStreamWaitEvent(st, b->fork, 0));
     if (io.occl) RB_TRY(enqueue_occl(b, w, io, true, st));
     if (io.elv) {
         hipLaunchKernelGGL(batch_elv_kernel, dim3((unsigned)b->B), dim3(256), 0, st, io.x, io.y,
@@ -425,7 +421,6 @@ hipError_t enqueue_all(const rb_batch *b, char *w, const BatchIO &io, hipStream_
         RB_TRY(hipGetLastError());
     }
     if (need_cross) RB_TRY(enqueue_cross(b, w, io, true, main));
-    if (!overlap) return hipSuccess;
     RB_TRY(hipEventRecord(b->join, st));
     return hipStreamWaitEvent(main, b->join, 0);
 }
@@ -584,7 +579,7 @@ rb_status rb_batch_evaluate(const rb_batch *b, const float *x, const float *y, c
                (unsigned long long *)out_crossings, out_crossing_angle, out_min_angle, out_elv};
     rb_status s = check_io(b, io, ws, ws_bytes);
     if (s) return s;
-    hipError_t e = enqueue_all(b, (char *)ws, io, (hipStream_t)stream, true);
+    hipError_t e = enqueue_all(b, (char *)ws, io, (hipStream_t)stream);
     if (e != hipSuccess) return (rb_status)hip_error(e, "rb_batch_evaluate");
     return RB_OK;
 }
@@ -679,7 +674,7 @@ rb_status rb_batch_graph_create(const rb_batch *b, const float *x, const float *
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e2 = enqueue_all(b, (char *)ws, io, cs, false);
+        hipError_t e2 = enqueue_all(b, (char *)ws, io, cs);
         e = hipStreamEndCapture(cs, &graph);
         if (e2 != hipSuccess) e = e2;
     }
