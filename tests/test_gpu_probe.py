@@ -25,3 +25,32 @@ def test_probe_rate_is_below_the_nominal_peak():
     assert float(sink.item()) == 0.0
     for iters, reps in ((0, 1), (1 << 25, 1), (4, 0), (4, 1001)):
         assert R.rb_valu_probe(iters, reps, C.byref(rate), C.c_void_p(sink.data_ptr()), stream) != 0
+
+
+def test_timing_records_the_fused_adjoint_sweep():
+    """rb_timing kind 4 holds one event pair per rb_loss_grad call (the fused
+    forward + adjoint sweep only), and none for the plain crossing sweep."""
+    import torch
+    from paper_2411_09809_amd import gen, metrics, optim
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    R = _lib.lib()
+    L = gen.uniform_layout(seed=0)
+    D = metrics.DeviceLayout.from_host(L)
+    optim.loss_grad(D.x, D.y, D.src, D.dst)
+    torch.cuda.synchronize()
+    R.rb_timing_reset()
+    R.rb_timing_enable(1)
+    try:
+        for _ in range(3):
+            optim.loss_grad(D.x, D.y, D.src, D.dst)
+        metrics.crossing_angle(D.x, D.y, D.src, D.dst)
+        torch.cuda.synchronize()
+    finally:
+        R.rb_timing_enable(0)
+    ms, n = C.c_double(), C.c_int64()
+    _lib.check(R.rb_timing_read(4, C.byref(ms), C.byref(n)), "timing")
+    assert n.value == 3 and ms.value > 0.0
+    _lib.check(R.rb_timing_read(0, C.byref(ms), C.byref(n)), "timing")
+    assert n.value == 1
+    R.rb_timing_reset()
