@@ -67,8 +67,14 @@ void load_locked(const char *path) {
 }
 
 // the built-in default of a kind and size class: the pruned sweep takes the
-// 1-row tiles (tightest boxes) below 2^17 edges and 2-row tiles above
-int default_variant(int k, int c) { return (k == 3 && c >= 17) ? 1 : kDefault[k]; }
+// 1-row tiles (tightest boxes) below 2^17 edges and 2-row tiles above; the
+// node sweep takes 8-row tiles from 2^19 nodes (the fewest LDS reads per
+// pair, once there are units enough to fill the chip)
+int default_variant(int k, int c) {
+    if (k == 3 && c >= 17) return 1;
+    if (k == 2 && c >= 19) return 0;
+    return kDefault[k];
+}
 
 void defaults_locked() {
     for (int k = 0; k < kKinds; ++k)
