@@ -44,7 +44,7 @@ def lib():
         L.oracle_edge_length_variation.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _dp, _dp]
         L.oracle_segment_pair.argtypes = [_dp, C.c_double, C.POINTER(C.c_int), _dp]
         L.oracle_crossing_angle_rows.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, C.c_double,
-                                                 _i64, _i64, _u64p, _dp]
+                                                 _i64, _i64, _u64p, _u64p, _dp]
         L.oracle_node_occlusion_rows.argtypes = [_dp, _dp, _i64, C.c_double, _i64, _i64, _u64p]
         L.oracle_enhanced_crossing.argtypes = [_dp, _dp, _i64, _i32p, _i32p, _i64, _i64, C.c_int,
                                                C.c_double, _u64p, _dp]
@@ -154,14 +154,19 @@ def segment_pair(p, ideal_angle: float = 1.2217304763960306) -> tuple[int, float
     return int(kind.value), float(ang.value)
 
 
-def crossing_angle_rows(x, y, src, dst, ideal_angle: float, r0: int, r1: int):
-    """(crossings, sum of |ideal - a|/ideal) over pairs (e, f), r0 <= e < r1, e < f."""
+def crossing_angle_rows(x, y, src, dst, ideal_angle: float, r0: int, r1: int,
+                        proper: bool = False):
+    """(crossings, sum of |ideal - a|/ideal) over pairs (e, f), r0 <= e < r1,
+    e < f; with ``proper``, (crossings, proper crossings, sum)."""
     x, y, s, d = _f64(x), _f64(y), _i32(src), _i32(dst)
-    cnt, dev = C.c_uint64(), C.c_double()
+    cnt, prop, dev = C.c_uint64(), C.c_uint64(), C.c_double()
     _check(lib().oracle_crossing_angle_rows(_p(x, _dp), _p(y, _dp), x.shape[0], _p(s, _i32p),
                                             _p(d, _i32p), s.shape[0], float(ideal_angle),
-                                            int(r0), int(r1), C.byref(cnt), C.byref(dev)),
+                                            int(r0), int(r1), C.byref(cnt), C.byref(prop),
+                                            C.byref(dev)),
            "crossing_angle_rows")
+    if proper:
+        return int(cnt.value), int(prop.value), float(dev.value)
     return int(cnt.value), float(dev.value)
 
 

@@ -131,25 +131,43 @@ static int ccw(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t cx, int64
 static int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 static int64_t max64(int64_t a, int64_t b) { return a > b ? a : b; }
 
-/* Crossing test of two edges (v1,u1) and (v2,u2) given by node ids.
+/* Algorithm 4 first joins every edge with the positions of its two end
+ * nodes (the table the paper calls D_epos); the pair tests below read that
+ * table.  Coordinates are integers with |c| <= 2^20, so they fit in int32. */
+typedef struct { int32_t v, u; int32_t x1, y1, x2, y2; } epos_t;
+
+static epos_t *join_positions(const int64_t *ix, const int64_t *iy, const int32_t *src,
+                              const int32_t *dst, int64_t m) {
+    epos_t *E = (epos_t *)malloc(sizeof(epos_t) * (size_t)(m > 0 ? m : 1));
+    for (int64_t e = 0; e < m; ++e) {
+        E[e].v = src[e];
+        E[e].u = dst[e];
+        E[e].x1 = (int32_t)ix[src[e]];
+        E[e].y1 = (int32_t)iy[src[e]];
+        E[e].x2 = (int32_t)ix[dst[e]];
+        E[e].y2 = (int32_t)iy[dst[e]];
+    }
+    return E;
+}
+
+/* Crossing test of two edges a = (v1,u1) and b = (v2,u2).
  * Returns 0 (no crossing), 1 (crossing, segments touch or overlap),
  * 2 (proper crossing: each segment strictly separates the other's ends). */
-static int edge_pair_crossing(const int64_t *ix, const int64_t *iy,
-                              int32_t v1, int32_t u1, int32_t v2, int32_t u2) {
+static int edge_pair_crossing(const epos_t *a, const epos_t *b) {
     /* R2: pairs sharing an endpoint id are incident, not crossing */
-    if (v1 == v2 || v1 == u2 || u1 == v2 || u1 == u2) return 0;
-    int c1 = ccw(ix[v1], iy[v1], ix[u1], iy[u1], ix[v2], iy[v2]);
-    int c2 = ccw(ix[v1], iy[v1], ix[u1], iy[u1], ix[u2], iy[u2]);
-    int c3 = ccw(ix[v2], iy[v2], ix[u2], iy[u2], ix[v1], iy[v1]);
-    int c4 = ccw(ix[v2], iy[v2], ix[u2], iy[u2], ix[u1], iy[u1]);
+    if (a->v == b->v || a->v == b->u || a->u == b->v || a->u == b->u) return 0;
+    int c1 = ccw(a->x1, a->y1, a->x2, a->y2, b->x1, b->y1);
+    int c2 = ccw(a->x1, a->y1, a->x2, a->y2, b->x2, b->y2);
+    int c3 = ccw(b->x1, b->y1, b->x2, b->y2, a->x1, a->y1);
+    int c4 = ccw(b->x1, b->y1, b->x2, b->y2, a->x2, a->y2);
     int p12 = c1 * c2, p34 = c3 * c4;
     if (p12 > 0 || p34 > 0) return 0;              /* Algorithm 4's <= 0 test */
     if (p12 < 0 && p34 < 0) return 2;
     if (p12 == 0 && p34 == 0) {                    /* R3: boxes must meet */
-        int64_t ax0 = min64(ix[v1], ix[u1]), ax1 = max64(ix[v1], ix[u1]);
-        int64_t ay0 = min64(iy[v1], iy[u1]), ay1 = max64(iy[v1], iy[u1]);
-        int64_t bx0 = min64(ix[v2], ix[u2]), bx1 = max64(ix[v2], ix[u2]);
-        int64_t by0 = min64(iy[v2], iy[u2]), by1 = max64(iy[v2], iy[u2]);
+        int64_t ax0 = min64(a->x1, a->x2), ax1 = max64(a->x1, a->x2);
+        int64_t ay0 = min64(a->y1, a->y2), ay1 = max64(a->y1, a->y2);
+        int64_t bx0 = min64(b->x1, b->x2), bx1 = max64(b->x1, b->x2);
+        int64_t by0 = min64(b->y1, b->y2), by1 = max64(b->y1, b->y2);
         if (max64(ax0, bx0) > min64(ax1, bx1)) return 0;
         if (max64(ay0, by0) > min64(ay1, by1)) return 0;
     }
@@ -164,16 +182,17 @@ int oracle_edge_crossing(const double *x, const double *y, int64_t n,
     int64_t *ix, *iy;
     int st = to_int_coords(x, y, n, &ix, &iy);
     if (st) return st;
+    epos_t *E = join_positions(ix, iy, src, dst, m);
     uint64_t closed = 0, proper = 0;
     #pragma omp parallel for schedule(dynamic, 16) reduction(+:closed, proper)
     for (int64_t e = 0; e < m; ++e) {
         for (int64_t f = e + 1; f < m; ++f) {          /* each unordered pair once */
-            int r = edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f]);
+            int r = edge_pair_crossing(&E[e], &E[f]);
             closed += (r != 0);
             proper += (r == 2);
         }
     }
-    free(ix); free(iy);
+    free(E); free(ix); free(iy);
     *out_count = closed;
     if (out_proper) *out_proper = proper;
     return 0;
@@ -183,10 +202,9 @@ int oracle_edge_crossing(const double *x, const double *y, int64_t n,
 
 /* Acute angle between the lines of two edges, from exact integer cross and
  * dot products of their direction vectors (R5). */
-static double crossing_angle(const int64_t *ix, const int64_t *iy,
-                             int32_t v1, int32_t u1, int32_t v2, int32_t u2) {
-    int64_t ax = ix[u1] - ix[v1], ay = iy[u1] - iy[v1];
-    int64_t bx = ix[u2] - ix[v2], by = iy[u2] - iy[v2];
+static double crossing_angle(const epos_t *a, const epos_t *b) {
+    int64_t ax = (int64_t)a->x2 - a->x1, ay = (int64_t)a->y2 - a->y1;
+    int64_t bx = (int64_t)b->x2 - b->x1, by = (int64_t)b->y2 - b->y1;
     int64_t cr = ax * by - ay * bx;
     int64_t dt = ax * bx + ay * by;
     return atan2(fabs((double)cr), fabs((double)dt));
@@ -201,14 +219,15 @@ int oracle_crossing_angle(const double *x, const double *y, int64_t n,
     int64_t *ix, *iy;
     int st = to_int_coords(x, y, n, &ix, &iy);
     if (st) return st;
+    epos_t *E = join_positions(ix, iy, src, dst, m);
     double *row_sum = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
     uint64_t count = 0;
     #pragma omp parallel for schedule(dynamic, 16) reduction(+:count)
     for (int64_t e = 0; e < m; ++e) {
         nsum acc = {0.0, 0.0};
         for (int64_t f = e + 1; f < m; ++f) {
-            if (!edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) continue;
-            double a = crossing_angle(ix, iy, src[e], dst[e], src[f], dst[f]);
+            if (!edge_pair_crossing(&E[e], &E[f])) continue;
+            double a = crossing_angle(&E[e], &E[f]);
             nsum_add(&acc, fabs(ideal_angle - a) / ideal_angle);      /* R6 */
             count += 1;
         }
@@ -217,7 +236,7 @@ int oracle_crossing_angle(const double *x, const double *y, int64_t n,
     nsum tot = {0.0, 0.0};
     for (int64_t e = 0; e < m; ++e) nsum_add(&tot, row_sum[e]);
     double s = nsum_get(&tot);
-    free(row_sum); free(ix); free(iy);
+    free(row_sum); free(E); free(ix); free(iy);
     *out_metric = count ? 1.0 - s / (double)count : 1.0;               /* R7 */
     if (out_count) *out_count = count;
     if (out_dev_sum) *out_dev_sum = s;
@@ -238,6 +257,7 @@ int oracle_crossings_of_edges(const double *x, const double *y, int64_t n,
     int64_t *ix, *iy;
     int st = to_int_coords(x, y, n, &ix, &iy);
     if (st) return st;
+    epos_t *E = join_positions(ix, iy, src, dst, m);
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t i = 0; i < k; ++i) {
         int64_t e = which[i];
@@ -245,14 +265,14 @@ int oracle_crossings_of_edges(const double *x, const double *y, int64_t n,
         nsum acc = {0.0, 0.0};
         for (int64_t f = 0; f < m; ++f) {
             if (f == e) continue;
-            if (!edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) continue;
+            if (!edge_pair_crossing(&E[e], &E[f])) continue;
             c += 1;
-            nsum_add(&acc, fabs(ideal_angle - crossing_angle(ix, iy, src[e], dst[e], src[f], dst[f])));
+            nsum_add(&acc, fabs(ideal_angle - crossing_angle(&E[e], &E[f])));
         }
         out_count[i] = c;
         if (out_dev) out_dev[i] = nsum_get(&acc);
     }
-    free(ix); free(iy);
+    free(E); free(ix); free(iy);
     return 0;
 }
 
@@ -370,8 +390,11 @@ int oracle_segment_pair(const double *p, double ideal_angle, int *out_kind,
     int64_t *ix, *iy;
     int st = to_int_coords(x, y, 4, &ix, &iy);
     if (st) return st;
-    *out_kind = edge_pair_crossing(ix, iy, 0, 1, 2, 3);
-    if (out_angle) *out_angle = crossing_angle(ix, iy, 0, 1, 2, 3);
+    const int32_t src[2] = {0, 2}, dst[2] = {1, 3};
+    epos_t *E = join_positions(ix, iy, src, dst, 2);
+    *out_kind = edge_pair_crossing(&E[0], &E[1]);
+    if (out_angle) *out_angle = crossing_angle(&E[0], &E[1]);
+    free(E);
     (void)ideal_angle;
     free(ix); free(iy);
     return 0;
@@ -400,6 +423,7 @@ int oracle_crossing_pairs(const double *x, const double *y, int64_t n,
     int64_t *ix, *iy;
     int st = to_int_coords(x, y, n, &ix, &iy);
     if (st) return st;
+    epos_t *E = join_positions(ix, iy, src, dst, m);
     /* count per row, then fill each row's slice: the pairs come out in
      * (e, f) order whatever the thread count */
     int64_t *row = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
@@ -407,7 +431,7 @@ int oracle_crossing_pairs(const double *x, const double *y, int64_t n,
     for (int64_t e = 0; e < m; ++e) {
         int64_t c = 0;
         for (int64_t f = e + 1; f < m; ++f)
-            c += edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f]) != 0;
+            c += edge_pair_crossing(&E[e], &E[f]) != 0;
         row[e + 1] = c;
     }
     for (int64_t e = 0; e < m; ++e) row[e + 1] += row[e];
@@ -417,7 +441,7 @@ int oracle_crossing_pairs(const double *x, const double *y, int64_t n,
         for (int64_t e = 0; e < m; ++e) {
             int64_t at = row[e];
             for (int64_t f = e + 1; f < m; ++f)
-                if (edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) {
+                if (edge_pair_crossing(&E[e], &E[f])) {
                     out_pairs[2 * at] = e;
                     out_pairs[2 * at + 1] = f;
                     ++at;
@@ -425,7 +449,7 @@ int oracle_crossing_pairs(const double *x, const double *y, int64_t n,
         }
     }
     free(row);
-    free(ix); free(iy);
+    free(E); free(ix); free(iy);
     *out_n = k;
     return 0;
 }
@@ -523,31 +547,36 @@ int oracle_loss_grad(const double *x, const double *y, int64_t n, const int32_t 
 int oracle_crossing_angle_rows(const double *x, const double *y, int64_t n,
                                const int32_t *src, const int32_t *dst, int64_t m,
                                double ideal_angle, int64_t r0, int64_t r1,
-                               uint64_t *out_count, double *out_dev_sum) {
+                               uint64_t *out_count, uint64_t *out_proper,
+                               double *out_dev_sum) {
     if (n < 0 || m < 0 || r0 < 0 || r1 < r0 || r1 > m || !out_count || !(ideal_angle > 0.0))
         return 1;
     if (check_edges(src, dst, m, n)) return 3;
     int64_t *ix, *iy;
     int st = to_int_coords(x, y, n, &ix, &iy);
     if (st) return st;
+    epos_t *E = join_positions(ix, iy, src, dst, m);
     const int64_t k = r1 - r0;
     double *row_sum = (double *)calloc((size_t)(k > 0 ? k : 1), sizeof(double));
-    uint64_t count = 0;
-    #pragma omp parallel for schedule(dynamic, 4) reduction(+:count)
+    uint64_t count = 0, proper = 0;
+    #pragma omp parallel for schedule(dynamic, 4) reduction(+:count, proper)
     for (int64_t e = r0; e < r1; ++e) {
         nsum acc = {0.0, 0.0};
         for (int64_t f = e + 1; f < m; ++f) {
-            if (!edge_pair_crossing(ix, iy, src[e], dst[e], src[f], dst[f])) continue;
-            nsum_add(&acc, fabs(ideal_angle - crossing_angle(ix, iy, src[e], dst[e], src[f], dst[f])) /
+            int r = edge_pair_crossing(&E[e], &E[f]);
+            if (!r) continue;
+            nsum_add(&acc, fabs(ideal_angle - crossing_angle(&E[e], &E[f])) /
                                ideal_angle);
             count += 1;
+            proper += (r == 2);
         }
         row_sum[e - r0] = nsum_get(&acc);
     }
     nsum tot = {0.0, 0.0};
     for (int64_t i = 0; i < k; ++i) nsum_add(&tot, row_sum[i]);
-    free(row_sum); free(ix); free(iy);
+    free(row_sum); free(E); free(ix); free(iy);
     *out_count = count;
+    if (out_proper) *out_proper = proper;
     if (out_dev_sum) *out_dev_sum = nsum_get(&tot);
     return 0;
 }

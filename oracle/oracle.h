@@ -39,7 +39,8 @@ int oracle_loss_grad(const double *x, const double *y, int64_t n, const int32_t 
 int oracle_crossing_angle_rows(const double *x, const double *y, int64_t n,
                                const int32_t *src, const int32_t *dst, int64_t m,
                                double ideal_angle, int64_t r0, int64_t r1,
-                               uint64_t *out_count, double *out_dev_sum);
+                               uint64_t *out_count, uint64_t *out_proper,
+                               double *out_dev_sum);
 int oracle_node_occlusion_rows(const double *x, const double *y, int64_t n, double diameter,
                                int64_t r0, int64_t r1, uint64_t *out_count);
 int oracle_enhanced_crossing(const double *x, const double *y, int64_t n,

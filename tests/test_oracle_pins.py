@@ -176,17 +176,21 @@ def test_row_slices_match_rational_brute_force(orc):
         s, d = gen.distinct_random_edges(rng, n, m)
         pts = [(int(a), int(b)) for a, b in zip(x, y)]
         r0, r1 = sorted(int(v) for v in rng.integers(0, m + 1, size=2))
-        cnt = 0
+        cnt = prop = 0
         dev = 0.0
         for e in range(r0, r1):
             for f in range(e + 1, m):
                 if {int(s[e]), int(d[e])} & {int(s[f]), int(d[f])}:
                     continue
-                if rational_segment_relation(pts[s[e]], pts[d[e]], pts[s[f]], pts[d[f]]):
+                rel = rational_segment_relation(pts[s[e]], pts[d[e]], pts[s[f]], pts[d[f]])
+                if rel:
                     cnt += 1
+                    prop += rel == 2
                     dev += abs(IDEAL - acos_angle(pts[s[e]], pts[d[e]], pts[s[f]], pts[d[f]])) / IDEAL
         c2, dev2 = orc.crossing_angle_rows(x, y, s, d, IDEAL, r0, r1)
         assert c2 == cnt and abs(dev2 - dev) < 1e-7
+        c3, p3, dev3 = orc.crossing_angle_rows(x, y, s, d, IDEAL, r0, r1, proper=True)
+        assert (c3, p3, dev3) == (c2, prop, dev2)
         diam = float(rng.choice([1.0, 1.5, 2.0, 2.9]))
         q0, q1 = sorted(int(v) for v in rng.integers(0, n + 1, size=2))
         occ = sum(1 for u in range(q0, q1) for v in range(u + 1, n)
@@ -199,6 +203,9 @@ def test_row_slices_match_rational_brute_force(orc):
              for a, b in zip(cuts, cuts[1:])]
     assert sum(p[0] for p in parts) == full[1]
     assert sum(p[1] for p in parts) == pytest.approx(full[2], rel=1e-12)
+    parts = [orc.crossing_angle_rows(L.x, L.y, L.src, L.dst, IDEAL, a, b, proper=True)
+             for a, b in zip(cuts, cuts[1:])]
+    assert sum(p[1] for p in parts) == orc.edge_crossing(L.x, L.y, L.src, L.dst)[1]
     cuts = [0, 5, 1500, 3000]
     assert sum(orc.node_occlusion_rows(L.x, L.y, 40.0, a, b)
                for a, b in zip(cuts, cuts[1:])) == orc.node_occlusion(L.x, L.y, 40.0)
