@@ -64,9 +64,23 @@ class CrossingAngleLengthLoss(torch.autograd.Function):
                 None, None, None)
 
 
+def descent_step(mx, my, gx, gy, step_size: float):
+    """One step of ``descend`` in place: the master coordinates move by
+    ``step_size`` grid units along -g / max|g|; a zero gradient (a layout at
+    a stationary point, e.g. no crossings and equal edge lengths) leaves them
+    where they are.  No host synchronisation."""
+    if gx.numel() == 0:
+        return
+    scale = torch.maximum(gx.abs().max(), gy.abs().max())
+    step = torch.where(scale > 0, step_size / scale, 0.0)   # 1/0 = inf is not selected
+    mx -= gx * step
+    my -= gy * step
+
+
 def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
             extent: int = 1 << 16, ideal_angle: float = IDEAL_ANGLE, w_angle: float = 1.0,
-            w_length: float = 1.0, log=None, pruned: bool = False, w_min_angle: float = 0.0):
+            w_length: float = 1.0, log=None, pruned: bool = False, w_min_angle: float = 0.0,
+            trace: list | None = None):
     """Gradient descent on the readability loss.
 
     A float32 master copy of the coordinates moves by ``step_size`` grid
@@ -75,7 +89,9 @@ def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
     [0, extent).  Returns (x, y, history) with history = list of
     (loss, crossings, seconds) per step, seconds being the step's GPU time.
     The steps are enqueued without waiting for the GPU unless ``log`` is
-    given (it is called with each step's entry as soon as it is known)."""
+    given (it is called with each step's entry as soon as it is known).
+    With ``trace`` (a list), each step's evaluated integer layout is appended
+    to it as a pair of device tensors."""
     mx = x.detach().clone().to(torch.float32)
     my = y.detach().clone().to(torch.float32)
     marks = [torch.cuda.Event(enable_timing=True)]
@@ -88,13 +104,13 @@ def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
                                                   w_length, pruned, w_min_angle)
         loss.backward()
         with torch.no_grad():
-            scale = torch.maximum(xi.grad.abs().max(), yi.grad.abs().max()).clamp_min(1e-300)
-            mx -= step_size * xi.grad / scale
-            my -= step_size * yi.grad / scale
+            descent_step(mx, my, xi.grad, yi.grad, step_size)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         marks.append(ev)
         vals.append((loss.detach(), cnt))
+        if trace is not None:
+            trace.append((xi.detach(), yi.detach()))
         if log:
             ev.synchronize()
             hist.append((float(loss), int(cnt), marks[-2].elapsed_time(ev) * 1e-3))
