@@ -267,7 +267,11 @@ rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes,
  * fastest in the plan and the tuning table, re-uploads; it synchronises.
  * rb_batch_graph_create captures rb_batch_evaluate with these arguments into
  * a hipGraph (on a private stream); rb_graph_launch replays it on `stream`.
- * The graph reuses the given pointers: keep them valid while it is used. */
+ * The graph reuses the given pointers: keep them valid while it is used.
+ * A graph records the plan it was captured from: a later rb_batch_upload or
+ * rb_batch_autotune of that batch rewrites the plan's tables (possibly for
+ * another sweep variant), after which rb_graph_launch returns RB_EINVAL
+ * and the graph must be captured again.  Destroy graphs before their batch. */
 typedef struct rb_batch rb_batch;
 typedef struct rb_graph rb_graph;
 rb_status rb_batch_create(int64_t n_layouts, const int64_t *node_off, const int64_t *edge_off,

@@ -34,6 +34,10 @@ struct rb_batch {
            o_ang = 0, o_dv = 0, o_big = 0, o_sc = 0, total = 0;
     int64_t n_nodes = 0, n_edges = 0;
     const void *uploaded = nullptr;               // workspace holding the current tables
+    // incremented by every upload (rb_batch_upload, rb_batch_autotune): a
+    // graph captured under another generation walks tables that no longer
+    // match the kernels and grid it recorded, and is refused
+    uint64_t plan_gen = 0;
     // second stream (default priority) for the metrics that overlap the edge
     // sweep, and the fork / join events; made on first use, on the device of
     // that call
@@ -50,6 +54,8 @@ struct rb_batch {
 struct rb_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    const rb_batch *batch = nullptr;              // the plan it was captured from ...
+    uint64_t plan_gen = 0;                        // ... and that plan's generation
 };
 
 namespace rb {
@@ -484,6 +490,7 @@ hipError_t upload(rb_batch *b, void *ws, hipStream_t st) {
     b->cross_grid_n = (int)std::min<int64_t>(cu, cross_grid(b->cross_var, true));
     b->occl_grid_n = (int)std::min<int64_t>(ou, occl_grid(b->occl_var));
     b->uploaded = ws;
+    ++b->plan_gen;
     return hipSuccess;
 }
 
@@ -688,6 +695,8 @@ rb_status rb_batch_graph_create(const rb_batch *b, const float *x, const float *
     rb_graph *g = new rb_graph;
     g->graph = graph;
     g->exec = exec;
+    g->batch = b;
+    g->plan_gen = b->plan_gen;
     *out = g;
     return RB_OK;
 }
@@ -695,6 +704,11 @@ rb_status rb_batch_graph_create(const rb_batch *b, const float *x, const float *
 rb_status rb_graph_launch(rb_graph *g, void *stream) {
     clear_error();
     if (!g) return (rb_status)set_error(RB_EINVAL, "graph is NULL");
+    if (g->batch->plan_gen != g->plan_gen)
+        return (rb_status)set_error(RB_EINVAL,
+                                    "the batch plan was uploaded again (rb_batch_upload or "
+                                    "rb_batch_autotune) after this graph was captured: "
+                                    "capture a new graph");
     hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
     if (e != hipSuccess) return (rb_status)hip_error(e, "rb_graph_launch");
     return RB_OK;

@@ -116,6 +116,34 @@ def test_graph_replay_matches_eager(torch_mod):
     B.release_graph()
 
 
+def test_graph_is_refused_after_the_plan_is_uploaded_again(torch_mod):
+    """A re-upload (here directly through the C ABI, as rb_batch_autotune
+    also does) may rewrite the unit tables for another sweep variant; the
+    graph captured before must not replay over them."""
+    from paper_2411_09809_amd import _lib
+    from paper_2411_09809_amd.batch import Batch
+    layouts = mixed_layouts(seed=4)
+    B = Batch(layouts)
+    B.evaluate()
+    eager = B.results()
+    B.capture()
+    B.replay()
+    torch_mod.cuda.synchronize()
+    B._upload()
+    with pytest.raises(_lib.RBError) as err:
+        B.replay()
+    assert err.value.status == _lib.RB_EINVAL and "capture a new graph" in str(err.value)
+    B.capture()
+    for t in (B.out_occlusion, B.out_crossings):
+        t.fill_(-7)
+    B.replay()
+    torch_mod.cuda.synchronize()
+    R = B.results()
+    for k in eager:
+        np.testing.assert_array_equal(R[k], eager[k], err_msg=k)
+    B.release_graph()
+
+
 def test_batch_of_512_uneven_layouts(torch_mod):
     """The 512-layout workload (|V| log-uniform in [200, 20000], |E| =
     U[1.5,4]|V|, coords in [0,2^16)^2): all layouts against single calls,
