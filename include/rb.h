@@ -106,6 +106,24 @@ rb_status rb_crossing_angle(const float *x, const float *y, int64_t n_nodes,
                             uint64_t *out_count, double *out_dev_sum,
                             void *ws, size_t ws_bytes, void *stream);
 
+/* rb_crossing_angle without a workspace, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments and results as rb_crossing_angle
+ * (identical kernels, so identical outputs), minus ws / ws_bytes: the edge
+ * records and the sweep's partial slots live in a static device array of
+ * the library, about 68 MB, which each device that runs this call holds
+ * from its first call until the process ends (its address is looked up
+ * once per device; `stream` must belong to the current device).  It calls
+ * no allocator.  n_edges <= 1,000,000, else RB_EINVAL before anything is
+ * enqueued.  All calls on one device share that array, and every call
+ * rewrites all of it that it reads, so calls whose work overlaps in time on
+ * one device (two streams, two host threads) race and give undefined
+ * results; calls ordered on one stream are safe.                          */
+rb_status rb_crossing_angle_noalloc(const float *x, const float *y, int64_t n_nodes,
+                                    const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                    double ideal_angle, double *out_metric,
+                                    uint64_t *out_count, double *out_dev_sum, void *stream);
+
 /* Grid-pruned exact paths.  They return exactly what the brute-force calls
  * return (integer counts bit for bit) while skipping pairs that cannot
  * count, and they use their own workspace: rb_grid_workspace_size(V, E)

@@ -35,6 +35,8 @@ _SIGS = {
     "rb_edge_crossing": ([_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp], C.c_int),
     "rb_crossing_angle": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _vp, _vp, _vp, _vp, _sz, _vp],
                           C.c_int),
+    "rb_crossing_angle_noalloc": ([_vp, _vp, _i64, _vp, _vp, _i64, _f64, _vp, _vp, _vp, _vp],
+                                  C.c_int),
     "rb_min_angle": ([_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp], C.c_int),
     "rb_edge_length_variation": ([_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp],
                                  C.c_int),

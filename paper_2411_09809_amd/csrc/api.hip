@@ -249,6 +249,13 @@ rb_status rb_node_occlusion(const float *x, const float *y, int64_t n_nodes, dou
     return RB_OK;
 }
 
+static rb_status crossing_launch(const float *x, const float *y, int64_t n_nodes,
+                                 const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                 bool angle, double ideal, uint64_t *out_count,
+                                 uint64_t *out_proper, double *out_metric, double *out_dev_sum,
+                                 EdgeRec *rec, int64_t n_edge_pad, CrossPartial *part,
+                                 hipStream_t st);
+
 static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes,
                                  const int32_t *src, const int32_t *dst, int64_t n_edges,
                                  bool angle, double ideal, uint64_t *out_count,
@@ -258,10 +265,20 @@ static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes
     if (s) return s;
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
-    hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
-    EdgeRec *rec = (EdgeRec *)(w + L.edge_rec);
-    CrossPartial *part = (CrossPartial *)(w + L.partial);
+    return crossing_launch(x, y, n_nodes, src, dst, n_edges, angle, ideal, out_count, out_proper,
+                           out_metric, out_dev_sum, (EdgeRec *)(w + L.edge_rec), L.n_edge_pad,
+                           (CrossPartial *)(w + L.partial), (hipStream_t)stream);
+}
+
+// Edge preparation, the all-pairs sweep and its finalize into caller-chosen
+// record (n_edge_pad entries) and partial-slot (kMaxPartials) buffers.
+static rb_status crossing_launch(const float *x, const float *y, int64_t n_nodes,
+                                 const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                 bool angle, double ideal, uint64_t *out_count,
+                                 uint64_t *out_proper, double *out_metric, double *out_dev_sum,
+                                 EdgeRec *rec, int64_t n_edge_pad, CrossPartial *part,
+                                 hipStream_t st) {
     const int v = tuned_variant(angle ? 1 : 0, false, n_edges);
     const int rows = cross_variant(v).rows;
     SweepArgs a;
@@ -271,7 +288,7 @@ static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes
     a.n_units = sweep_units(n_edges, rows);
     a.unit_base = 0;
     const int grid = (int)std::min<int64_t>(a.n_units, cross_grid(v, angle));
-    hipError_t e = launch_edge_prep(x, y, src, dst, n_nodes, n_edges, L.n_edge_pad, rec, st);
+    hipError_t e = launch_edge_prep(x, y, src, dst, n_nodes, n_edges, n_edge_pad, rec, st);
     if (e != hipSuccess) return hip_fail(e, "edge_prep launch");
     TimedLaunch tl(0, st);
     e = launch_cross_sweep(v, angle, rec, a, grid, ideal, part, st);
@@ -480,6 +497,73 @@ rb_status rb_crossing_angle(const float *x, const float *y, int64_t n_nodes, con
         return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
     return crossing_common(x, y, n_nodes, src, dst, n_edges, true, ideal_angle, out_count,
                            nullptr, out_metric, out_dev_sum, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free variant
+// rb_crossing_angle_noalloc keeps the edge records and the sweep's partial
+// slots in this file-scope device array instead of a caller workspace.  In
+// host code the array's name only stands in for the symbol: kernels get the
+// device address that hipGetSymbolAddress returns, looked up once per device.
+namespace rb {
+
+constexpr int64_t kNoAllocMaxEdges = 1000000;
+constexpr int64_t kNoAllocEdgePad = (kNoAllocMaxEdges + kRecPad - 1) / kRecPad * kRecPad;
+constexpr size_t kNoAllocRecBytes = sizeof(EdgeRec) * (size_t)kNoAllocEdgePad;
+constexpr size_t kNoAllocBytes = kNoAllocRecBytes + sizeof(CrossPartial) * (size_t)kMaxPartials;
+static_assert(kNoAllocRecBytes % 256 == 0, "the partial slots start 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[64];
+
+// Device address of `scratch` on the current device.
+rb_status scratch_address(char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(RB_EINVAL, "device %d: only devices 0..63", dev);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p & 255u) != 0)
+            return fail(RB_EHIP, "static scratch is not 256-byte aligned");
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RB_OK;
+}
+
+}  // namespace
+}  // namespace rb
+
+extern "C" {
+
+rb_status rb_crossing_angle_noalloc(const float *x, const float *y, int64_t n_nodes,
+                                    const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                    double ideal_angle, double *out_metric, uint64_t *out_count,
+                                    double *out_dev_sum, void *stream) {
+    g_err.clear();
+    if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
+    if (!(ideal_angle > 0.0) || !(ideal_angle <= 1.5707963267948966))
+        return fail(RB_EINVAL, "ideal_angle must be in (0, pi/2]");
+    rb_status s = check_layout(x, y, n_nodes, src, dst, n_edges);
+    if (s) return s;
+    if (n_edges > kNoAllocMaxEdges)
+        return fail(RB_EINVAL, "n_edges = %lld exceeds the %lld edges the static scratch holds",
+                    (long long)n_edges, (long long)kNoAllocMaxEdges);
+    char *w = nullptr;
+    if ((s = scratch_address(&w))) return s;
+    const int64_t pad = (int64_t)round_up((size_t)std::max<int64_t>(n_edges, 1), kRecPad);
+    return crossing_launch(x, y, n_nodes, src, dst, n_edges, true, ideal_angle, out_count,
+                           nullptr, out_metric, out_dev_sum, (EdgeRec *)w, pad,
+                           (CrossPartial *)(w + kNoAllocRecBytes), (hipStream_t)stream);
 }
 
 rb_status rb_min_angle(const float *x, const float *y, int64_t n_nodes, const int32_t *src,

@@ -144,6 +144,29 @@ def crossing_angle(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, *, async_: 
     return float(vals[0]), int(vals.view(torch.int64)[1]), float(vals[2])
 
 
+def crossing_angle_noalloc(x, y, src, dst, ideal_angle: float = IDEAL_ANGLE, *, out=None,
+                           async_: bool = False):
+    """``crossing_angle`` through the entry point that uses the library's
+    static device scratch instead of a workspace (at most 1,000,000 edges).
+    ``out`` (float64[3] on the layout's device) may be given so that the
+    call allocates nothing; calls overlapping on one device race."""
+    _check_coords(x, y)
+    _check_edges(x, src, dst)
+    if out is None:
+        out = _out(3, torch.float64, x.device)
+    elif not (out.dtype == torch.float64 and out.numel() >= 3 and out.device == x.device
+              and out.is_contiguous()):
+        raise ValueError("out must be a contiguous float64 tensor of 3 entries on x's device")
+    p = _ptr(out)
+    check(lib().rb_crossing_angle_noalloc(_ptr(x), _ptr(y), x.numel(), _ptr(src), _ptr(dst),
+                                          src.numel(), float(ideal_angle), p, p + 8, p + 16,
+                                          _stream(x.device)), "rb_crossing_angle_noalloc")
+    if async_:
+        return out
+    vals = out.cpu()
+    return float(vals[0]), int(vals.view(torch.int64)[1]), float(vals[2])
+
+
 def min_angle(x, y, src, dst, *, async_: bool = False):
     """(M_a, sum of d_v, nodes of degree >= 1) (Algorithm 2)."""
     _check_coords(x, y)

@@ -166,3 +166,16 @@ def test_built_in_tuning_defaults(L, tmp_path):
     assert q(2, 50_000) == (4, 6) and q(2, (1 << 19) - 1) == (4, 6)
     assert q(2, 1 << 19) == (8, 4) and q(2, 1_000_000) == (8, 4)
     assert q(3, (1 << 17) - 1) == (1, 8) and q(3, 1 << 17) == (2, 7)
+
+
+def test_static_scratch_limit_needs_no_gpu(L):
+    fake = 0x1000                     # never dereferenced: checks fail first
+    assert L.rb_crossing_angle_noalloc(fake, fake, 10, fake, fake, 1_000_001, 1.2, fake, None,
+                                       None, None) == _lib.RB_EINVAL
+    assert "static scratch" in _err(L)
+    assert L.rb_crossing_angle_noalloc(fake, fake, 10, fake, fake, 5, 1.2, None, None, None,
+                                       None) == _lib.RB_EINVAL
+    assert "out_metric" in _err(L)
+    assert L.rb_crossing_angle_noalloc(fake, fake, 10, fake, fake, 5, 0.0, fake, None, None,
+                                       None) == _lib.RB_EINVAL
+
