@@ -692,12 +692,45 @@ int oracle_enhanced_crossing(const double *x, const double *y, int64_t n,
  * and a direction alpha of v -> u turns with u as (-dy, dx) / l^2 (and with v
  * as the opposite).  Kinks contribute 0: a smallest gap attained twice, a
  * zero gap (two edges in one direction) or a zero-length edge bounding it.
- * The gradient (if gx, gy are given) is added to gx, gy. */
-typedef struct { double a; int32_t u; } dir_t;
+ * The gradient (if gx, gy are given) is added to gx, gy.
+ *
+ * Which gap is smallest, and whether it is attained twice, is decided
+ * exactly when every coordinate is an integer with |c| <= 2^20 (the domain
+ * of the library): the gap from direction p to the next direction q is the
+ * angle of the rotation taking p to q, the argument in [0, 2 pi) of
+ * z = (p . q, p x q), and two such arguments are compared by the half plane
+ * of z and the sign of the 128-bit cross product of the two z (no rounding;
+ * gaps that are equal as real numbers, e.g. to (2,1), (1,1), (1,2), tie).
+ * A zero-length edge points along +x (R10: atan2(0, 0) = 0).  At other
+ * coordinates (the finite-difference pins jitter the layout off the
+ * integers, where exact ties do not occur) the gaps are compared as the
+ * differences of the sorted double angles. */
+typedef struct { double a; int32_t u; int64_t dx, dy; } dir_t;
 
 static int cmp_dir(const void *p, const void *q) {
     double a = ((const dir_t *)p)->a, b = ((const dir_t *)q)->a;
     return (a > b) - (a < b);
+}
+
+typedef struct { int64_t dot, cr; } gapz_t;   /* p . q and p x q */
+
+static gapz_t gap_between(const dir_t *p, const dir_t *q) {
+    int64_t px = p->dx, py = p->dy, qx = q->dx, qy = q->dy;
+    if (px == 0 && py == 0) px = 1;            /* R10: direction 0 */
+    if (qx == 0 && qy == 0) qx = 1;
+    gapz_t z = {px * qx + py * qy, px * qy - py * qx};
+    return z;
+}
+
+/* 0 for an argument in [0, pi), 1 for [pi, 2 pi) (z is never 0) */
+static int gap_half(gapz_t z) { return (z.cr > 0 || (z.cr == 0 && z.dot > 0)) ? 0 : 1; }
+
+/* sign of arg(a) - arg(b), both in [0, 2 pi) */
+static int gap_cmp(gapz_t a, gapz_t b) {
+    int ha = gap_half(a), hb = gap_half(b);
+    if (ha != hb) return ha < hb ? -1 : 1;
+    __int128 c = (__int128)a.dot * b.cr - (__int128)a.cr * b.dot;   /* a x b */
+    return c > 0 ? -1 : (c < 0 ? 1 : 0);
 }
 
 int oracle_min_angle_term(const double *x, const double *y, int64_t n, const int32_t *src,
@@ -718,6 +751,8 @@ int oracle_min_angle_term(const double *x, const double *y, int64_t n, const int
     }
     int64_t used = 0;
     for (int64_t v = 0; v < n; ++v) used += deg[v] > 0;
+    int64_t *ix = NULL, *iy = NULL;
+    const int exact = to_int_coords(x, y, n, &ix, &iy) == 0;   /* integer layout */
     nsum tot = {0.0, 0.0};
     dir_t *dir = (dir_t *)malloc(sizeof(dir_t) * (size_t)(2 * m + 1));
     for (int64_t v = 0; v < n; ++v) {
@@ -729,21 +764,36 @@ int oracle_min_angle_term(const double *x, const double *y, int64_t n, const int
             if (a < 0.0) a += two_pi;                                  /* R10 */
             dir[i].a = a;
             dir[i].u = u;
+            dir[i].dx = exact ? ix[u] - ix[v] : 0;
+            dir[i].dy = exact ? iy[u] - iy[v] : 0;
         }
         qsort(dir, (size_t)k, sizeof(dir_t), cmp_dir);
         /* gaps: dir[i] -> dir[i+1], and the wrap dir[k-1] -> dir[0] */
-        double phi = two_pi;
-        int64_t at = -1, ties = 0;
+        double phi = two_pi;                             /* the metric's phi_v */
+        int64_t at = -1, ties = 0;                       /* the gradient's gap */
+        int zero_gap = 0;
         if (k >= 2) {
+            double best_g = two_pi;
+            gapz_t best_z = {0, 0};
             for (int64_t i = 0; i < k; ++i) {
                 const double g = i + 1 < k ? dir[i + 1].a - dir[i].a
                                            : two_pi - dir[k - 1].a + dir[0].a;
-                if (g < phi) { phi = g; at = i; ties = 1; }
-                else if (g == phi) ties++;
+                if (g < phi) phi = g;
+                int c;
+                if (exact) {
+                    const gapz_t z = gap_between(&dir[i], &dir[i + 1 < k ? i + 1 : 0]);
+                    c = at < 0 ? -1 : gap_cmp(z, best_z);
+                    if (c < 0) best_z = z;
+                } else {
+                    c = (at < 0 || g < best_g) ? -1 : (g == best_g ? 0 : 1);
+                }
+                if (c < 0) { best_g = g; at = i; ties = 1; }
+                else if (c == 0) ties++;
             }
+            zero_gap = exact ? (best_z.cr == 0 && best_z.dot > 0) : !(best_g > 0.0);
         }
         nsum_add(&tot, phi * (double)k / two_pi);
-        if (!gx || !gy || k < 2 || ties != 1 || !(phi > 0.0)) continue;
+        if (!gx || !gy || k < 2 || ties != 1 || zero_gap) continue;
         const double c = -w_m * (double)k / (two_pi * (double)used);   /* dT / d phi_v */
         const dir_t p = dir[at], q = dir[at + 1 < k ? at + 1 : 0];
         const double pdx = x[p.u] - x[v], pdy = y[p.u] - y[v];
@@ -757,6 +807,7 @@ int oracle_min_angle_term(const double *x, const double *y, int64_t n, const int
         gx[v] += c * -pdy / pl2;    gy[v] += c * pdx / pl2;
     }
     *out_term = used ? w_m * (1.0 - nsum_get(&tot) / (double)used) : 0.0;
+    if (exact) { free(ix); free(iy); }
     free(dir); free(deg); free(start); free(fill); free(nbr);
     return 0;
 }

@@ -314,8 +314,9 @@ __global__ __launch_bounds__(256) void min_angle_big_kernel(
 // dT/dphi_v = -w_m deg_v / (2 pi N); a direction of v -> u turns as
 // (-dy, dx) / l^2 with u (and the opposite with v).  A vertex contributes only
 // if its smallest gap is attained once, is nonzero and both bounding edges
-// have nonzero length (the kinks contribute 0).  Gaps are formed exactly as
-// in the sorted sweep of Algorithm 2: a_next - a, and (2 pi - a_last) + a_first.
+// have nonzero length (the kinks contribute 0).  The gaps are those of the
+// sorted sweep of Algorithm 2: from each direction to the next, and from the
+// last to the first.
 
 __device__ __forceinline__ void ma_scatter(const float *x, const float *y, int32_t v, int32_t up,
                                            int32_t uq, double c, double *gx, double *gy) {
@@ -332,6 +333,47 @@ __device__ __forceinline__ void ma_scatter(const float *x, const float *y, int32
     atomicAdd(&gy[up], -py);
     atomicAdd(&gx[v], px - qx);
     atomicAdd(&gy[v], py - qy);
+}
+
+// Which gap is smallest, and whether it is attained more than once, is
+// decided exactly on the integer directions (the angles only order them:
+// distinct integer directions below 2^21 differ in angle by far more than
+// the rounding of atan2).  The gap from direction p to the next direction q
+// is the angle of the rotation taking p to q: the argument, in [0, 2 pi), of
+// z = (p . q, p x q), whose parts are integers below 2^44.  Two arguments are
+// compared by the half plane of z and then the sign of the cross product of
+// the two z in 128-bit integers.  A zero-length edge points along +x (its
+// angle is atan2(0, 0) = 0).
+struct GapZ {
+    long long dot, cr;
+};
+
+__device__ __forceinline__ GapZ gap_z(long long px, long long py, long long qx, long long qy) {
+    if (px == 0 && py == 0) px = 1;
+    if (qx == 0 && qy == 0) qx = 1;
+    return {px * qx + py * qy, px * qy - py * qx};
+}
+
+// 0 for an argument in [0, pi), 1 for [pi, 2 pi)
+__device__ __forceinline__ int gap_half(GapZ z) {
+    return (z.cr > 0 || (z.cr == 0 && z.dot > 0)) ? 0 : 1;
+}
+
+// sign of arg(a) - arg(b)
+__device__ __forceinline__ int gap_cmp(GapZ a, GapZ b) {
+    const int ha = gap_half(a), hb = gap_half(b);
+    if (ha != hb) return ha < hb ? -1 : 1;
+    const __int128 c = (__int128)a.dot * b.cr - (__int128)a.cr * b.dot;
+    return c > 0 ? -1 : (c < 0 ? 1 : 0);
+}
+
+__device__ __forceinline__ bool gap_is_zero(GapZ z) { return z.cr == 0 && z.dot > 0; }
+
+// integer direction v -> u (coordinates are integers, |c| <= 2^20)
+__device__ __forceinline__ void int_dir(const float *x, const float *y, int32_t v, int32_t u,
+                                        long long *dx, long long *dy) {
+    *dx = (long long)(x[u] - x[v]);
+    *dy = (long long)(y[u] - y[v]);
 }
 
 // degree 2 .. kSmallDeg: one thread per vertex.  Directions are taken in
@@ -355,28 +397,41 @@ __global__ __launch_bounds__(256) void ma_grad_small_kernel(
         }
         const uint32_t o = offs[v];
         double a[kSmallDeg];
+        int32_t ex[kSmallDeg], ey[kSmallDeg];
 #pragma unroll
-        for (int i = 0; i < kSmallDeg; ++i) a[i] = (uint32_t)i < d ? ang[o + i] : 0.0;
-        // first and last directions in (angle, slot) order
-        double alo = a[0], ahi = a[0];
-        int lo = 0;
-#pragma unroll
-        for (int i = 1; i < kSmallDeg; ++i) {
+        for (int i = 0; i < kSmallDeg; ++i) {
+            a[i] = 0.0;
+            ex[i] = 0;
+            ey[i] = 0;
             if ((uint32_t)i < d) {
-                if (a[i] < alo) {
-                    alo = a[i];
-                    lo = i;
-                }
-                if (a[i] >= ahi) ahi = a[i];
+                a[i] = ang[o + i];
+                long long dx, dy;
+                int_dir(x, y, (int32_t)v, nbr[o + i], &dx, &dy);
+                ex[i] = (int32_t)dx;
+                ey[i] = (int32_t)dy;
             }
         }
-        double phi = kTwoPi;
+        // first direction in (angle, slot) order
+        double alo = a[0];
+        int lo = 0;
+        int32_t lox = ex[0], loy = ey[0];
+#pragma unroll
+        for (int i = 1; i < kSmallDeg; ++i) {
+            if ((uint32_t)i < d && a[i] < alo) {
+                alo = a[i];
+                lo = i;
+                lox = ex[i];
+                loy = ey[i];
+            }
+        }
+        GapZ best = {0, 0};
         int at_p = -1, at_q = -1, ties = 0;
 #pragma unroll
         for (int i = 0; i < kSmallDeg; ++i) {
             if ((uint32_t)i >= d) continue;
             int nx = -1;                     // successor of (a_i, i)
             double an = 0.0;
+            int32_t nqx = 0, nqy = 0;
 #pragma unroll
             for (int j = 0; j < kSmallDeg; ++j) {
                 if ((uint32_t)j >= d || j == i) continue;
@@ -384,20 +439,27 @@ __global__ __launch_bounds__(256) void ma_grad_small_kernel(
                 if (after && (nx < 0 || a[j] < an)) {
                     nx = j;
                     an = a[j];
+                    nqx = ex[j];
+                    nqy = ey[j];
                 }
             }
-            const double g = nx >= 0 ? an - a[i] : (kTwoPi - ahi) + alo;
-            if (nx < 0) nx = lo;
-            if (g < phi) {
-                phi = g;
+            if (nx < 0) {                    // the wrap gap to the first direction
+                nx = lo;
+                nqx = lox;
+                nqy = loy;
+            }
+            const GapZ z = gap_z(ex[i], ey[i], nqx, nqy);
+            const int c = at_p < 0 ? -1 : gap_cmp(z, best);
+            if (c < 0) {
+                best = z;
                 at_p = i;
                 at_q = nx;
                 ties = 1;
-            } else if (g == phi) {
+            } else if (c == 0) {
                 ++ties;
             }
         }
-        if (ties != 1 || !(phi > 0.0)) continue;
+        if (ties != 1 || gap_is_zero(best)) continue;
         ma_scatter(x, y, (int32_t)v, nbr[o + at_p], nbr[o + at_q], c0 * (double)d, gx, gy);
     }
 }
@@ -442,7 +504,7 @@ __global__ __launch_bounds__(256) void ma_grad_big_kernel(
     const unsigned long long *__restrict__ n_used, double *gx, double *gy) {
     __shared__ double sa[kLdsDeg];
     __shared__ int32_t sp[kLdsDeg];
-    __shared__ double rv[256];
+    __shared__ long long rd[256], rc[256];
     __shared__ int32_t ri[256];
     __shared__ uint32_t rt[256];
     const unsigned long long n_big = *big_count, N = *n_used;
@@ -462,40 +524,51 @@ __global__ __launch_bounds__(256) void ma_grad_big_kernel(
         }
         __syncthreads();
         block_sort_pairs(a, p, d);
+        // the gap after sorted direction i, as a rotation
+        auto gap = [&](uint32_t i) {
+            long long px, py, qx, qy;
+            int_dir(x, y, v, p[i], &px, &py);
+            int_dir(x, y, v, p[i + 1 < d ? i + 1 : 0], &qx, &qy);
+            return gap_z(px, py, qx, qy);
+        };
         // smallest gap, its first position, and how many gaps attain it
-        double best = kTwoPi;
+        GapZ best = {0, 0};
         int32_t at = -1;
         for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) {
-            const double g = i + 1 < d ? a[i + 1] - a[i] : (kTwoPi - a[d - 1]) + a[0];
-            if (g < best) { best = g; at = (int32_t)i; }
+            const GapZ z = gap(i);
+            if (at < 0 || gap_cmp(z, best) < 0) {
+                best = z;
+                at = (int32_t)i;
+            }
         }
-        rv[threadIdx.x] = best;
+        rd[threadIdx.x] = best.dot;
+        rc[threadIdx.x] = best.cr;
         ri[threadIdx.x] = at;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
             if (threadIdx.x < s) {
-                const double o = rv[threadIdx.x + s];
-                if (o < rv[threadIdx.x]) {
-                    rv[threadIdx.x] = o;
-                    ri[threadIdx.x] = ri[threadIdx.x + s];
+                const int32_t oi = ri[threadIdx.x + s];
+                const GapZ o = {rd[threadIdx.x + s], rc[threadIdx.x + s]};
+                const GapZ m = {rd[threadIdx.x], rc[threadIdx.x]};
+                if (oi >= 0 && (ri[threadIdx.x] < 0 || gap_cmp(o, m) < 0)) {
+                    rd[threadIdx.x] = o.dot;
+                    rc[threadIdx.x] = o.cr;
+                    ri[threadIdx.x] = oi;
                 }
             }
             __syncthreads();
         }
-        const double phi = rv[0];
+        const GapZ phi = {rd[0], rc[0]};
         const int32_t at0 = ri[0];
         uint32_t ties = 0;
-        for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) {
-            const double g = i + 1 < d ? a[i + 1] - a[i] : (kTwoPi - a[d - 1]) + a[0];
-            ties += g == phi ? 1u : 0u;
-        }
+        for (uint32_t i = threadIdx.x; i < d; i += blockDim.x) ties += gap_cmp(gap(i), phi) == 0;
         rt[threadIdx.x] = ties;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
             if (threadIdx.x < s) rt[threadIdx.x] += rt[threadIdx.x + s];
             __syncthreads();
         }
-        if (threadIdx.x == 0 && rt[0] == 1 && phi > 0.0 && at0 >= 0) {
+        if (threadIdx.x == 0 && rt[0] == 1 && !gap_is_zero(phi) && at0 >= 0) {
             const uint32_t q = (uint32_t)at0 + 1 < d ? (uint32_t)at0 + 1 : 0u;
             ma_scatter(x, y, v, p[at0], p[q], c0 * (double)d, gx, gy);
         }

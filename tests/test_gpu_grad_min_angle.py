@@ -159,6 +159,46 @@ def test_kinks_contribute_zero(torch_mod):
         assert (gx == 0).all() and (gy == 0).all()
 
 
+def _mirror_star(hub, pair, ring, radius, a0, a1):
+    """A hub with neighbours in directions pair[0], (1,1), pair[1] (mirror
+    images across the diagonal, so the two gaps between them are equal as
+    real numbers) and `ring` more on a circle between angles a0 and a1."""
+    dirs = [pair[0], (1, 1), pair[1]]
+    for t in np.linspace(a0, a1, ring):
+        dirs.append((int(round(radius * np.cos(t))), int(round(radius * np.sin(t)))))
+    x = np.array([hub[0]] + [hub[0] + dx for dx, _ in dirs], dtype=np.float64)
+    y = np.array([hub[1]] + [hub[1] + dy for _, dy in dirs], dtype=np.float64)
+    k = len(dirs)
+    return x, y, np.zeros(k, np.int64), np.arange(1, k + 1)
+
+
+@pytest.mark.parametrize("shape", [
+    ("thread", (0, 0), ((2, 1), (1, 2)), 0, 1, 0.0, 0.0),
+    ("thread", (50, 60), ((7, 3), (3, 7)), 5, 30, 1.8, 6.0),
+    ("lds", (1 << 12, 1 << 12), ((20, 19), (19, 20)), 40, 1000, 1.0, 2 * np.pi - 0.2),
+    ("in-place", (1 << 19, 1 << 19), ((1000, 999), (999, 1000)), 2100, 500000, 1.0,
+     2 * np.pi - 0.2),
+])
+def test_exact_ties_off_the_axes(torch_mod, shape):
+    """A smallest gap attained twice contributes nothing, on each vertex
+    path, also when the two gaps are equal only as real numbers; moving one
+    neighbour of the pair by one unit breaks the tie and the gradient
+    returns, as in the oracle."""
+    path, hub, pair, ring, radius, a0, a1 = shape
+    x, y, src, dst = _mirror_star(hub, pair, ring, radius, a0, a1)
+    L = gen._finish(x, y, src, dst, diameter=1.0, name=f"tie-{path}")
+    for pruned in (False, True):
+        gx_ref, gy_ref = check(L, (0.0, 0.0, 1.0), pruned, f"tie {path}")
+        assert (gx_ref == 0).all() and (gy_ref == 0).all()
+        _, gx, gy, _ = run(L, (0.0, 0.0, 1.0), pruned)
+        assert (gx == 0).all() and (gy == 0).all()
+    y2 = y.copy()
+    y2[3] += 1.0
+    L = gen._finish(x, y2, src, dst, diameter=1.0, name=f"no-tie-{path}")
+    gx_ref, gy_ref = check(L, (0.0, 0.0, 1.0), False, f"broken tie {path}")
+    assert np.abs(gx_ref).max() > 0
+
+
 def _unique_gap_margin(x, y, nbrs, v):
     """(second smallest gap - smallest gap, smallest gap, shortest edge) at v."""
     d = np.array([np.arctan2(y[u] - y[v], x[u] - x[v]) for u in nbrs[v]])

@@ -162,3 +162,71 @@ def test_min_angle_term_rotating_one_edge_closed_form(orc):
         _, gx, gy = orc.min_angle_term(np.array(xs), np.array(ys), np.array([0, 0]),
                                        np.array([1, 2]), 1.0, grad=True)
         assert np.abs(gx).max() == 0.0 and np.abs(gy).max() == 0.0
+
+
+# Two smallest gaps that are equal as real numbers but not as differences of
+# rounded atan2 values: directions (2,1), (1,1), (1,2) from the centre give
+# gaps pi/4 - atan(1/2) and atan(2) - pi/4, equal since atan(2) + atan(1/2) =
+# pi/2.  Likewise (3,1)/(1,1)/(1,3) and (7,3)/(1,1)/(3,7).  A smallest gap
+# attained twice is a kink of the minimum-angle term: no gradient.
+TIE_STARS = [((2, 1), (1, 1), (1, 2)), ((3, 1), (1, 1), (1, 3)), ((7, 3), (1, 1), (3, 7)),
+             ((5, 2), (3, 3), (2, 5))]
+
+
+def _star(dirs, centre=(1000, 2000), turn=0):
+    """Centre node 0 and one neighbour per direction, turned by turn * 90 deg."""
+    xs, ys = [float(centre[0])], [float(centre[1])]
+    for dx, dy in dirs:
+        for _ in range(turn):
+            dx, dy = -dy, dx
+        xs.append(float(centre[0] + dx))
+        ys.append(float(centre[1] + dy))
+    k = len(dirs)
+    return np.array(xs), np.array(ys), np.zeros(k, np.int32), np.arange(1, k + 1, dtype=np.int32)
+
+
+@pytest.mark.parametrize("dirs", TIE_STARS)
+@pytest.mark.parametrize("turn", [0, 1, 2, 3])
+def test_min_angle_exact_ties_off_the_axes_give_no_gradient(orc, dirs, turn):
+    x, y, s, d = _star(dirs, turn=turn)
+    t, gx, gy = orc.min_angle_term(x, y, s, d, 1.0, grad=True)
+    assert np.abs(gx).max() == 0.0 and np.abs(gy).max() == 0.0
+    # the value is still the metric's: phi = the tied gap
+    ma, _, _ = orc.min_angle(x, y, s, d)
+    assert t == pytest.approx(1.0 - ma, rel=1e-12)
+
+
+def test_min_angle_near_tie_moves_only_the_smaller_gap(orc):
+    """(2,1), (1,1), (1,3): gaps pi/4 - atan(1/2) = 0.3218 and
+    atan(3) - pi/4 = 0.4636.  Only the first bounds phi: turning (1,1) about
+    the centre by +dt widens it by dt, turning (2,1) by +dt narrows it, and
+    (1,3) has no gradient.  dT/dphi = -k / (2 pi N) with k = 3, N = 4."""
+    x, y, s, d = _star(((2, 1), (1, 1), (1, 3)))
+    _, gx, gy = orc.min_angle_term(x, y, s, d, 1.0, grad=True)
+    c = -3.0 / (2 * math.pi * 4)
+    turn = lambda i: gx[i] * -(y[i] - y[0]) + gy[i] * (x[i] - x[0])
+    assert turn(2) == pytest.approx(c, rel=1e-12)
+    assert turn(1) == pytest.approx(-c, rel=1e-12)
+    assert gx[3] == 0.0 and gy[3] == 0.0
+    assert gx.sum() == pytest.approx(0.0, abs=1e-15) and gy.sum() == pytest.approx(0.0, abs=1e-15)
+
+
+def test_min_angle_tie_inside_a_layout(orc):
+    """A tie star embedded in a random layout: the centre and its three
+    neighbours get exactly the gradient the rest of the layout gives them
+    (the star's own term is a kink), checked against the same layout with
+    the tie broken by moving one neighbour one unit."""
+    L = gen.uniform_layout(200, 380, extent=1 << 12, seed=9)
+    x, y = L.x.astype(np.float64).copy(), L.y.astype(np.float64).copy()
+    # four fresh nodes far from the others, wired as the (3,1)/(1,1)/(1,3) star
+    sx, sy = [3500.0, 3503.0, 3501.0, 3501.0], [3500.0, 3501.0, 3501.0, 3503.0]
+    n = L.n_nodes
+    x = np.concatenate([x, sx]); y = np.concatenate([y, sy])
+    src = np.concatenate([L.src, [n, n, n]]).astype(np.int32)
+    dst = np.concatenate([L.dst, [n + 1, n + 2, n + 3]]).astype(np.int32)
+    _, gx, gy = orc.min_angle_term(x, y, src, dst, 1.0, grad=True)
+    assert np.abs(gx[n:]).max() == 0.0 and np.abs(gy[n:]).max() == 0.0
+    assert np.abs(gx[:n]).max() > 0.0
+    y2 = y.copy(); y2[n + 3] += 1.0                      # (1,3) -> (1,4): no tie
+    _, gx2, gy2 = orc.min_angle_term(x, y2, src, dst, 1.0, grad=True)
+    assert np.abs(gx2[n:]).max() > 0.0
