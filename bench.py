@@ -4,24 +4,25 @@ One step = one evaluation of all five metrics (node occlusion, crossing
 count + crossing angle, minimum angle, edge length variation) of one layout
 already resident in GPU memory: the edge-pair sweep on the current stream,
 the other metrics on a second stream that overlaps it (``--serial`` runs
-them one after another on one stream).  Default workload: preferential-attachment
-graph, |V| = 50,000, |E| = 149,994, 64 Gaussian clusters in [0,2^20)^2,
-diameter 64, ideal crossing angle 70 degrees.
+them one after another on one stream).  Default workload: the largest
+single layout, 1,000,000 nodes and 3,000,000 edges with power-law degrees
+(exponent 2.3, maximum degree 10,000) on hub-heavy Gaussian clusters in
+[0,2^20)^2, diameter 16, ideal crossing angle 70 degrees (4.5e12 edge pairs
+and 5.0e11 node pairs per step).  ``--workload ba_cluster`` runs the
+50,000-node preferential-attachment layout instead.
 
 Prints one JSON line.  ``value`` is edge-pair tests per second of the whole
 step: C(|E|,2) per step / step time.  ``roofline`` reports the edge-pair
 sweep kernel (the dominant kernel) against the VALU issue peak; its duration
-comes from HIP events recorded by librb on the launch stream.  Beside that
-nominal peak it gives the attainable one, the FP64 FMA rate that independent
-FMA chains reach on the device (``attainable``, ``frac_of_attainable``).
+comes from HIP events recorded by librb on the launch stream.
 ``cpu_baseline`` times the CPU oracle on a bounded sample of the same layout.
-Further sections: ``batched`` (512 layouts, one hipGraph replay against 512
-plain launch sets), ``fwd_bwd`` (loss and gradient against the forward
-alone, and a 100-step descent), ``optimise`` (100 descent steps from a
-force-directed layout, all metrics before and after), ``pruned`` (the grid-pruned exact paths
-against the brute-force sweeps), ``approx`` (error and time of the strip
-approximation of Sections 3.2.2 / 3.2.3) and ``largest`` (one pass over the
-1,000,000-node / 3,000,000-edge layout).
+Further sections: ``ba_cluster`` (the same step on the 50,000-node layout),
+``batched`` (512 layouts, one hipGraph replay against 512 plain launch sets),
+``fwd_bwd`` (loss and gradient against the forward alone, and a 100-step
+descent), ``optimise`` (100 descent steps from a force-directed layout, all
+metrics before and after), ``pruned`` (the grid-pruned exact paths against
+the brute-force sweeps) and ``approx`` (error and time of the strip
+approximation of Sections 3.2.2 / 3.2.3).
 """
 import argparse
 import json
@@ -51,26 +52,47 @@ OPS_PER_NODE_PAIR = 3
 # dot product of the directions (2), the sign product (v dot) cross (2), two
 # compares for q = +1 / -1 and the masked +-1 into the row's integer sum (2)
 OPS_PER_ADJOINT_PAIR = 25
-# HBM bytes per launch of the crossing + angle sweep on this workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE (scaled by a 256 MiB copy: x2.000 and
-# x1.000), by (rows per thread, waves per SIMD).  Valid only for the kernel
-# source they were measured on (first 16 hex digits of its sha256).
-MEASURED_TRAFFIC = {"source_sha": "ab5d2f79d670990a",
-                    "bytes": {(4, 5): 142.2e6, (3, 6): 796.1e6, (2, 7): 165.6e6, (1, 8): 1050.8e6}}
+# HBM bytes per launch of the crossing + angle sweep, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size, per
+# workload and (rows per thread, waves per SIMD).  Valid only for the kernel
+# source they were measured on (first 16 hex digits of its sha256); None
+# otherwise.
+MEASURED_TRAFFIC = {
+    "powerlaw": {"source_sha": "ab5d2f79d670990a",
+                 "bytes": {(2, 7): 264395278.0625 * 1024 * 1.9998 + 4123.125 * 1024}},
+    "ba_cluster": {"source_sha": "ab5d2f79d670990a",
+                   "bytes": {(4, 5): 142.2e6, (3, 6): 796.1e6, (2, 7): 165.6e6,
+                             (1, 8): 1050.8e6}},
+}
 
 
-def measured_traffic(rows, waves):
+def measured_traffic(workload, rows, waves):
     import hashlib
+    m = MEASURED_TRAFFIC.get(workload)
+    if m is None:
+        return None
     src = os.path.join(ROOT, "paper_2411_09809_amd", "csrc", "cross.hip")
     with open(src, "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()[:16]
-    if sha != MEASURED_TRAFFIC["source_sha"]:
+    if sha != m["source_sha"]:
         return None
-    return MEASURED_TRAFFIC["bytes"].get((rows, waves))
+    return m["bytes"].get((rows, waves))
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def cpu_baseline(L, budget_pairs: float):
@@ -89,9 +111,9 @@ def cpu_baseline(L, budget_pairs: float):
     S, dt = run(budget_pairs)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     out = {"value": math.comb(S, 2) / dt, "unit": "edge-pair tests/s", "cores": threads,
-           "kind": "oracle",
+           "kind": "oracle", "cpu_model": cpu_model(),
            "sample": f"crossing + crossing-angle test over the first {S} edges "
-                     f"({math.comb(S, 2):.3e} pairs) of the same layout, {dt:.1f} s"}
+                     f"({math.comb(S, 2):.3e} pairs) of the {L.name} layout, {dt:.1f} s"}
     try:                                  # the oracle's OpenMP runtime
         gomp = C.CDLL("libgomp.so.1")
     except OSError:
@@ -104,21 +126,6 @@ def cpu_baseline(L, budget_pairs: float):
     out["value_1_thread"] = math.comb(S1, 2) / dt1
     out["sample_1_thread"] = (f"first {S1} edges ({math.comb(S1, 2):.3e} pairs), {dt1:.1f} s")
     return out
-
-
-def valu_probe(torch, iters=4096, repeats=20):
-    """FP64 FMA lane-operations per second that independent FMA chains reach
-    on this device: the clock the sweeps run at under FP64 load times the
-    lanes, an attainable ceiling beside the nominal one."""
-    import ctypes as C
-    from paper_2411_09809_amd import _lib
-    R = _lib.lib()
-    sink = torch.zeros(1, dtype=torch.float64, device="cuda")
-    rate = C.c_double()
-    _lib.check(R.rb_valu_probe(iters, repeats, C.byref(rate), C.c_void_p(sink.data_ptr()),
-                               C.c_void_p(torch.cuda.current_stream().cuda_stream)),
-               "rb_valu_probe")
-    return rate.value
 
 
 def bench_batch(torch, steps: int):
@@ -369,76 +376,132 @@ def bench_optimise(torch, steps: int):
                                "after": {k: after_m[k] for k in keep}}}
 
 
-def bench_largest(torch):
-    """The 1,000,000-node / 3,000,000-edge power-law layout: one pass of each
-    sweep (4.5e12 edge pairs, 5.0e11 node pairs) plus the two small metrics,
-    timed with the library's launch events."""
-    import ctypes as C
-    from paper_2411_09809_amd import _lib, gen, metrics
+WORKLOAD_TEXT = {
+    "powerlaw": "power-law degrees (gamma 2.3, max degree 10,000), hub-heavy Gaussian clusters in "
+                "[0,2^20)^2, diameter 16, ideal angle 70 deg",
+    "ba_cluster": "preferential attachment m=3 on 64 Gaussian clusters in [0,2^20)^2, "
+                  "diameter 64, ideal angle 70 deg",
+}
 
-    L = gen.powerlaw_layout(seed=0)
-    D = metrics.DeviceLayout.from_host(L)
+
+def make_layout(kind: str, seed: int):
+    from paper_2411_09809_amd import gen
+    return gen.powerlaw_layout(seed=seed) if kind == "powerlaw" else gen.ba_cluster_layout(seed=seed)
+
+
+def sweep_variants(L):
+    """Rows per thread and waves per SIMD of the sweeps this layout uses."""
+    import ctypes as C
+    from paper_2411_09809_amd import _lib
+    out = {}
+    for kind, name, n_items in ((1, "cross_angle", L.n_edges), (2, "occlusion", L.n_nodes)):
+        rows, waves = C.c_int(), C.c_int()
+        _lib.check(_lib.lib().rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves)), "q")
+        out[name] = {"rows_per_thread": rows.value, "waves_per_simd": waves.value}
+    return out
+
+
+def bench_step(torch, L, steps: int, warmup: int, serial: bool = False, autotune: bool = False):
+    """Time `steps` steps (all five metrics of layout L) after `warmup`, with
+    the edge-pair sweep's launches timed by librb's events; then the
+    node-pair sweep and the grid occlusion on their own."""
+    import ctypes as C
+    from paper_2411_09809_amd import _lib, metrics
+
+    dev = torch.device("cuda:0")
+    D = metrics.DeviceLayout.from_host(L, device=dev)
     R = _lib.lib()
-    pairs = math.comb(L.n_edges, 2)
-    node_pairs = math.comb(L.n_nodes, 2)
+    if autotune:     # fastest sweep variants for this layout's size classes (untimed)
+        ws = metrics.workspace(L.n_nodes, L.n_edges, dev)
+        w, wb = metrics._ws_args(ws)
+        tuned = C.c_double()
+        _lib.check(R.rb_autotune(D.x.data_ptr(), D.y.data_ptr(), L.n_nodes, D.src.data_ptr(),
+                                 D.dst.data_ptr(), L.n_edges, D.diameter, D.ideal_angle, 2,
+                                 C.byref(tuned), w, wb, metrics._stream(dev)), "rb_autotune")
+
+    def step():
+        if serial:
+            return [metrics.node_occlusion(D.x, D.y, D.diameter, async_=True),
+                    metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True),
+                    metrics.min_angle(D.x, D.y, D.src, D.dst, async_=True),
+                    metrics.edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)]
+        # the edge sweep on this stream, the other metrics on a second one
+        return list(metrics.evaluate_async(D))
+
+    out = None
+    for _ in range(warmup):
+        out = step()
     torch.cuda.synchronize()
     R.rb_timing_reset()
     R.rb_timing_enable(1)
-    t0 = time.perf_counter()
-    occ = metrics.node_occlusion(D.x, D.y, D.diameter, async_=True)
-    ang = metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True)
-    ma = metrics.min_angle(D.x, D.y, D.src, D.dst, async_=True)
-    ml = metrics.edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)
     torch.cuda.synchronize()
-    total = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
     R.rb_timing_enable(0)
     ms, n = C.c_double(), C.c_int64()
     _lib.check(R.rb_timing_read(0, C.byref(ms), C.byref(n)), "rb_timing_read")
-    cross_ms = ms.value
-    _lib.check(R.rb_timing_read(1, C.byref(ms), C.byref(n)), "rb_timing_read")
-    occl_ms = ms.value
+    cross_ms = ms.value / max(n.value, 1)
     R.rb_timing_reset()
-    ang = ang.cpu()
-    occ_grid = metrics.node_occlusion_grid(D.x, D.y, D.diameter)
-    R.rb_timing_enable(1)
-    for _ in range(3):
-        metrics.node_occlusion_grid(D.x, D.y, D.diameter, async_=True)
-    torch.cuda.synchronize()
-    R.rb_timing_enable(0)
-    _lib.check(R.rb_timing_read(2, C.byref(ms), C.byref(n)), "rb_timing_read")
-    grid_ms = ms.value / max(n.value, 1)
-    R.rb_timing_reset()
-    if occ_grid != int(occ.item()):
-        raise RuntimeError(f"grid occlusion {occ_grid} != brute force {int(occ.item())}")
-    pruned = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, D.ideal_angle)
-    if pruned[1] != int(ang.view(torch.int64)[1]):
-        raise RuntimeError("pruned crossing count differs from the brute-force count")
-    pruned_ms = time_kind(torch, 3, lambda: metrics.crossing_angle_pruned(
-        D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True), 1)
-    return {"workload": f"power-law (gamma 2.3, max degree 10,000) |V|={L.n_nodes} |E|={L.n_edges}, "
-                        "hub-heavy clusters in [0,2^20)^2, diameter 16",
-            "edge_pairs": pairs, "node_pairs": node_pairs, "step_s": total,
-            "edge_pair_sweep_ms": cross_ms, "edge_pair_sweep_pairs_per_s": pairs / (cross_ms * 1e-3),
-            "edge_pair_sweep_valu_frac":
-                OPS_PER_EDGE_PAIR * pairs / (cross_ms * 1e-3) / VALU_PEAK_OPS,
-            "node_pair_sweep_ms": occl_ms,
-            "node_pair_sweep_pairs_per_s": node_pairs / (occl_ms * 1e-3),
-            "node_occlusion_grid_ms": grid_ms,
-            "crossing_pruned_ms": pruned_ms,
-            "edge_crossings": int(ang.view(torch.int64)[1]), "crossing_angle": float(ang[0]),
-            "node_occlusions": int(occ.item()), "min_angle": float(ma[0]),
-            "edge_length_variation": float(ml[0])}
+    vals = [o.cpu() for o in out]
+
+    # the node-pair sweep on its own: inside a step it shares the GPU with the
+    # edge sweep, so its launch duration there is not its cost
+    reps = max(1, min(steps, 3))
+    occl_ms = time_kind(torch, 1, lambda: metrics.node_occlusion(D.x, D.y, D.diameter,
+                                                                 async_=True), reps)
+    # the grid method of Section 3.2.1 on the same layout (same exact count)
+    grid_occ = metrics.node_occlusion_grid(D.x, D.y, D.diameter)
+    grid_ms = time_kind(torch, 2, lambda: metrics.node_occlusion_grid(D.x, D.y, D.diameter,
+                                                                      async_=True), reps)
+    if grid_occ != int(vals[0][0]):
+        raise RuntimeError(f"grid occlusion {grid_occ} != brute force {int(vals[0][0])}")
+    pairs, node_pairs = math.comb(L.n_edges, 2), math.comb(L.n_nodes, 2)
+    res = {"elapsed_s": elapsed, "ms_per_step": elapsed * 1e3 / steps,
+           "edge_pairs_per_s": pairs * steps / elapsed, "edge_pair_sweep_ms": cross_ms,
+           "edge_pair_sweep_pairs_per_s": pairs / (cross_ms * 1e-3),
+           "edge_pair_sweep_valu_frac":
+               OPS_PER_EDGE_PAIR * pairs / (cross_ms * 1e-3) / VALU_PEAK_OPS,
+           "node_pair_sweep_ms": occl_ms,
+           "node_pair_sweep_pairs_per_s": node_pairs / (occl_ms * 1e-3),
+           "node_pair_sweep_valu_frac":
+               OPS_PER_NODE_PAIR * node_pairs / (occl_ms * 1e-3) / VALU_PEAK_OPS,
+           "node_occlusion_grid_ms": grid_ms,
+           "results": {"node_occlusion": int(vals[0][0]),
+                       "edge_crossing": int(vals[1].view(torch.int64)[1]),
+                       "crossing_angle": float(vals[1][0]), "min_angle": float(vals[2][0]),
+                       "edge_length_variation": float(vals[3][0])},
+           "variants": sweep_variants(L)}
+    return D, res
+
+
+def roofline(res, L, traffic_kind):
+    pairs = math.comb(L.n_edges, 2)
+    achieved = OPS_PER_EDGE_PAIR * pairs / (res["edge_pair_sweep_ms"] * 1e-3)
+    v = res["variants"]["cross_angle"]
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
+            "traffic": measured_traffic(traffic_kind, v["rows_per_thread"], v["waves_per_simd"]),
+            "kernel": "cross_sweep_kernel (crossing + angle)",
+            "ops_per_pair": OPS_PER_EDGE_PAIR, "kernel_ms": res["edge_pair_sweep_ms"],
+            "variant": v}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", choices=("powerlaw", "ba_cluster"), default="powerlaw",
+                    help="the layout of the timed step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=float, default=5e9,
+    ap.add_argument("--cpu-pairs", type=float, default=1.6e10,
                     help="edge pairs in the CPU-baseline sample")
+    ap.add_argument("--no-sections", action="store_true",
+                    help="only the timed step (for profiler runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-layout comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward part")
     ap.add_argument("--no-pruned", action="store_true",
@@ -449,8 +512,8 @@ def main():
                     help="skip the end-to-end layout optimisation")
     ap.add_argument("--no-approx", action="store_true",
                     help="skip the error study of the strip approximation")
-    ap.add_argument("--no-largest", action="store_true",
-                    help="skip the single pass over the 1M-node / 3M-edge layout")
+    ap.add_argument("--no-ba-cluster", action="store_true",
+                    help="skip the 50,000-node section")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -461,8 +524,6 @@ def main():
         sys.exit(2)
 
     import torch
-
-    from paper_2411_09809_amd import _lib, gen, metrics
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
@@ -481,137 +542,73 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n}))
         return
 
-    L = gen.ba_cluster_layout(seed=args.seed)
-    D = metrics.DeviceLayout.from_host(L, device=dev)
+    L = make_layout(args.workload, args.seed)
     pairs = math.comb(L.n_edges, 2)
-    node_pairs = math.comb(L.n_nodes, 2)
-    log(f"[bench] workload V={L.n_nodes} E={L.n_edges} pairs={pairs:.3e}")
-
-    # pick the fastest sweep variants for this layout's size classes (untimed)
-    import ctypes as C
-    ws = metrics.workspace(L.n_nodes, L.n_edges, dev)
-    w, wb = metrics._ws_args(ws)
-    tuned = C.c_double()
-    _lib.check(_lib.lib().rb_autotune(D.x.data_ptr(), D.y.data_ptr(), L.n_nodes, D.src.data_ptr(),
-                                      D.dst.data_ptr(), L.n_edges, D.diameter, D.ideal_angle, 2,
-                                      C.byref(tuned), w, wb, metrics._stream(dev)), "rb_autotune")
-    variant = {}
-    for kind, name in ((1, "cross_angle"), (2, "occlusion")):
-        rows, waves = C.c_int(), C.c_int()
-        n_items = L.n_nodes if kind == 2 else L.n_edges
-        _lib.check(_lib.lib().rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves)), "q")
-        variant[name] = {"rows_per_thread": rows.value, "waves_per_simd": waves.value}
-
-    def step():
-        if args.serial:
-            return [metrics.node_occlusion(D.x, D.y, D.diameter, async_=True),
-                    metrics.crossing_angle(D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True),
-                    metrics.min_angle(D.x, D.y, D.src, D.dst, async_=True),
-                    metrics.edge_length_variation(D.x, D.y, D.src, D.dst, async_=True)]
-        # the edge sweep on this stream, the other metrics on a second one
-        return list(metrics.evaluate_async(D))
-
-    for _ in range(args.warmup):
-        out = step()
-    torch.cuda.synchronize()
-    R = _lib.lib()
-    R.rb_timing_reset()
-    R.rb_timing_enable(1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    R.rb_timing_enable(0)
-    ms, n = C.c_double(), C.c_int64()
-    _lib.check(R.rb_timing_read(0, C.byref(ms), C.byref(n)), "rb_timing_read")
-    cross_ms = ms.value / max(n.value, 1)
-    R.rb_timing_reset()
-
-    # the node-pair sweep on its own: inside a step it shares the GPU with the
-    # edge sweep, so its launch duration there is not its cost
-    R.rb_timing_enable(1)
-    for _ in range(args.steps):
-        metrics.node_occlusion(D.x, D.y, D.diameter, async_=True)
-    torch.cuda.synchronize()
-    R.rb_timing_enable(0)
-    _lib.check(R.rb_timing_read(1, C.byref(ms), C.byref(n)), "rb_timing_read")
-    occl_ms = ms.value / max(n.value, 1)
-    R.rb_timing_reset()
-
-    # the grid method of Section 3.2.1 on the same layout (same exact count)
-    grid_occ = metrics.node_occlusion_grid(D.x, D.y, D.diameter)
-    R.rb_timing_reset()
-    R.rb_timing_enable(1)
-    for _ in range(args.steps):
-        metrics.node_occlusion_grid(D.x, D.y, D.diameter, async_=True)
-    torch.cuda.synchronize()
-    R.rb_timing_enable(0)
-    _lib.check(R.rb_timing_read(2, C.byref(ms), C.byref(n)), "rb_timing_read")
-    grid_ms = ms.value / max(n.value, 1)
-    R.rb_timing_reset()
-
-    attainable = valu_probe(torch)
-
-    vals = [o.cpu() for o in out]
-    if grid_occ != int(vals[0][0]):
-        raise RuntimeError(f"grid occlusion {grid_occ} != brute force {int(vals[0][0])}")
-    log(f"[bench] occlusion={int(vals[0][0])} E_c={int(vals[1].view(torch.int64)[1])} "
-        f"E_ca={float(vals[1][0]):.6f} M_a={float(vals[2][0]):.6f} M_l={float(vals[3][0]):.6g}")
-    ms_step = elapsed * 1e3 / args.steps
-    achieved = OPS_PER_EDGE_PAIR * pairs / (cross_ms * 1e-3)
+    log(f"[bench] {L.name} V={L.n_nodes} E={L.n_edges} pairs={pairs:.3e}: "
+        f"{args.warmup} warm-up and {args.steps} timed steps")
+    # the 50,000-node layout is tuned by rb_autotune; at 3M edges a variant
+    # launch takes seconds, so that layout keeps the built-in defaults
+    D, res = bench_step(torch, L, args.steps, args.warmup, args.serial,
+                        autotune=args.workload == "ba_cluster")
+    r = res["results"]
+    log(f"[bench] step {res['ms_per_step']:.1f} ms: N_c={r['node_occlusion']} "
+        f"E_c={r['edge_crossing']} E_ca={r['crossing_angle']:.6f} M_a={r['min_angle']:.6f} "
+        f"M_l={r['edge_length_variation']:.6g}")
+    kernels = {k: res[k] for k in ("edge_pair_sweep_ms", "edge_pair_sweep_pairs_per_s",
+                                   "edge_pair_sweep_valu_frac", "node_pair_sweep_ms",
+                                   "node_pair_sweep_pairs_per_s", "node_pair_sweep_valu_frac",
+                                   "node_occlusion_grid_ms")}
+    if args.workload == "powerlaw" and not args.no_sections:
+        from paper_2411_09809_amd import metrics
+        pruned = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, D.ideal_angle)
+        if pruned[1] != r["edge_crossing"]:
+            raise RuntimeError("pruned crossing count differs from the brute-force count")
+        kernels["crossing_pruned_ms"] = time_kind(torch, 3, lambda: metrics.crossing_angle_pruned(
+            D.x, D.y, D.src, D.dst, D.ideal_angle, async_=True), 1)
+    del D
     rec = {
         "metric": "edge-pair tests/s (exact crossings + crossing angle, all five metrics per step)",
-        "value": pairs * args.steps / elapsed,
+        "value": res["edge_pairs_per_s"],
         "unit": "edge-pair tests/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "ba_cluster_V50000_E149994: preferential attachment m=3 on 64 "
-                               "Gaussian clusters in [0,2^20)^2, diameter 64, ideal angle 70 deg",
-                   "n_nodes": L.n_nodes, "n_edges": L.n_edges, "seed": args.seed},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": measured_traffic(variant["cross_angle"]["rows_per_thread"],
-                                                 variant["cross_angle"]["waves_per_simd"]),
-                     "kernel": "cross_sweep_kernel (crossing + angle)",
-                     "ops_per_pair": OPS_PER_EDGE_PAIR, "kernel_ms": cross_ms,
-                     "attainable": attainable / 1e12,
-                     "frac_of_attainable": achieved / attainable,
-                     "variant": variant["cross_angle"]},
-        "kernels": {"edge_pair_sweep_ms": cross_ms,
-                    "edge_pair_sweep_pairs_per_s": pairs / (cross_ms * 1e-3),
-                    "node_pair_sweep_ms": occl_ms,
-                    "node_pair_sweep_pairs_per_s": node_pairs / (occl_ms * 1e-3),
-                    "node_pair_sweep_valu_frac":
-                        OPS_PER_NODE_PAIR * node_pairs / (occl_ms * 1e-3) / VALU_PEAK_OPS,
-                    "node_occlusion_grid_ms": grid_ms},
+        "config": {"workload": f"{L.name}: {WORKLOAD_TEXT[args.workload]}",
+                   "n_nodes": L.n_nodes, "n_edges": L.n_edges, "edge_pairs": pairs,
+                   "node_pairs": math.comb(L.n_nodes, 2), "seed": args.seed},
+        "roofline": roofline(res, L, args.workload),
+        "kernels": kernels,
+        "results": r,
     }
-    if not args.no_batch:
-        log("[bench] batched 512 layouts ...")
-        rec["batched"] = bench_batch(torch, max(3, args.steps // 4))
-    if not args.no_adjoint:
-        log("[bench] forward + adjoint ...")
-        rec["fwd_bwd"] = bench_adjoint(torch, max(3, args.steps // 2), 100)
-    if not args.no_pruned:
-        log("[bench] grid-pruned paths ...")
-        rec["pruned"] = bench_pruned(torch, max(3, args.steps // 4))
-    if not args.no_optimise:
-        log("[bench] layout optimisation ...")
-        rec["optimise"] = bench_optimise(torch, 100)
-    if not args.no_approx:
-        log("[bench] strip approximation error ...")
-        rec["approx"] = bench_approx(torch)
-    if not args.no_largest:
-        log("[bench] largest layout (1M nodes, 3M edges) ...")
-        rec["largest"] = bench_largest(torch)
+    if not args.no_sections:
+        if args.workload == "powerlaw" and not args.no_ba_cluster:
+            log("[bench] 50,000-node preferential-attachment layout ...")
+            Lb = make_layout("ba_cluster", args.seed)
+            _, rb = bench_step(torch, Lb, 20, 3, args.serial, autotune=True)
+            rb["workload"] = f"{Lb.name}: {WORKLOAD_TEXT['ba_cluster']}"
+            rb["roofline"] = roofline(rb, Lb, "ba_cluster")
+            rec["ba_cluster"] = rb
+        if not args.no_batch:
+            log("[bench] batched 512 layouts ...")
+            rec["batched"] = bench_batch(torch, 5)
+        if not args.no_adjoint:
+            log("[bench] forward + adjoint ...")
+            rec["fwd_bwd"] = bench_adjoint(torch, 10, 100)
+        if not args.no_pruned:
+            log("[bench] grid-pruned paths ...")
+            rec["pruned"] = bench_pruned(torch, 5)
+        if not args.no_optimise:
+            log("[bench] layout optimisation ...")
+            rec["optimise"] = bench_optimise(torch, 100)
+        if not args.no_approx:
+            log("[bench] strip approximation error ...")
+            rec["approx"] = bench_approx(torch)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(L, args.cpu_pairs)
