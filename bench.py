@@ -395,9 +395,12 @@ def sweep_variants(L):
     from paper_2411_09809_amd import _lib
     out = {}
     for kind, name, n_items in ((1, "cross_angle", L.n_edges), (2, "occlusion", L.n_nodes)):
-        rows, waves = C.c_int(), C.c_int()
-        _lib.check(_lib.lib().rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves)), "q")
+        rows, waves, split = C.c_int(), C.c_int(), C.c_int()
+        _lib.check(_lib.lib().rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves),
+                                            C.byref(split)), "rb_tune_query")
         out[name] = {"rows_per_thread": rows.value, "waves_per_simd": waves.value}
+        if kind == 2:
+            out[name]["chunk_split"] = split.value
     return out
 
 

@@ -131,6 +131,9 @@ rb_status rb_crossing_angle_noalloc(const float *x, const float *y, int64_t n_no
  * rb_node_occlusion_grid: N_c as rb_node_occlusion, by the grid method of
  *   Section 3.2.1 (cells of side >= d; each node meets the nodes of its own
  *   and four neighbour cells).  Work is O(|V| log |V| + candidate pairs).
+ *   Below 2^15 nodes it runs the all-pairs sweep of rb_node_occlusion
+ *   instead (the grid's sort and count passes cost more there); the count
+ *   is the same either way.
  * rb_crossing_angle_pruned: E_ca, E_c and the deviation sum as
  *   rb_crossing_angle (Algorithms 4 and 5), skipping the tiles of the pair
  *   triangle whose edges' bounding boxes cannot meet: edges are ordered by
@@ -316,8 +319,9 @@ rb_status rb_graph_launch(rb_graph *graph, void *stream);
 void rb_graph_destroy(rb_graph *graph);
 
 /* Autotuning of the all-pairs sweeps.  The sweeps come in variants (rows
- * of the pair matrix held per thread, waves per SIMD); all variants give
- * identical results.  Each call above picks the variant recorded for the
+ * of the pair matrix held per thread, waves per SIMD and, for the node
+ * sweep, how many units each 256-column chunk is split into); all variants
+ * give identical results.  Each call above picks the variant recorded for the
  * layout's size class (floor(log2) of its edge count, node count for the
  * occlusion sweep); built-in defaults apply until tuned.
  *   kind: 0 = edge crossing, 1 = crossing angle, 2 = node occlusion,
@@ -330,7 +334,9 @@ void rb_graph_destroy(rb_graph *graph);
  * fastest for its size classes and returns the sum of the three best mean
  * launch times in *out_best_ms (host, may be NULL).  It synchronises
  * `stream`.  rb_tune_set forces a variant index (0 .. variants-1) for a size
- * class; rb_tune_query reports the rows and waves of the variant in use.
+ * class; rb_tune_query reports the rows, waves and column split (1, 4 or
+ * 8; 1 for the edge sweeps) of the variant in use (each out pointer may be
+ * NULL).
  * rb_tune_save / rb_tune_load write and read the table as text (a load
  * replaces the whole table: classes the file does not list return to the
  * built-in defaults); the file
@@ -340,7 +346,8 @@ rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes,
                       double diameter, double ideal_angle, int repeats, double *out_best_ms,
                       void *ws, size_t ws_bytes, void *stream);
 rb_status rb_tune_set(int kind, int batch, int64_t n_items, int variant);
-rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *waves);
+rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *waves,
+                        int *col_split);
 rb_status rb_tune_save(const char *path);
 rb_status rb_tune_load(const char *path);
 

@@ -62,7 +62,8 @@ _SIGS = {
                      _vp, _sz, _vp], C.c_int),
     "rb_valu_probe": ([C.c_int, C.c_int, C.POINTER(C.c_double), _vp, _vp], C.c_int),
     "rb_tune_set": ([C.c_int, C.c_int, _i64, C.c_int], C.c_int),
-    "rb_tune_query": ([C.c_int, C.c_int, _i64, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+    "rb_tune_query": ([C.c_int, C.c_int, _i64, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                       C.POINTER(C.c_int)], C.c_int),
     "rb_tune_save": ([C.c_char_p], C.c_int),
     "rb_tune_load": ([C.c_char_p], C.c_int),
     "rb_batch_create": ([_i64, _vp, _vp, _vp, C.POINTER(C.c_void_p)], C.c_int),

@@ -213,6 +213,11 @@ size_t rb_workspace_size(int64_t n_nodes, int64_t n_edges) {
     return L.total;
 }
 
+static rb_status occlusion_launch(const float *x, const float *y, int64_t n_nodes,
+                                  double diameter, uint64_t *out_count, NodeRec *rec,
+                                  int64_t n_node_pad, OcclPartial *part, hipStream_t st,
+                                  int timed_kind);
+
 rb_status rb_node_occlusion(const float *x, const float *y, int64_t n_nodes, double diameter,
                             uint64_t *out_count, void *ws, size_t ws_bytes, void *stream) {
     g_err.clear();
@@ -224,23 +229,31 @@ rb_status rb_node_occlusion(const float *x, const float *y, int64_t n_nodes, dou
         return fail(RB_EINVAL, "diameter must be finite and >= 0");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, 0, &L))) return s;
-    hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
-    NodeRec *rec = (NodeRec *)(w + L.node_rec);
-    OcclPartial *part = (OcclPartial *)(w + L.partial);
+    return occlusion_launch(x, y, n_nodes, diameter, out_count, (NodeRec *)(w + L.node_rec),
+                            L.n_node_pad, (OcclPartial *)(w + L.partial), (hipStream_t)stream, 1);
+}
+
+// Node preparation, the all-pairs node sweep and its finalize into the given
+// record (n_node_pad entries) and partial-slot (kMaxPartials) buffers; the
+// sweep's launch is timed as `timed_kind`.
+static rb_status occlusion_launch(const float *x, const float *y, int64_t n_nodes,
+                                  double diameter, uint64_t *out_count, NodeRec *rec,
+                                  int64_t n_node_pad, OcclPartial *part, hipStream_t st,
+                                  int timed_kind) {
     const int v = tuned_variant(2, false, n_nodes);
-    const int rows = occl_variant(v).rows;
+    const int rows = occl_variant(v).rows, shift = occl_variant(v).col_shift;
     SweepArgs a;
     a.table = nullptr;
-    a.single = sweep_layout(n_nodes, rows, 0, 0);
+    a.single = sweep_layout(n_nodes, rows, 0, 0, shift);
     a.n_layouts = 1;
-    a.n_units = sweep_units(n_nodes, rows);
+    a.n_units = sweep_units(n_nodes, rows, shift);
     a.unit_base = 0;
     const int grid = (int)std::min<int64_t>(a.n_units, occl_grid(v));
-    hipError_t e = launch_node_prep(x, y, n_nodes, L.n_node_pad, occlusion_threshold(diameter),
+    hipError_t e = launch_node_prep(x, y, n_nodes, n_node_pad, occlusion_threshold(diameter),
                                     rec, st);
     if (e != hipSuccess) return hip_fail(e, "node_prep launch");
-    TimedLaunch tl(1, st);
+    TimedLaunch tl(timed_kind, st);
     e = launch_occl_sweep(v, rec, a, grid, part, st);
     tl.done();
     if (e != hipSuccess) return hip_fail(e, "occlusion sweep launch");
@@ -303,11 +316,11 @@ static rb_status crossing_launch(const float *x, const float *y, int64_t n_nodes
 // Tile-aligned, equal-work shard k of n of a single-layout unit list:
 // row tiles [t_k, t_k+1) where t_k is the first tile whose preceding units
 // reach ceil(k U / n).
-static void shard_tiles(int64_t n_items, int rows, int64_t k, int64_t n, int64_t *tile_b,
-                        int64_t *tile_e, int64_t *unit_b, int64_t *unit_e) {
-    const SweepLayout l = sweep_layout(n_items, rows, 0, 0);
+static void shard_tiles(int64_t n_items, int rows, int col_shift, int64_t k, int64_t n,
+                        int64_t *tile_b, int64_t *tile_e, int64_t *unit_b, int64_t *unit_e) {
+    const SweepLayout l = sweep_layout(n_items, rows, 0, 0, col_shift);
     auto before = [&](int64_t I) {
-        return I * l.n_chunks - (int64_t)rows * I * (I - 1) / 2;
+        return I * l.n_chunks - ((int64_t)rows << col_shift) * I * (I - 1) / 2;
     };
     const int64_t U = before(l.n_row_tiles);
     auto first_tile = [&](int64_t q) {   // smallest I with before(I) >= ceil(q U / n)
@@ -348,7 +361,7 @@ rb_status rb_crossing_angle_shard(const float *x, const float *y, int64_t n_node
     const int v = tuned_variant(1, false, n_edges);
     const int rows = cross_variant(v).rows;
     int64_t tb, te, ub, ue;
-    shard_tiles(n_edges, rows, shard, n_shards, &tb, &te, &ub, &ue);
+    shard_tiles(n_edges, rows, 0, shard, n_shards, &tb, &te, &ub, &ue);
     const int64_t R = (int64_t)kBlock * rows;
     if (out_row_begin) *out_row_begin = std::min<int64_t>(tb * R, n_edges);
     if (out_row_end) *out_row_end = std::min<int64_t>(te * R, n_edges);
@@ -391,15 +404,15 @@ rb_status rb_node_occlusion_shard(const float *x, const float *y, int64_t n_node
     NodeRec *rec = (NodeRec *)(w + L.node_rec);
     OcclPartial *part = (OcclPartial *)(w + L.partial);
     const int v = tuned_variant(2, false, n_nodes);
-    const int rows = occl_variant(v).rows;
+    const int rows = occl_variant(v).rows, shift = occl_variant(v).col_shift;
     int64_t tb, te, ub, ue;
-    shard_tiles(n_nodes, rows, shard, n_shards, &tb, &te, &ub, &ue);
+    shard_tiles(n_nodes, rows, shift, shard, n_shards, &tb, &te, &ub, &ue);
     const int64_t R = (int64_t)kBlock * rows;
     if (out_row_begin) *out_row_begin = std::min<int64_t>(tb * R, n_nodes);
     if (out_row_end) *out_row_end = std::min<int64_t>(te * R, n_nodes);
     SweepArgs a;
     a.table = nullptr;
-    a.single = sweep_layout(n_nodes, rows, 0, 0);
+    a.single = sweep_layout(n_nodes, rows, 0, 0, shift);
     a.n_layouts = 1;
     a.n_units = ue - ub;
     a.unit_base = ub;
@@ -439,6 +452,12 @@ rb_status rb_node_occlusion_grid(const float *x, const float *y, int64_t n_nodes
     if (ws_bytes < G.total)
         return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, G.total);
     hipStream_t st = (hipStream_t)stream;
+    if (n_nodes < kGridMinNodes) {     // the sweep costs less than the grid's passes
+        const int64_t pad = (std::max<int64_t>(n_nodes, 1) + kRecPad - 1) / kRecPad * kRecPad;
+        return occlusion_launch(x, y, n_nodes, diameter, out_count,
+                                (NodeRec *)((char *)ws + G.node_rec), pad,
+                                (OcclPartial *)((char *)ws + G.partial), st, 2);
+    }
     TimedLaunch tl(2, st);
     hipError_t e = launch_occlusion_grid(x, y, n_nodes, occlusion_threshold(diameter), G,
                                          (char *)ws, (unsigned long long *)out_count, st);
@@ -784,12 +803,12 @@ rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes, const int
         int best = -1;
         float best_ms = 0.f;
         for (int v = 0; v < nv && e == hipSuccess; ++v) {
-            const int rows = occl ? occl_variant(v).rows : cross_variant(v).rows;
+            const SweepVariant sv = occl ? occl_variant(v) : cross_variant(v);
             SweepArgs a;
             a.table = nullptr;
-            a.single = sweep_layout(n, rows, 0, 0);
+            a.single = sweep_layout(n, sv.rows, 0, 0, sv.col_shift);
             a.n_layouts = 1;
-            a.n_units = sweep_units(n, rows);
+            a.n_units = sweep_units(n, sv.rows, sv.col_shift);
             a.unit_base = 0;
             const int grid = (int)std::min<int64_t>(a.n_units, occl ? occl_grid(v) : cross_grid(v, angle));
             float ms = 0.f;
@@ -824,7 +843,8 @@ rb_status rb_tune_set(int kind, int batch, int64_t n_items, int variant) {
     return RB_OK;
 }
 
-rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *waves) {
+rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *waves,
+                        int *col_split) {
     g_err.clear();
     if (kind < 0 || kind > 3) return fail(RB_EINVAL, "kind must be 0, 1, 2 or 3");
     if (n_items < 0) return fail(RB_EINVAL, "n_items must be >= 0");
@@ -832,6 +852,7 @@ rb_status rb_tune_query(int kind, int batch, int64_t n_items, int *rows, int *wa
     const SweepVariant sv = kind == 2 ? occl_variant(v) : cross_variant(v);
     if (rows) *rows = sv.rows;
     if (waves) *waves = sv.waves;
+    if (col_split) *col_split = 1 << sv.col_shift;
     return RB_OK;
 }
 

@@ -285,6 +285,7 @@ int grid_for(int64_t n) {
 void build_tables(const rb_batch *b, std::vector<SweepLayout> *ct, std::vector<SweepLayout> *ot,
                   int64_t *cu, int64_t *ou) {
     const int rc = cross_variant(b->cross_var).rows, ro = occl_variant(b->occl_var).rows;
+    const int so = occl_variant(b->occl_var).col_shift;
     ct->resize(b->B + 1);
     ot->resize(b->B + 1);
     int64_t uc = 0, uo = 0;
@@ -292,9 +293,9 @@ void build_tables(const rb_batch *b, std::vector<SweepLayout> *ct, std::vector<S
         const int64_t E = b->edge_off[L + 1] - b->edge_off[L];
         const int64_t V = b->node_off[L + 1] - b->node_off[L];
         (*ct)[L] = sweep_layout(E, rc, uc, b->erec_off[L]);
-        (*ot)[L] = sweep_layout(V, ro, uo, b->nrec_off[L]);
+        (*ot)[L] = sweep_layout(V, ro, uo, b->nrec_off[L], so);
         uc += sweep_units(E, rc);
-        uo += sweep_units(V, ro);
+        uo += sweep_units(V, ro, so);
     }
     (*ct)[b->B] = SweepLayout{uc, b->erec_off[b->B], 0, 0};
     (*ot)[b->B] = SweepLayout{uo, b->nrec_off[b->B], 0, 0};

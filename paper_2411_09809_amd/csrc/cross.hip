@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void cross_finalize_kernel(
     }
 }
 
-constexpr SweepVariant kCross[kCrossVariants] = {{1, 8}, {2, 7}, {3, 6}, {4, 5}};
+constexpr SweepVariant kCross[kCrossVariants] = {{1, 8, 0}, {2, 7, 0}, {3, 6, 0}, {4, 5, 0}};
 
 template <int V>
 struct CrossV {

@@ -467,6 +467,8 @@ bool grid_ws_layout(int64_t n_nodes, int64_t n_edges, GridWs *G) {
     G->scalars = take(sizeof(Scalars));
     G->fwd = take(sizeof(Fwd));
     const int64_t V = std::max<int64_t>(n_nodes, 1);
+    G->node_rec = take(V < kGridMinNodes ? sizeof(NodeRec) * ((V + kRecPad - 1) / kRecPad * kRecPad)
+                                         : 0);
     G->deg = take(sizeof(uint32_t) * V);
     G->cursor = take(sizeof(uint32_t) * V);
     G->offs = take(sizeof(uint32_t) * (V + 1));

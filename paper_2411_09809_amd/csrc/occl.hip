@@ -2,11 +2,15 @@
 // closer than the diameter d = 2r.
 //
 // Same decomposition as the edge sweep: a row tile of R = 256*K nodes held in
-// registers against chunks of 256 nodes staged in LDS, over the upper
+// registers (K per thread) against chunks of W nodes staged in LDS, over the upper
 // triangle of each layout, one block per equal contiguous range of the unit
-// list of all layouts (many more blocks than the chip holds at once).  The exact integer test
-// |p_u - p_v|^2 <= T (T = largest integer < d^2) is evaluated as
-// g = x_u x_v + (y_u y_v + q_v) >= h_u (see NodeRec).
+// list of all layouts (many more blocks than the chip holds at once).  W is
+// 256, or 256/S for the variants that split chunks S ways: a layout of some
+// ten thousand nodes has only a few thousand 256-column units, a few per
+// block slot, and the last round of blocks would leave most of the chip idle.
+//
+// The exact integer test |p_u - p_v|^2 <= T (T = largest integer < d^2) is
+// evaluated as g = x_u x_v + (y_u y_v + q_v) >= h_u (see NodeRec).
 //
 // Occluding pairs are rare in any readable layout, so a chunk is first swept
 // keeping only each row's largest g: two fused multiply-adds and one max per
@@ -18,25 +22,29 @@
 namespace rb {
 namespace {
 
-__device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
-    return I * nC - (int64_t)K * I * (I - 1) / 2;
+// units of the row tiles before tile I: tile i meets chunks i*KS .. nC-1
+__device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int64_t KS) {
+    return I * nC - KS * I * (I - 1) / 2;
 }
 
 template <int K, bool DIAG>
-__device__ __forceinline__ uint32_t occl_count(const NodeRec *__restrict__ col,
+__device__ __forceinline__ uint32_t occl_count(const NodeRec *__restrict__ col, int W,
                                                const double (&rX)[K], const double (&rY)[K],
                                                const double (&rH)[K], int64_t row0,
                                                int64_t col0) {
     uint32_t n = 0;
-#pragma unroll 2
-    for (int j = 0; j < kChunk; ++j) {
-        const double cX = col[j].x, cY = col[j].y, cQ = col[j].q;
+    for (int j0 = 0; j0 < W; j0 += 4) {          // W is a multiple of 4
 #pragma unroll
-        for (int r = 0; r < K; ++r) {
-            const double g = fma(rX[r], cX, fma(rY[r], cY, cQ));
-            bool hit = g >= rH[r];
-            if (DIAG) hit = hit & (col0 + j > row0 + (int64_t)r * kBlock);
-            n += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+        for (int jj = 0; jj < 4; ++jj) {
+            const int j = j0 + jj;
+            const double cX = col[j].x, cY = col[j].y, cQ = col[j].q;
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const double g = fma(rX[r], cX, fma(rY[r], cY, cQ));
+                bool hit = g >= rH[r];
+                if (DIAG) hit = hit & (col0 + j > row0 + (int64_t)r * kBlock);
+                n += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+            }
         }
     }
     return n;
@@ -52,25 +60,27 @@ __device__ __forceinline__ double max2(double a, double b) {
 }
 
 template <int K>
-__device__ __forceinline__ uint32_t occl_chunk(const NodeRec *__restrict__ col,
+__device__ __forceinline__ uint32_t occl_chunk(const NodeRec *__restrict__ col, int W,
                                                const double (&rX)[K], const double (&rY)[K],
                                                const double (&rH)[K], int64_t row0,
                                                int64_t col0) {
     double gmax[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) gmax[r] = -HUGE_VAL;
-#pragma unroll 2
-    for (int j = 0; j < kChunk; ++j) {
-        const double cX = col[j].x, cY = col[j].y, cQ = col[j].q;
+    for (int j0 = 0; j0 < W; j0 += 4) {          // W is a multiple of 4
 #pragma unroll
-        for (int r = 0; r < K; ++r)
-            gmax[r] = max2(gmax[r], fma(rX[r], cX, fma(rY[r], cY, cQ)));
+        for (int jj = 0; jj < 4; ++jj) {
+            const double cX = col[j0 + jj].x, cY = col[j0 + jj].y, cQ = col[j0 + jj].q;
+#pragma unroll
+            for (int r = 0; r < K; ++r)
+                gmax[r] = max2(gmax[r], fma(rX[r], cX, fma(rY[r], cY, cQ)));
+        }
     }
     bool any = false;
 #pragma unroll
     for (int r = 0; r < K; ++r) any |= gmax[r] >= rH[r];
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(any) == 0, 1)) return 0;
-    return occl_count<K, false>(col, rX, rY, rH, row0, col0);
+    return occl_count<K, false>(col, W, rX, rY, rH, row0, col0);
 }
 
 template <int K, int WAVES, bool BATCH>
@@ -95,15 +105,17 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
         L = lo;
     }
     SweepLayout lay = BATCH ? a.table[L] : a.single;
+    int W = kChunk >> lay.col_shift;               // columns per unit
+    int64_t KS = (int64_t)K << lay.col_shift;      // chunks spanned by a row tile
     const int64_t lu = u_begin - lay.unit_off;
     int64_t lo = 0, hi = lay.n_row_tiles - 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
-        if (units_before(mid, lay.n_chunks, K) <= lu) lo = mid;
+        if (units_before(mid, lay.n_chunks, KS) <= lu) lo = mid;
         else hi = mid - 1;
     }
     int64_t I = lo;
-    int64_t c = I * K + (lu - units_before(I, lay.n_chunks, K));
+    int64_t c = I * KS + (lu - units_before(I, lay.n_chunks, KS));
 
     double rX[K], rY[K], rH[K];
     bool rows_loaded = false;
@@ -135,21 +147,25 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
             rows_loaded = true;
         }
         __syncthreads();
-        col[tid] = rec[lay.rec_off + c * kChunk + tid];
+        if (tid < W) col[tid] = rec[lay.rec_off + c * W + tid];
         __syncthreads();
-        const int64_t row0 = I * R + tid, col0 = c * kChunk;
-        if (c < (I + 1) * K) tot += occl_count<K, true>(col, rX, rY, rH, row0, col0);
-        else tot += occl_chunk<K>(col, rX, rY, rH, row0, col0);
+        const int64_t row0 = I * R + tid, col0 = c * W;
+        if (c < (I + 1) * KS) tot += occl_count<K, true>(col, W, rX, rY, rH, row0, col0);
+        else tot += occl_chunk<K>(col, W, rX, rY, rH, row0, col0);
         ++seg_units;
         if (++c == lay.n_chunks) {
             ++I;
-            c = I * K;
+            c = I * KS;
             rows_loaded = false;
             if (BATCH && I == lay.n_row_tiles) {
                 flush(b + L);
                 seg_units = 0;
                 ++L;
-                if (L < a.n_layouts) lay = a.table[L];
+                if (L < a.n_layouts) {
+                    lay = a.table[L];
+                    W = kChunk >> lay.col_shift;
+                    KS = (int64_t)K << lay.col_shift;
+                }
                 I = 0;
                 c = 0;
             }
@@ -194,7 +210,12 @@ __global__ __launch_bounds__(256) void occl_finalize_kernel(const OcclPartial *_
     if (tid == 0) *out_count = s[0];
 }
 
-constexpr SweepVariant kOccl[kOcclVariants] = {{8, 4}, {2, 8}, {4, 6}};
+// rows per thread, waves per SIMD, column split (log2): the split variants
+// cut each 256-column chunk into 4 or 8 units, for layouts too small to
+// fill the chip with whole chunks
+constexpr SweepVariant kOccl[kOcclVariants] = {{8, 5, 0}, {2, 8, 0}, {4, 6, 0}, {4, 6, 2},
+                                               {2, 8, 2}, {4, 6, 3}, {2, 8, 3}, {8, 5, 2},
+                                               {8, 5, 3}};
 
 template <int V>
 struct OcclV {
@@ -217,12 +238,24 @@ int occl_grid(int) { return kMaxPartials; }
 hipError_t launch_occl_sweep(int v, const NodeRec *rec, const SweepArgs &a, int grid,
                              OcclPartial *part, hipStream_t st) {
     const bool batch = a.table != nullptr;
+#define RB_OCASE(V)                                                                       \
+    case V:                                                                               \
+        if (batch) launch_v<V, true>(rec, a, grid, part, st);                             \
+        else launch_v<V, false>(rec, a, grid, part, st);                                  \
+        break;
     switch (v) {
-        case 0: batch ? launch_v<0, true>(rec, a, grid, part, st) : launch_v<0, false>(rec, a, grid, part, st); break;
-        case 1: batch ? launch_v<1, true>(rec, a, grid, part, st) : launch_v<1, false>(rec, a, grid, part, st); break;
-        case 2: batch ? launch_v<2, true>(rec, a, grid, part, st) : launch_v<2, false>(rec, a, grid, part, st); break;
+        RB_OCASE(0)
+        RB_OCASE(1)
+        RB_OCASE(2)
+        RB_OCASE(3)
+        RB_OCASE(4)
+        RB_OCASE(5)
+        RB_OCASE(6)
+        RB_OCASE(7)
+        RB_OCASE(8)
         default: return hipErrorInvalidValue;
     }
+#undef RB_OCASE
     return hipGetLastError();
 }
 

@@ -15,20 +15,24 @@
 
 namespace rb {
 
-SweepLayout sweep_layout(int64_t n_items, int rows, int64_t unit_off, int64_t rec_off) {
+SweepLayout sweep_layout(int64_t n_items, int rows, int64_t unit_off, int64_t rec_off,
+                         int col_shift) {
     const int64_t R = (int64_t)kBlock * rows;
+    const int64_t W = (int64_t)(kChunk >> col_shift);
     const int64_t n = n_items > 0 ? n_items : 1;
     SweepLayout l;
     l.unit_off = unit_off;
     l.rec_off = rec_off;
     l.n_row_tiles = (n + R - 1) / R;
-    l.n_chunks = (n + kChunk - 1) / kChunk;
+    l.n_chunks = (n + W - 1) / W;
+    l.col_shift = col_shift;
     return l;
 }
 
-int64_t sweep_units(int64_t n_items, int rows) {
-    const SweepLayout l = sweep_layout(n_items, rows, 0, 0);
-    return l.n_row_tiles * l.n_chunks - (int64_t)rows * l.n_row_tiles * (l.n_row_tiles - 1) / 2;
+int64_t sweep_units(int64_t n_items, int rows, int col_shift) {
+    const SweepLayout l = sweep_layout(n_items, rows, 0, 0, col_shift);
+    return l.n_row_tiles * l.n_chunks -
+           ((int64_t)rows << col_shift) * l.n_row_tiles * (l.n_row_tiles - 1) / 2;
 }
 
 namespace {
@@ -66,20 +70,32 @@ void load_locked(const char *path) {
     fclose(f);
 }
 
-// the built-in default of a kind and size class: the pruned sweep takes the
-// 1-row tiles (tightest boxes) below 2^17 edges and 2-row tiles above; the
-// node sweep takes 8-row tiles from 2^19 nodes (the fewest LDS reads per
-// pair, once there are units enough to fill the chip)
-int default_variant(int k, int c) {
+// the built-in default of a kind, batch flag and size class: the pruned
+// sweep takes the 1-row tiles (tightest boxes) below 2^17 edges and 2-row
+// tiles above.  The node sweep of a single layout splits its 256-column
+// chunks below 2^16 nodes (2 rows per thread and 32 columns below 2^13
+// nodes, 2 rows and 64 columns below 2^15, 4 rows and 64 columns below
+// 2^16: units enough to fill the chip), takes whole chunks at 4 rows below
+// 2^17 and 8-row tiles (the fewest LDS reads per pair) from there; a batch
+// has units enough in any case and keeps 4-row tiles up to a mean of 2^19
+// nodes per layout.
+int default_variant(int k, int b, int c) {
     if (k == 3 && c >= 17) return 1;
-    if (k == 2 && c >= 19) return 0;
+    if (k == 2) {
+        if (b) return c >= 19 ? 0 : 2;
+        if (c <= 12) return 6;
+        if (c <= 14) return 4;
+        if (c == 15) return 3;
+        if (c == 16) return 2;
+        return 0;
+    }
     return kDefault[k];
 }
 
 void defaults_locked() {
     for (int k = 0; k < kKinds; ++k)
         for (int b = 0; b < 2; ++b)
-            for (int c = 0; c < kClasses; ++c) g_tab.v[k][b][c] = default_variant(k, c);
+            for (int c = 0; c < kClasses; ++c) g_tab.v[k][b][c] = default_variant(k, b, c);
 }
 
 void init_locked() {
@@ -112,7 +128,7 @@ bool save_tuning(const char *path) {
     for (int k = 0; k < kKinds; ++k)
         for (int b = 0; b < 2; ++b)
             for (int c = 0; c < kClasses; ++c)
-                if (g_tab.v[k][b][c] != default_variant(k, c))
+                if (g_tab.v[k][b][c] != default_variant(k, b, c))
                     fprintf(f, "%d %d %d %d\n", k, b, c, g_tab.v[k][b][c]);
     return fclose(f) == 0;
 }

@@ -74,13 +74,16 @@ constexpr int kSmallDeg = 16;        // min-angle: thread-per-node up to this de
 constexpr int kLdsDeg = 2048;        // min-angle: block sort in LDS up to this degree
 
 // One layout inside a sweep's unit list.  Row tile I (R = 256*K records)
-// meets column chunks c = I*K .. n_chunks-1 (256 records each); the layout's
-// units are numbered from unit_off in that order.
+// meets column chunks c = I*K*S .. n_chunks-1 of W = 256/S records each
+// (S = 2^col_shift: the node sweep splits chunks when a layout has too few
+// units to fill the chip; the edge sweeps keep S = 1); the layout's units
+// are numbered from unit_off in that order.
 struct SweepLayout {
     int64_t unit_off;       // first global unit of this layout
     int64_t rec_off;        // first record of this layout (multiple of kRecPad)
     int64_t n_row_tiles;
     int64_t n_chunks;
+    int64_t col_shift;
 };
 
 // Kernel arguments of a sweep.  A single layout travels by value; a batch
@@ -94,13 +97,15 @@ struct SweepArgs {
     int64_t unit_base;      // ... starting at this global unit (single layout only)
 };
 
-// Sweep kernel variants: rows per thread and minimum waves per SIMD.
+// Sweep kernel variants: rows per thread, minimum waves per SIMD and the
+// column split of the unit list (log2 S; node sweep only).
 struct SweepVariant {
     int rows;
     int waves;
+    int col_shift;
 };
 constexpr int kCrossVariants = 4;
-constexpr int kOcclVariants = 3;
+constexpr int kOcclVariants = 9;
 SweepVariant cross_variant(int v);
 SweepVariant occl_variant(int v);
 
@@ -125,11 +130,16 @@ struct GridWs {
     size_t rec, box, tile_cnt, tile_off, list;   // pruned edge sweep
     size_t kacc, scalars, fwd;                    // pruned loss and gradient
     size_t deg, cursor, offs, angles, nbr, dv, big_list;   // minimum-angle term
+    size_t node_rec;                              // sweep records below kGridMinNodes
     size_t total;
     int64_t n_sort_blocks, n_edge_pad, max_units;
 };
 // largest edge count of the pruned edge sweep (its unit list is indexed in 32 bits)
 constexpr int64_t kMaxPrunedEdges = 1ll << 24;
+// below this many nodes the grid occlusion call runs the all-pairs sweep: its
+// sort and count passes cost about 0.1 ms whatever the size, more than the
+// sweep of 2^15 nodes
+constexpr int64_t kGridMinNodes = 1ll << 15;
 bool grid_ws_layout(int64_t n_nodes, int64_t n_edges, GridWs *G);
 
 // Small device scalars used between kernels of one call.
@@ -186,8 +196,9 @@ struct SweepPlan {
     SweepLayout single;
 };
 // Unit list of one layout of n_items records for a variant.
-SweepLayout sweep_layout(int64_t n_items, int rows, int64_t unit_off, int64_t rec_off);
-int64_t sweep_units(int64_t n_items, int rows);
+SweepLayout sweep_layout(int64_t n_items, int rows, int64_t unit_off, int64_t rec_off,
+                         int col_shift = 0);
+int64_t sweep_units(int64_t n_items, int rows, int col_shift = 0);
 // Largest grid (blocks) of a sweep variant; a launch uses min(units, this),
 // one equal contiguous range of the unit list per block.
 int cross_grid(int variant, bool angle);

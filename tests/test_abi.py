@@ -148,23 +148,30 @@ def test_argument_errors_of_the_other_entry_points_need_no_gpu(L):
 
 def test_built_in_tuning_defaults(L, tmp_path):
     """The defaults a table returns to on a load of an empty file: crossing
-    sweeps 2 rows / 7 waves at every size; the node sweep 4 rows / 6 waves
-    below 2^19 nodes and 8 rows / 4 waves from there; the pruned sweep 1-row
-    tiles below 2^17 edges and 2-row tiles from there."""
+    sweeps 2 rows / 7 waves at every size; the node sweep of a single layout
+    2 rows / 8 waves in chunks split 8 ways below 2^13 nodes, split 4 ways
+    below 2^15, 4 rows / 6 waves split 4 ways below 2^16, whole chunks below
+    2^17 and 8 rows / 5 waves from there (a batch: 4 rows / 6 waves, whole
+    chunks, below a mean of 2^19 nodes); the pruned sweep 1-row tiles below
+    2^17 edges and 2-row tiles from there."""
     import ctypes as C
     empty = tmp_path / "tune.txt"
     empty.write_text("")
     assert L.rb_tune_load(str(empty).encode()) == 0
 
-    def q(kind, n):
-        rows, waves = C.c_int(), C.c_int()
-        assert L.rb_tune_query(kind, 0, n, C.byref(rows), C.byref(waves)) == 0
-        return rows.value, waves.value
+    def q(kind, n, batch=0):
+        rows, waves, split = C.c_int(), C.c_int(), C.c_int()
+        assert L.rb_tune_query(kind, batch, n, C.byref(rows), C.byref(waves),
+                               C.byref(split)) == 0
+        return (rows.value, waves.value) if kind != 2 else (rows.value, waves.value, split.value)
 
     for n in (2_000, 149_994, 3_000_000):
         assert q(0, n) == (2, 7) and q(1, n) == (2, 7)
-    assert q(2, 50_000) == (4, 6) and q(2, (1 << 19) - 1) == (4, 6)
-    assert q(2, 1 << 19) == (8, 4) and q(2, 1_000_000) == (8, 4)
+    assert q(2, 1_000) == (2, 8, 8) and q(2, (1 << 13) - 1) == (2, 8, 8)
+    assert q(2, 1 << 13) == (2, 8, 4) and q(2, 20_000) == (2, 8, 4)
+    assert q(2, 50_000) == (4, 6, 4) and q(2, 100_000) == (4, 6, 1)
+    assert q(2, 1 << 17) == (8, 5, 1) and q(2, 1_000_000) == (8, 5, 1)
+    assert q(2, 50_000, batch=1) == (4, 6, 1) and q(2, 1 << 19, batch=1) == (8, 5, 1)
     assert q(3, (1 << 17) - 1) == (1, 8) and q(3, 1 << 17) == (2, 7)
 
 

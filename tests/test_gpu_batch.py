@@ -201,9 +201,9 @@ def test_every_sweep_variant_agrees(torch_mod, kind):
     n_items = L.n_nodes if kind == 2 else L.n_edges
     lib = _lib.lib()
     rows, waves = C.c_int(), C.c_int()
-    _lib.check(lib.rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves)), "query")
+    _lib.check(lib.rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves), None), "query")
     default = None
-    for v in range(3 if kind == 2 else 4):
+    for v in range(9 if kind == 2 else 4):
         _lib.check(lib.rb_tune_set(kind, 0, n_items, v), "rb_tune_set")
         say(f"[variant] kind {kind} variant {v}")
         if kind == 0:

@@ -4,7 +4,9 @@ rb_node_occlusion_grid must return the brute-force N_c bit for bit: on
 closed-form lattices, coincident nodes, the full range of diameters (zero,
 sub-unit, exact integer thresholds, larger than the layout), crowded and
 negative-coordinate layouts, and the full-size workloads up to the
-1,000,000-node power-law layout.
+1,000,000-node power-law layout.  Below 2^15 nodes the call runs the
+all-pairs sweep; the small cases are also run with a lattice of far filler
+nodes added (same count), which takes them through the grid kernels.
 """
 import sys
 
@@ -35,6 +37,51 @@ def dev_xy(torch, x, y):
     return t(x), t(y)
 
 
+GRID_MIN_NODES = 1 << 15      # below this the grid call runs the all-pairs sweep
+FILL_SIDE = 182               # 182^2 >= 2^15 filler nodes
+
+
+def with_fillers(xs, ys, d):
+    """The layout plus a lattice of 182^2 filler nodes beside it, spaced at
+    least d apart and at least d from every node: the same occlusion count,
+    and enough nodes for the grid call to take the grid route.  None when
+    the lattice does not fit in [-2^20, 2^20]."""
+    xs, ys = np.asarray(xs, dtype=np.int64), np.asarray(ys, dtype=np.int64)
+    s = max(1, int(np.ceil(d)))
+    span = (FILL_SIDE - 1) * s
+    lo_y = int(ys.min()) if ys.size else 0
+    if lo_y + span > 1 << 20:
+        lo_y = (1 << 20) - span
+    if lo_y < -(1 << 20):
+        return None
+    hi_x = int(xs.max()) if xs.size else 0
+    lo_x = int(xs.min()) if xs.size else 0
+    if hi_x + s + span <= 1 << 20:
+        x0 = hi_x + s
+    elif lo_x - s - span >= -(1 << 20):
+        x0 = lo_x - s - span
+    else:
+        return None
+    gx, gy = np.meshgrid(np.arange(FILL_SIDE) * s + x0, np.arange(FILL_SIDE) * s + lo_y)
+    return (np.concatenate([xs, gx.ravel()]), np.concatenate([ys, gy.ravel()]))
+
+
+def grid_count(torch, xs, ys, d):
+    """rb_node_occlusion_grid on the layout (below 2^15 nodes: the sweep
+    route) and, where the fillers fit, on the layout with fillers (the grid
+    route); both must agree."""
+    from paper_2411_09809_amd import metrics
+    x, y = dev_xy(torch, xs, ys)
+    got = metrics.node_occlusion_grid(x, y, d)
+    if len(xs) < GRID_MIN_NODES:
+        padded = with_fillers(xs, ys, d)
+        if padded is not None:
+            assert padded[0].size >= GRID_MIN_NODES
+            px, py = dev_xy(torch, *padded)
+            assert metrics.node_occlusion_grid(px, py, d) == got, ("grid route", d)
+    return got
+
+
 @pytest.mark.parametrize("k,s,d", [(7, 4, 8.0), (7, 8, 8.0), (10, 3, 6.5), (12, 5, 7.0),
                                    (9, 1, 1.0), (9, 1, 1.5), (16, 2, 40.0)])
 def test_lattice(torch_mod, k, s, d):
@@ -42,16 +89,15 @@ def test_lattice(torch_mod, k, s, d):
     L = gen.square_lattice(k, s, d)
     x, y = dev_xy(torch_mod, L.x, L.y)
     want = oracle.node_occlusion(L.x, L.y, d)
-    assert metrics.node_occlusion_grid(x, y, d) == want
+    assert grid_count(torch_mod, L.x, L.y, d) == want
     assert metrics.node_occlusion(x, y, d) == want
 
 
 def test_coincident_and_tiny(torch_mod):
-    from paper_2411_09809_amd import metrics
     for n in (0, 1, 2, 5, 300):
-        x, y = dev_xy(torch_mod, np.full(n, 17.0), np.full(n, -3.0))
-        assert metrics.node_occlusion_grid(x, y, 1.0) == n * (n - 1) // 2
-        assert metrics.node_occlusion_grid(x, y, 0.0) == 0
+        xs, ys = np.full(n, 17.0), np.full(n, -3.0)
+        assert grid_count(torch_mod, xs, ys, 1.0) == n * (n - 1) // 2
+        assert grid_count(torch_mod, xs, ys, 0.0) == 0
 
 
 @pytest.mark.parametrize("d", [0.0, 0.5, 1.0, 1.0000001, 2.0, 3.0, 7.9, 8.0, 8.0000001, 33.3,
@@ -61,7 +107,7 @@ def test_diameters_uniform(torch_mod, d):
     L = gen.uniform_layout(4000, 10, extent=1 << 10, seed=31)
     x, y = dev_xy(torch_mod, L.x, L.y)
     want = metrics.node_occlusion(x, y, d)
-    got = metrics.node_occlusion_grid(x, y, d)
+    got = grid_count(torch_mod, L.x, L.y, d)
     say(f"[grid] d={d} brute={want} grid={got}")
     assert got == want
     assert want == oracle.node_occlusion(L.x, L.y, d)
@@ -81,7 +127,7 @@ def test_crowded_and_negative(torch_mod):
     for xs, ys, d in cases:
         x, y = dev_xy(torch_mod, xs, ys)
         want = oracle.node_occlusion(xs, ys, d)
-        assert metrics.node_occlusion_grid(x, y, d) == want
+        assert grid_count(torch_mod, xs, ys, d) == want
         assert metrics.node_occlusion(x, y, d) == want
 
 

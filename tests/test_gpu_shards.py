@@ -132,14 +132,14 @@ def test_powerlaw_whole_invariants(powerlaw, torch_mod):
     import os
     import tempfile
     rows, waves = C.c_int(), C.c_int()
-    assert lib().rb_tune_query(1, 0, L.n_edges, C.byref(rows), C.byref(waves)) == 0
+    assert lib().rb_tune_query(1, 0, L.n_edges, C.byref(rows), C.byref(waves), None) == 0
     with tempfile.TemporaryDirectory() as tmp:
         saved = os.path.join(tmp, "tune.txt").encode()
         assert lib().rb_tune_save(saved) == 0
         assert lib().rb_tune_set(1, 0, L.n_edges, 0 if rows.value != 1 else 3) == 0
         try:
             r2, w2 = C.c_int(), C.c_int()
-            lib().rb_tune_query(1, 0, L.n_edges, C.byref(r2), C.byref(w2))
+            lib().rb_tune_query(1, 0, L.n_edges, C.byref(r2), C.byref(w2), None)
             assert (r2.value, w2.value) != (rows.value, waves.value)
             say(f"[powerlaw] variant rows={r2.value} waves={w2.value}")
             eca_v, cnt_v, dev_v = metrics.crossing_angle(D.x, D.y, D.src, D.dst, IDEAL)
