@@ -58,11 +58,8 @@ OPS_PER_ADJOINT_PAIR = 25
 # source they were measured on (first 16 hex digits of its sha256); None
 # otherwise.
 MEASURED_TRAFFIC = {
-    "powerlaw": {"source_sha": "ab5d2f79d670990a",
-                 "bytes": {(2, 7): 264395278.0625 * 1024 * 1.9998 + 4123.125 * 1024}},
-    "ba_cluster": {"source_sha": "ab5d2f79d670990a",
-                   "bytes": {(4, 5): 142.2e6, (3, 6): 796.1e6, (2, 7): 165.6e6,
-                             (1, 8): 1050.8e6}},
+    "powerlaw": {"source_sha": "c847716cbc409f12",
+                 "bytes": {(4, 5): 132605213.3125 * 1024 * 1.9998 + 4096 * 1024}},
 }
 
 

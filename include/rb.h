@@ -334,7 +334,8 @@ void rb_graph_destroy(rb_graph *graph);
  * fastest for its size classes and returns the sum of the three best mean
  * launch times in *out_best_ms (host, may be NULL).  It synchronises
  * `stream`.  rb_tune_set forces a variant index (0 .. variants-1) for a size
- * class; rb_tune_query reports the rows, waves and column split (1, 4 or
+ * class (the batched edge sweeps do not offer variant 3, 4 rows per thread:
+ * RB_EINVAL); rb_tune_query reports the rows, waves and column split (1, 4 or
  * 8; 1 for the edge sweeps) of the variant in use (each out pointer may be
  * NULL).
  * rb_tune_save / rb_tune_load write and read the table as text (a load

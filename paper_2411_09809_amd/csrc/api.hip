@@ -839,6 +839,8 @@ rb_status rb_tune_set(int kind, int batch, int64_t n_items, int variant) {
     if (n_items < 0) return fail(RB_EINVAL, "n_items must be >= 0");
     const int nv = kind == 2 ? kOcclVariants : kCrossVariants;
     if (variant < 0 || variant >= nv) return fail(RB_EINVAL, "variant must be in [0, %d)", nv);
+    if (!variant_offered(kind, batch != 0, variant))
+        return fail(RB_EINVAL, "variant %d is not offered for batched crossing sweeps", variant);
     set_tuned_variant(kind, batch != 0, n_items, variant);
     return RB_OK;
 }

@@ -614,6 +614,7 @@ rb_status rb_batch_autotune(rb_batch *b, const float *x, const float *y, const i
         int best = -1;
         float best_ms = 0.f;
         for (int v = 0; v < nv && e == hipSuccess; ++v) {
+            if (!variant_offered(occl ? 2 : 1, true, v)) continue;
             if (occl) b->occl_var = v;
             else b->cross_var = v;
             e = upload(b, ws, st);

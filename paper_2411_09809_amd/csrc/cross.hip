@@ -51,7 +51,7 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
                                             const double (&rX)[K], const double (&rY)[K],
                                             const double (&rDX)[K], const double (&rDY)[K],
                                             const double (&rC)[K], const double (&rTH)[K],
-                                            int tid, int64_t row0, int64_t col0, double ideal,
+                                            int tid, int diag_off, double ideal,
                                             double angc, uint32_t &n_proper, uint32_t &n_touch,
                                             double &acc) {
 #pragma unroll 4
@@ -72,7 +72,9 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
             const double p12 = o1 * (o1 + cr);
             const double p34 = o3 * (o3 - cr);
             const double m = fmax(p12, p34);
-            const bool in_tri = !DIAG || (col0 + j > row0 + (int64_t)r * kBlock);
+            // a diagonal unit keeps column index > row index: with the tile's
+            // first row as origin, diag_off + j > r * 256 + tid
+            const bool in_tri = !DIAG || (diag_off + j > r * kBlock + tid);
             const bool prop = (m < 0.0) & in_tri;
             zr[r] = (m == 0.0) & in_tri;
             const uint64_t pmask = __builtin_amdgcn_ballot_w64(prop);
@@ -156,7 +158,11 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
         if (ANGLE) {
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         }
-        const int wave = tid >> 6, lane = tid & 63;
+        // the reduction's LDS addresses are formed here, not held (or spilled)
+        // across the sweep
+        int t = tid;
+        __asm__ volatile("" : "+v"(t));
+        const int wave = t >> 6, lane = t & 63;
         __syncthreads();
         if (lane == 0) {
             red_p[wave] = tot_p;
@@ -190,15 +196,22 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
             }
             rows_loaded = true;
         }
-        col[tid] = rec[lay.rec_off + c * kChunk + tid];
+        {
+            // recompute the lane's address each unit: held across the whole
+            // loop it is one more 64-bit register pair, which the 3- and
+            // 4-row variants had to spill
+            int lane_rec = tid;
+            __asm__ volatile("" : "+v"(lane_rec));
+            col[tid] = rec[lay.rec_off + c * kChunk + lane_rec];
+        }
         __syncthreads();
         uint32_t n_p = 0, n_t = 0;
-        const int64_t row0 = I * R + tid, col0 = c * kChunk;
+        const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
-            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, row0, col0,
+            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
                                         ideal, angc, n_p, n_t, acc);
         else
-            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, row0, col0,
+            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
                                          ideal, angc, n_p, n_t, acc);
         tot_p += n_p;
         tot_t += n_t;
@@ -287,12 +300,12 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
         col[tid] = rec[c * kChunk + tid];
         __syncthreads();
         uint32_t n_p = 0, n_t = 0;
-        const int64_t row0 = I * R + tid, col0 = c * kChunk;
+        const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
-            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, row0, col0,
+            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
                                         ideal, angc, n_p, n_t, acc);
         else
-            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, row0, col0,
+            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
                                          ideal, angc, n_p, n_t, acc);
         tot_p += n_p;
         tot_t += n_t;
@@ -389,7 +402,7 @@ __global__ __launch_bounds__(256) void cross_finalize_kernel(
     }
 }
 
-constexpr SweepVariant kCross[kCrossVariants] = {{1, 8, 0}, {2, 7, 0}, {3, 6, 0}, {4, 5, 0}};
+constexpr SweepVariant kCross[kCrossVariants] = {{1, 8, 0}, {2, 7, 0}, {3, 5, 0}, {4, 5, 0}};
 
 template <int V>
 struct CrossV {

@@ -64,13 +64,16 @@ void load_locked(const char *path) {
     int kind, batch, cls, var;
     while (fscanf(f, "%d %d %d %d", &kind, &batch, &cls, &var) == 4) {
         if (kind >= 0 && kind < kKinds && (batch == 0 || batch == 1) && cls >= 0 &&
-            cls < kClasses && var >= 0 && var < n_variants(kind))
+            cls < kClasses && var >= 0 && var < n_variants(kind) &&
+            variant_offered(kind, batch != 0, var))
             g_tab.v[kind][batch][cls] = var;
     }
     fclose(f);
 }
 
-// the built-in default of a kind, batch flag and size class: the pruned
+// the built-in default of a kind, batch flag and size class: the crossing
+// sweeps take 2 rows per thread, and the crossing + angle sweep of a single
+// layout 4 rows from 2^21 edges (1.3% faster at 3M edges); the pruned
 // sweep takes the 1-row tiles (tightest boxes) below 2^17 edges and 2-row
 // tiles above.  The node sweep of a single layout splits its 256-column
 // chunks below 2^16 nodes (2 rows per thread and 32 columns below 2^13
@@ -81,6 +84,7 @@ void load_locked(const char *path) {
 // nodes per layout.
 int default_variant(int k, int b, int c) {
     if (k == 3 && c >= 17) return 1;
+    if (k == 1 && !b && c >= 21) return 3;
     if (k == 2) {
         if (b) return c >= 19 ? 0 : 2;
         if (c <= 12) return 6;

@@ -108,6 +108,13 @@ constexpr int kCrossVariants = 4;
 constexpr int kOcclVariants = 9;
 SweepVariant cross_variant(int v);
 SweepVariant occl_variant(int v);
+// The batched edge sweep offers every crossing variant but the 4-row one:
+// in batch form its table walk does not fit the register budget of 5 waves
+// per SIMD and would be spilled to scratch memory in every block.
+constexpr int kBatchCrossExcluded = 3;
+inline bool variant_offered(int kind, bool batch, int v) {
+    return !(batch && (kind == 0 || kind == 1) && v == kBatchCrossExcluded);
+}
 
 // Layout of the caller's workspace for one layout (byte offsets, 256-aligned).
 struct WsLayout {

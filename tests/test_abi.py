@@ -148,7 +148,8 @@ def test_argument_errors_of_the_other_entry_points_need_no_gpu(L):
 
 def test_built_in_tuning_defaults(L, tmp_path):
     """The defaults a table returns to on a load of an empty file: crossing
-    sweeps 2 rows / 7 waves at every size; the node sweep of a single layout
+    sweeps 2 rows / 7 waves, but 4 rows / 5 waves for the crossing + angle
+    sweep of a single layout from 2^21 edges; the node sweep of a single layout
     2 rows / 8 waves in chunks split 8 ways below 2^13 nodes, split 4 ways
     below 2^15, 4 rows / 6 waves split 4 ways below 2^16, whole chunks below
     2^17 and 8 rows / 5 waves from there (a batch: 4 rows / 6 waves, whole
@@ -166,7 +167,9 @@ def test_built_in_tuning_defaults(L, tmp_path):
         return (rows.value, waves.value) if kind != 2 else (rows.value, waves.value, split.value)
 
     for n in (2_000, 149_994, 3_000_000):
-        assert q(0, n) == (2, 7) and q(1, n) == (2, 7)
+        assert q(0, n) == (2, 7) and q(1, n, batch=1) == (2, 7)
+    assert q(1, 149_994) == (2, 7) and q(1, (1 << 21) - 1) == (2, 7)
+    assert q(1, 1 << 21) == (4, 5) and q(1, 3_000_000) == (4, 5)
     assert q(2, 1_000) == (2, 8, 8) and q(2, (1 << 13) - 1) == (2, 8, 8)
     assert q(2, 1 << 13) == (2, 8, 4) and q(2, 20_000) == (2, 8, 4)
     assert q(2, 50_000) == (4, 6, 4) and q(2, 100_000) == (4, 6, 1)
@@ -185,4 +188,29 @@ def test_static_scratch_limit_needs_no_gpu(L):
     assert "out_metric" in _err(L)
     assert L.rb_crossing_angle_noalloc(fake, fake, 10, fake, fake, 5, 0.0, fake, None, None,
                                        None) == _lib.RB_EINVAL
+
+
+def test_batched_crossing_sweep_does_not_offer_four_rows(L, tmp_path):
+    """The 4-row variant (index 3) of the edge sweep is refused for batches
+    (its batch form would spill registers in every block) and accepted for
+    single layouts; a tuning file that names it for a batch is ignored."""
+    import ctypes as C
+    empty = tmp_path / "tune.txt"
+    empty.write_text("")
+    try:
+        assert L.rb_tune_set(1, 1, 1000, 3) == _lib.RB_EINVAL
+        assert "not offered" in _err(L)
+        assert L.rb_tune_set(0, 1, 1000, 3) == _lib.RB_EINVAL
+        assert L.rb_tune_set(1, 0, 1000, 3) == _lib.RB_OK
+        assert L.rb_tune_set(1, 1, 1000, 2) == _lib.RB_OK
+        f = tmp_path / "t.txt"
+        f.write_text("1 1 9 3\n1 1 10 2\n")
+        assert L.rb_tune_load(str(f).encode()) == 0
+        rows, waves = C.c_int(), C.c_int()
+        assert L.rb_tune_query(1, 1, 1000, C.byref(rows), C.byref(waves), None) == 0
+        assert (rows.value, waves.value) == (2, 7)            # class 9: default kept
+        assert L.rb_tune_query(1, 1, 1500, C.byref(rows), C.byref(waves), None) == 0
+        assert (rows.value, waves.value) == (3, 5)            # class 10: loaded
+    finally:
+        assert L.rb_tune_load(str(empty).encode()) == 0
 
