@@ -17,7 +17,11 @@
  *                              0 <= id < n_nodes, src != dst, and no edge
  *                              listed twice (in either orientation).
  * These preconditions are not checked by the metric calls (their results are
- * only defined for valid input); rb_validate_layout checks all of them.
+ * only defined for valid input); rb_validate_layout checks all of them.  With
+ * the environment variable RB_VALIDATE set (to anything but "" or "0"),
+ * every call that takes a rb_workspace_size workspace checks them first and
+ * returns RB_EDOMAIN on a violation; those calls then synchronise `stream`
+ * and cannot be captured into a hipGraph (a debugging aid).
  * Limits: 0 <= n_nodes <= 2^31-1, 0 <= n_edges <= 2^30.
  *
  * ------------------------------------------------------------------ calls
@@ -38,8 +42,20 @@
  * Argument errors (NULL required pointer, negative or too large size, a bad
  * parameter, a workspace too small or misaligned) return RB_EINVAL or
  * RB_EWORKSPACE before anything is enqueued.  A failing HIP runtime call
- * returns RB_EHIP.  rb_last_error() then describes the failure (per host
- * thread; valid until the next call on that thread).
+ * returns RB_EHIP; a failed allocation of the library's own resources (a
+ * batch plan, a graph) RB_ENOMEM.  rb_last_error() then describes the
+ * failure (per host thread; valid until the next call on that thread).
+ *
+ * ------------------------------------------------------- fault injection
+ * For tests of callers' error paths, the environment variable RB_FAULT (a
+ * comma-separated list, read at each call) makes the library fail on
+ * purpose: "launch" -- every call that enqueues GPU work returns RB_EHIP
+ * after its argument checks and before its first HIP call (nothing is
+ * enqueued, outputs are untouched); "alloc" -- rb_batch_create and
+ * rb_batch_graph_create return RB_ENOMEM before allocating; "capture" --
+ * rb_batch_graph_create fails inside its stream capture (the capture is
+ * ended and discarded) and returns RB_EHIP.  rb_last_error() names the
+ * injected fault.
  */
 #ifndef RB_H
 #define RB_H
@@ -56,7 +72,8 @@ typedef enum rb_status {
     RB_EINVAL = 1,      /* bad argument                                     */
     RB_EWORKSPACE = 2,  /* workspace NULL, misaligned or too small          */
     RB_EDOMAIN = 3,     /* layout violates the preconditions (validation)   */
-    RB_EHIP = 4         /* a HIP runtime call or kernel launch failed       */
+    RB_EHIP = 4,        /* a HIP runtime call or kernel launch failed       */
+    RB_ENOMEM = 5       /* the library could not allocate its own resources */
 } rb_status;
 
 /* Library version string, e.g. "rb 1.0.0 gfx950". */

@@ -2,7 +2,8 @@
 
 Argument marshalling only.  The library must have been built with
 ``python -m paper_2411_09809_amd.build`` (or ``__graft_entry__.build()``);
-there is no fallback: a missing library raises ``RBError``.
+there is no fallback: a missing library raises ``RBError``.  The environment
+variable RB_LIBRARY may name another build of it.
 """
 from __future__ import annotations
 
@@ -11,11 +12,14 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librb.so")
+# RB_LIBRARY names another build of the same library (the host-sanitized one
+# of the CPU tests); by default the in-tree librb.so
+LIB_PATH = os.environ.get("RB_LIBRARY") or os.path.join(HERE, "librb.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "rb.h")
 
-RB_OK, RB_EINVAL, RB_EWORKSPACE, RB_EDOMAIN, RB_EHIP = range(5)
-STATUS_NAMES = {0: "RB_OK", 1: "RB_EINVAL", 2: "RB_EWORKSPACE", 3: "RB_EDOMAIN", 4: "RB_EHIP"}
+RB_OK, RB_EINVAL, RB_EWORKSPACE, RB_EDOMAIN, RB_EHIP, RB_ENOMEM = range(6)
+STATUS_NAMES = {0: "RB_OK", 1: "RB_EINVAL", 2: "RB_EWORKSPACE", 3: "RB_EDOMAIN", 4: "RB_EHIP",
+                5: "RB_ENOMEM"}
 
 
 class RBError(RuntimeError):

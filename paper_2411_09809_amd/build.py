@@ -31,9 +31,10 @@ FILE_FLAGS = {
 }
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
+def _compile(src: str, verbose: bool, extra=(), obj_dir: str = OBJ) -> str:
+    obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *CFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), *extra, "-c", src, "-o",
+           obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -59,5 +60,47 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer build of the same
+# sources, for the CPU tests of the argument and error paths: the host code
+# (argument checks, workspace carving, planning, tuning table, fault
+# injection) is instrumented, the device code is not.  Loaded through
+# RB_LIBRARY with the sanitizer runtime preloaded; never by the GPU paths.
+SAN_OBJ = os.path.join(HERE, "_build_san")
+SAN_LIB = os.path.join(SAN_OBJ, "librb_san.so")
+SAN_HOST = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
+            "-fsanitize=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-fno-sanitize-recover=undefined"]
+CLANGXX = os.environ.get("RB_CLANGXX", "/opt/rocm/llvm/bin/clang++")
+
+
+def sanitizer_runtime() -> str:
+    """Path of clang's shared AddressSanitizer runtime (to preload)."""
+    libdir = os.path.join(os.path.dirname(os.path.dirname(CLANGXX)), "lib", "clang")
+    for ver in sorted(os.listdir(libdir), reverse=True):
+        p = os.path.join(libdir, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(p):
+            return p
+    raise FileNotFoundError("libclang_rt.asan-x86_64.so not found under " + libdir)
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    os.makedirs(SAN_OBJ, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose, SAN_HOST, SAN_OBJ), srcs))
+    # linked by the host compiler: the objects carry their own device code
+    cmd = [CLANGXX, "-shared", "-fPIC", "-fsanitize=address,undefined", "-shared-libasan",
+           "-o", SAN_LIB + ".tmp", *objs, "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,/opt/rocm/lib"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(SAN_LIB + ".tmp", SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

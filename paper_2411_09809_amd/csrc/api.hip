@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <mutex>
@@ -127,6 +128,42 @@ int g_cu_count[64];
 
 }  // namespace
 
+// The layout checks of rb_validate_layout on `st`, waited for: RB_OK, or
+// RB_EDOMAIN with the violations named in the error text.
+rb_status validate_now(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
+                       const int32_t *dst, int64_t n_edges, const WsLayout &L, char *w,
+                       hipStream_t st, int32_t *out_flags) {
+    hipError_t e = launch_validate(x, y, n_nodes, src, dst, n_edges, L, w, st);
+    if (e != hipSuccess) return hip_fail(e, "validate launch");
+    Scalars sc;
+    e = hipMemcpyAsync(&sc, w + L.scalars, sizeof sc, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "validate copy");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "validate synchronize");
+    if (out_flags) *out_flags = sc.flags;
+    if (sc.flags) {
+        std::string msg = "invalid layout:";
+        if (sc.flags & 1) msg += " non-integer coordinate;";
+        if (sc.flags & 2) msg += " coordinate beyond 2^20;";
+        if (sc.flags & 4) msg += " edge end out of range;";
+        if (sc.flags & 8) msg += " self-loop;";
+        if (sc.flags & 16) msg += " duplicate edge;";
+        g_err = msg;
+        return RB_EDOMAIN;
+    }
+    return RB_OK;
+}
+
+// RB_VALIDATE set to anything but "" or "0": the calls that take a
+// rb_workspace_size workspace check the layout first (synchronously).
+rb_status validate_if_requested(const float *x, const float *y, int64_t n_nodes,
+                                const int32_t *src, const int32_t *dst, int64_t n_edges,
+                                const WsLayout &L, char *w, hipStream_t st) {
+    const char *v = getenv("RB_VALIDATE");
+    if (!v || !*v || (v[0] == '0' && v[1] == 0)) return RB_OK;
+    return validate_now(x, y, n_nodes, src, dst, n_edges, L, w, st, nullptr);
+}
+
 int set_error(int status, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -138,6 +175,26 @@ int set_error(int status, const char *fmt, ...) {
 }
 
 int hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+
+bool fault_listed(const char *site) {
+    const char *v = getenv("RB_FAULT");
+    if (!v || !*v) return false;
+    const size_t n = strlen(site);
+    for (const char *p = v; *p;) {
+        const char *q = strchr(p, ',');
+        const size_t len = q ? (size_t)(q - p) : strlen(p);
+        if (len == n && strncmp(p, site, n) == 0) return true;
+        if (!q) break;
+        p = q + 1;
+    }
+    return false;
+}
+
+int inject_fault(const char *site, const char *where) {
+    if (!fault_listed(site)) return RB_OK;
+    const rb_status s = strcmp(site, "alloc") == 0 ? RB_ENOMEM : RB_EHIP;
+    return fail(s, "%s: injected failure (RB_FAULT=%s); nothing was enqueued", where, site);
+}
 
 void clear_error() { g_err.clear(); }
 
@@ -229,6 +286,10 @@ rb_status rb_node_occlusion(const float *x, const float *y, int64_t n_nodes, dou
         return fail(RB_EINVAL, "diameter must be finite and >= 0");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, 0, &L))) return s;
+    if (const int f = inject_fault("launch", "rb_node_occlusion")) return (rb_status)f;
+    if ((s = validate_if_requested(x, y, n_nodes, nullptr, nullptr, 0, L, (char *)ws,
+                                   (hipStream_t)stream)))
+        return s;
     char *w = (char *)ws;
     return occlusion_launch(x, y, n_nodes, diameter, out_count, (NodeRec *)(w + L.node_rec),
                             L.n_node_pad, (OcclPartial *)(w + L.partial), (hipStream_t)stream, 1);
@@ -241,6 +302,7 @@ static rb_status occlusion_launch(const float *x, const float *y, int64_t n_node
                                   double diameter, uint64_t *out_count, NodeRec *rec,
                                   int64_t n_node_pad, OcclPartial *part, hipStream_t st,
                                   int timed_kind) {
+    if (const int f = inject_fault("launch", "rb_node_occlusion")) return (rb_status)f;
     const int v = tuned_variant(2, false, n_nodes);
     const int rows = occl_variant(v).rows, shift = occl_variant(v).col_shift;
     SweepArgs a;
@@ -278,6 +340,10 @@ static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes
     if (s) return s;
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    if (const int f = inject_fault("launch", "rb_edge_crossing / rb_crossing_angle")) return (rb_status)f;
+    if ((s = validate_if_requested(x, y, n_nodes, src, dst, n_edges, L, (char *)ws,
+                                   (hipStream_t)stream)))
+        return s;
     char *w = (char *)ws;
     return crossing_launch(x, y, n_nodes, src, dst, n_edges, angle, ideal, out_count, out_proper,
                            out_metric, out_dev_sum, (EdgeRec *)(w + L.edge_rec), L.n_edge_pad,
@@ -292,6 +358,7 @@ static rb_status crossing_launch(const float *x, const float *y, int64_t n_nodes
                                  uint64_t *out_proper, double *out_metric, double *out_dev_sum,
                                  EdgeRec *rec, int64_t n_edge_pad, CrossPartial *part,
                                  hipStream_t st) {
+    if (const int f = inject_fault("launch", "rb_edge_crossing / rb_crossing_angle")) return (rb_status)f;
     const int v = tuned_variant(angle ? 1 : 0, false, n_edges);
     const int rows = cross_variant(v).rows;
     SweepArgs a;
@@ -354,6 +421,10 @@ rb_status rb_crossing_angle_shard(const float *x, const float *y, int64_t n_node
         return fail(RB_EINVAL, "need 0 <= shard < n_shards");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    if (const int f = inject_fault("launch", "rb_crossing_angle_shard")) return (rb_status)f;
+    if ((s = validate_if_requested(x, y, n_nodes, src, dst, n_edges, L, (char *)ws,
+                                   (hipStream_t)stream)))
+        return s;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
     EdgeRec *rec = (EdgeRec *)(w + L.edge_rec);
@@ -399,6 +470,10 @@ rb_status rb_node_occlusion_shard(const float *x, const float *y, int64_t n_node
         return fail(RB_EINVAL, "need 0 <= shard < n_shards");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, 0, &L))) return s;
+    if (const int f = inject_fault("launch", "rb_node_occlusion_shard")) return (rb_status)f;
+    if ((s = validate_if_requested(x, y, n_nodes, nullptr, nullptr, 0, L, (char *)ws,
+                                   (hipStream_t)stream)))
+        return s;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
     NodeRec *rec = (NodeRec *)(w + L.node_rec);
@@ -451,6 +526,7 @@ rb_status rb_node_occlusion_grid(const float *x, const float *y, int64_t n_nodes
     if (((uintptr_t)ws & 255u) != 0) return fail(RB_EWORKSPACE, "workspace not 256-byte aligned");
     if (ws_bytes < G.total)
         return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, G.total);
+    if (const int f = inject_fault("launch", "rb_node_occlusion_grid")) return (rb_status)f;
     hipStream_t st = (hipStream_t)stream;
     if (n_nodes < kGridMinNodes) {     // the sweep costs less than the grid's passes
         const int64_t pad = (std::max<int64_t>(n_nodes, 1) + kRecPad - 1) / kRecPad * kRecPad;
@@ -486,6 +562,7 @@ rb_status rb_crossing_angle_pruned(const float *x, const float *y, int64_t n_nod
     if (((uintptr_t)ws & 255u) != 0) return fail(RB_EWORKSPACE, "workspace not 256-byte aligned");
     if (ws_bytes < G.total)
         return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, G.total);
+    if (const int f = inject_fault("launch", "rb_crossing_angle_pruned")) return (rb_status)f;
     hipStream_t st = (hipStream_t)stream;
     const int v = tuned_variant(3, false, n_edges);
     TimedLaunch tl(3, st);
@@ -577,6 +654,7 @@ rb_status rb_crossing_angle_noalloc(const float *x, const float *y, int64_t n_no
     if (n_edges > kNoAllocMaxEdges)
         return fail(RB_EINVAL, "n_edges = %lld exceeds the %lld edges the static scratch holds",
                     (long long)n_edges, (long long)kNoAllocMaxEdges);
+    if (const int f = inject_fault("launch", "rb_crossing_angle_noalloc")) return (rb_status)f;
     char *w = nullptr;
     if ((s = scratch_address(&w))) return s;
     const int64_t pad = (int64_t)round_up((size_t)std::max<int64_t>(n_edges, 1), kRecPad);
@@ -595,6 +673,10 @@ rb_status rb_min_angle(const float *x, const float *y, int64_t n_nodes, const in
     if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    if (const int f = inject_fault("launch", "rb_min_angle")) return (rb_status)f;
+    if ((s = validate_if_requested(x, y, n_nodes, src, dst, n_edges, L, (char *)ws,
+                                   (hipStream_t)stream)))
+        return s;
     hipError_t e = launch_min_angle(x, y, n_nodes, src, dst, n_edges,
                                     min_angle_bufs(L, (char *)ws), out_metric, out_sum_dv,
                                     (unsigned long long *)out_n_used, (hipStream_t)stream);
@@ -612,6 +694,10 @@ rb_status rb_edge_length_variation(const float *x, const float *y, int64_t n_nod
     if (!out_metric) return fail(RB_EINVAL, "out_metric is NULL");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    if (const int f = inject_fault("launch", "rb_edge_length_variation")) return (rb_status)f;
+    if ((s = validate_if_requested(x, y, n_nodes, src, dst, n_edges, L, (char *)ws,
+                                   (hipStream_t)stream)))
+        return s;
     char *w = (char *)ws;
     hipError_t e = launch_elv(x, y, src, dst, n_nodes, n_edges, (double *)(w + L.partial),
                               (Scalars *)(w + L.scalars), out_metric, out_mean,
@@ -636,6 +722,10 @@ rb_status rb_loss_grad(const float *x, const float *y, int64_t n_nodes, const in
         return fail(RB_EINVAL, "weights must be finite");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    if (const int f = inject_fault("launch", "rb_loss_grad")) return (rb_status)f;
+    if ((s = validate_if_requested(x, y, n_nodes, src, dst, n_edges, L, (char *)ws,
+                                   (hipStream_t)stream)))
+        return s;
     hipError_t e = launch_loss_grad(x, y, n_nodes, src, dst, n_edges, ideal_angle, w_angle,
                                     w_length, w_min_angle, out_loss, out_grad_x, out_grad_y,
                                     (unsigned long long *)out_count, L, (char *)ws,
@@ -668,6 +758,7 @@ rb_status rb_loss_grad_pruned(const float *x, const float *y, int64_t n_nodes,
     if (((uintptr_t)ws & 255u) != 0) return fail(RB_EWORKSPACE, "workspace not 256-byte aligned");
     if (ws_bytes < G.total)
         return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, G.total);
+    if (const int f = inject_fault("launch", "rb_loss_grad_pruned")) return (rb_status)f;
     hipError_t e = launch_loss_grad_pruned(x, y, n_nodes, src, dst, n_edges, ideal_angle,
                                            w_angle, w_length, w_min_angle, out_loss, out_grad_x,
                                            out_grad_y,
@@ -699,6 +790,7 @@ rb_status rb_enhanced_crossing(const float *x, const float *y, int64_t n_nodes,
     if (ws_bytes < strip_ws_bytes(n_edges, 0))
         return fail(RB_EWORKSPACE, "workspace of %zu bytes, %zu needed to count pieces", ws_bytes,
                     strip_ws_bytes(n_edges, 0));
+    if (const int f = inject_fault("launch", "rb_enhanced_crossing")) return (rb_status)f;
     hipStream_t st = (hipStream_t)stream;
     const float *px = horizontal ? y : x, *py = horizontal ? x : y;   // strips across x
     hipError_t e = launch_strip_count(px, py, src, dst, n_nodes, n_edges, width, (char *)ws, st);
@@ -731,31 +823,11 @@ rb_status rb_validate_layout(const float *x, const float *y, int64_t n_nodes, co
     if (s) return s;
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
-    hipStream_t st = (hipStream_t)stream;
-    char *w = (char *)ws;
-    hipError_t e = launch_validate(x, y, n_nodes, src, dst, n_edges, L, w, st);
-    if (e != hipSuccess) return hip_fail(e, "validate launch");
-    Scalars sc;
-    e = hipMemcpyAsync(&sc, w + L.scalars, sizeof sc, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return hip_fail(e, "validate copy");
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "validate synchronize");
-    if (out_flags) *out_flags = sc.flags;
-    if (sc.flags) {
-        std::string msg = "invalid layout:";
-        if (sc.flags & 1) msg += " non-integer coordinate;";
-        if (sc.flags & 2) msg += " coordinate beyond 2^20;";
-        if (sc.flags & 4) msg += " edge end out of range;";
-        if (sc.flags & 8) msg += " self-loop;";
-        if (sc.flags & 16) msg += " duplicate edge;";
-        g_err = msg;
-        return RB_EDOMAIN;
-    }
-    return RB_OK;
+    if (const int f = inject_fault("launch", "rb_validate_layout")) return (rb_status)f;
+    return validate_now(x, y, n_nodes, src, dst, n_edges, L, (char *)ws, (hipStream_t)stream,
+                        out_flags);
 }
 
-// Times every sweep variant on this layout (after one untimed launch each)
-// and records the fastest for the layout's size class.  Synchronises.
 rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                       const int32_t *dst, int64_t n_edges, double diameter, double ideal_angle,
                       int repeats, double *out_best_ms, void *ws, size_t ws_bytes, void *stream) {
@@ -769,6 +841,10 @@ rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes, const int
     if (repeats < 1 || repeats > 1000) return fail(RB_EINVAL, "repeats must be in [1, 1000]");
     WsLayout L;
     if ((s = check_ws(ws, ws_bytes, n_nodes, n_edges, &L))) return s;
+    if (const int f = inject_fault("launch", "rb_autotune")) return (rb_status)f;
+    if ((s = validate_if_requested(x, y, n_nodes, src, dst, n_edges, L, (char *)ws,
+                                   (hipStream_t)stream)))
+        return s;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
     EdgeRec *erec = (EdgeRec *)(w + L.edge_rec);
@@ -898,6 +974,7 @@ rb_status rb_valu_probe(int iters, int repeats, double *out_lane_ops_per_s, doub
     if (iters < 1 || iters > (1 << 24) || repeats < 1 || repeats > 1000)
         return fail(RB_EINVAL, "iters must be in [1, 2^24] and repeats in [1, 1000]");
     if (!out_lane_ops_per_s || !sink) return fail(RB_EINVAL, "out_lane_ops_per_s or sink is NULL");
+    if (const int f = inject_fault("launch", "rb_valu_probe")) return (rb_status)f;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     double ops = 0.0;

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "rb.h"
@@ -540,7 +541,10 @@ rb_status rb_batch_create(int64_t n_layouts, const int64_t *node_off, const int6
     }
     if (node_off[n_layouts] > 2147483647LL || edge_off[n_layouts] > (1LL << 30))
         return (rb_status)set_error(RB_EINVAL, "batch too large");
-    rb_batch *b = new rb_batch;
+    if (const int f = inject_fault("alloc", "rb_batch_create")) return (rb_status)f;
+    rb_batch *b = new (std::nothrow) rb_batch;
+    if (!b) return (rb_status)set_error(RB_ENOMEM, "rb_batch_create: out of host memory");
+    try {
     b->B = n_layouts;
     b->node_off.assign(node_off, node_off + n_layouts + 1);
     b->edge_off.assign(edge_off, edge_off + n_layouts + 1);
@@ -560,6 +564,10 @@ rb_status rb_batch_create(int64_t n_layouts, const int64_t *node_off, const int6
     b->cross_var = tuned_variant(1, true, mean_e);
     b->occl_var = tuned_variant(2, true, mean_v);
     carve(b);
+    } catch (const std::bad_alloc &) {
+        delete b;
+        return (rb_status)set_error(RB_ENOMEM, "rb_batch_create: out of host memory");
+    }
     *out = b;
     return RB_OK;
 }
@@ -572,6 +580,7 @@ rb_status rb_batch_upload(rb_batch *b, void *ws, size_t ws_bytes, void *stream) 
     if (!ws || ((uintptr_t)ws & 255u) != 0 || ws_bytes < b->total)
         return (rb_status)set_error(RB_EWORKSPACE, "workspace NULL, misaligned or below %zu bytes",
                                     b->total);
+    if (const int f = inject_fault("launch", "rb_batch_upload")) return (rb_status)f;
     hipError_t e = upload(b, ws, (hipStream_t)stream);
     if (e != hipSuccess) return (rb_status)hip_error(e, "rb_batch_upload");
     return RB_OK;
@@ -587,6 +596,7 @@ rb_status rb_batch_evaluate(const rb_batch *b, const float *x, const float *y, c
                (unsigned long long *)out_crossings, out_crossing_angle, out_min_angle, out_elv};
     rb_status s = check_io(b, io, ws, ws_bytes);
     if (s) return s;
+    if (const int f = inject_fault("launch", "rb_batch_evaluate")) return (rb_status)f;
     hipError_t e = enqueue_all(b, (char *)ws, io, (hipStream_t)stream);
     if (e != hipSuccess) return (rb_status)hip_error(e, "rb_batch_evaluate");
     return RB_OK;
@@ -601,6 +611,7 @@ rb_status rb_batch_autotune(rb_batch *b, const float *x, const float *y, const i
     if (s) return s;
     if (repeats < 1 || repeats > 1000)
         return (rb_status)set_error(RB_EINVAL, "repeats must be in [1, 1000]");
+    if (const int f = inject_fault("launch", "rb_batch_autotune")) return (rb_status)f;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
     hipError_t e = enqueue_prep(b, w, io, st);
@@ -677,13 +688,21 @@ rb_status rb_batch_graph_create(const rb_batch *b, const float *x, const float *
                (unsigned long long *)out_crossings, out_crossing_angle, out_min_angle, out_elv};
     rb_status s = check_io(b, io, ws, ws_bytes);
     if (s) return s;
+    if (const int f = inject_fault("alloc", "rb_batch_graph_create")) return (rb_status)f;
+    rb_graph *g = new (std::nothrow) rb_graph;
+    if (!g) return (rb_status)set_error(RB_ENOMEM, "rb_batch_graph_create: out of host memory");
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) return (rb_status)hip_error(e, "capture stream");
+    if (e != hipSuccess) {
+        delete g;
+        return (rb_status)hip_error(e, "capture stream");
+    }
     hipGraph_t graph = nullptr;
+    bool injected = false;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e2 = enqueue_all(b, (char *)ws, io, cs);
+        injected = fault_listed("capture");
+        hipError_t e2 = injected ? hipErrorUnknown : enqueue_all(b, (char *)ws, io, cs);
         e = hipStreamEndCapture(cs, &graph);
         if (e2 != hipSuccess) e = e2;
     }
@@ -692,9 +711,12 @@ rb_status rb_batch_graph_create(const rb_batch *b, const float *x, const float *
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        if (injected)
+            return (rb_status)set_error(RB_EHIP, "rb_batch_graph_create: injected failure "
+                                                 "(RB_FAULT=capture) inside the capture");
         return (rb_status)hip_error(e, "rb_batch_graph_create");
     }
-    rb_graph *g = new rb_graph;
     g->graph = graph;
     g->exec = exec;
     g->batch = b;
@@ -711,6 +733,7 @@ rb_status rb_graph_launch(rb_graph *g, void *stream) {
                                     "the batch plan was uploaded again (rb_batch_upload or "
                                     "rb_batch_autotune) after this graph was captured: "
                                     "capture a new graph");
+    if (const int f = inject_fault("launch", "rb_graph_launch")) return (rb_status)f;
     hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
     if (e != hipSuccess) return (rb_status)hip_error(e, "rb_graph_launch");
     return RB_OK;

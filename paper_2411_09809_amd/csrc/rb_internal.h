@@ -194,6 +194,11 @@ inline MinAngleBufs min_angle_bufs(const GridWs &G, char *w) {
             (int32_t *)(w + G.big_list), (Scalars *)(w + G.scalars), (double *)(w + G.partial)};
 }
 
+// Fault injection (RB_FAULT, see rb.h): nonzero when `site` is listed;
+// then the error text names `where` and the site.
+bool fault_listed(const char *site);
+int inject_fault(const char *site, const char *where);
+
 // ------------------------------------------------------------------ plans
 struct SweepPlan {
     int variant;
