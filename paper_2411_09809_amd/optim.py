@@ -80,7 +80,8 @@ def descent_step(mx, my, gx, gy, step_size: float):
 def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
             extent: int = 1 << 16, ideal_angle: float = IDEAL_ANGLE, w_angle: float = 1.0,
             w_length: float = 1.0, log=None, pruned: bool = False, w_min_angle: float = 0.0,
-            trace: list | None = None):
+            trace: list | None = None, checkpoint: str | None = None,
+            checkpoint_every: int = 10, resume: str | None = None):
     """Gradient descent on the readability loss.
 
     A float32 master copy of the coordinates moves by ``step_size`` grid
@@ -91,13 +92,38 @@ def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
     The steps are enqueued without waiting for the GPU unless ``log`` is
     given (it is called with each step's entry as soon as it is known).
     With ``trace`` (a list), each step's evaluated integer layout is appended
-    to it as a pair of device tensors."""
+    to it as a pair of device tensors.
+
+    ``checkpoint`` (a file name) saves the master coordinates and the number
+    of steps taken (numpy ``.npz``) every ``checkpoint_every`` steps and after
+    the last; ``resume`` starts from such a file, taking the steps that
+    remain of ``steps`` (the history then covers those steps only).  A run
+    cut into pieces this way ends where the uninterrupted run ends: each
+    step depends only on the master coordinates."""
+    import os
+
+    import numpy as np
     mx = x.detach().clone().to(torch.float32)
     my = y.detach().clone().to(torch.float32)
+    first = 0
+    if resume is not None:
+        with np.load(resume) as z:
+            if z["mx"].shape != tuple(mx.shape):
+                raise ValueError(f"{resume}: {z['mx'].shape[0]} nodes, the layout has "
+                                 f"{mx.shape[0]}")
+            mx.copy_(torch.from_numpy(z["mx"]))
+            my.copy_(torch.from_numpy(z["my"]))
+            first = int(z["step"])
+
+    def save(done):
+        tmp = checkpoint + ".tmp.npz"
+        np.savez(tmp, mx=mx.cpu().numpy(), my=my.cpu().numpy(), step=np.int64(done))
+        os.replace(tmp, checkpoint)
+
     marks = [torch.cuda.Event(enable_timing=True)]
     marks[0].record()
     vals, hist = [], []
-    for k in range(steps):
+    for k in range(first, steps):
         xi = torch.clamp(torch.round(mx), 0, extent - 1).requires_grad_(True)
         yi = torch.clamp(torch.round(my), 0, extent - 1).requires_grad_(True)
         loss, cnt = CrossingAngleLengthLoss.apply(xi, yi, src, dst, ideal_angle, w_angle,
@@ -115,6 +141,8 @@ def descend(x, y, src, dst, steps: int = 100, step_size: float = 2.0,
             ev.synchronize()
             hist.append((float(loss), int(cnt), marks[-2].elapsed_time(ev) * 1e-3))
             log(k, hist[-1])
+        if checkpoint and ((k + 1) % checkpoint_every == 0 or k + 1 == steps):
+            save(k + 1)
     if not log:
         marks[-1].synchronize()
         hist = [(float(l), int(c), marks[i].elapsed_time(marks[i + 1]) * 1e-3)

@@ -78,3 +78,28 @@ def test_the_loss_goes_down(trajectory):
     _, _, hist = trajectory
     assert len(hist) == STEPS
     assert min(h[0] for h in hist[1:]) < hist[0][0]
+
+
+def test_checkpoint_and_resume(tmp_path):
+    """A run saved after 4 steps and resumed to 7: the resumed run's first
+    evaluated layout is the saved one (rounded), it takes the 3 remaining
+    steps, and its exact counts are the oracle's."""
+    import torch
+    from paper_2411_09809_amd import metrics, optim
+    L = gen.uniform_layout(600, 1500, extent=1 << 12, seed=17)
+    D = metrics.DeviceLayout.from_host(L)
+    f = str(tmp_path / "descent.npz")
+    xa, ya, ha = optim.descend(D.x, D.y, D.src, D.dst, steps=4, step_size=4.0,
+                               extent=1 << 12, checkpoint=f, checkpoint_every=2)
+    z = np.load(f)
+    assert int(z["step"]) == 4 and len(ha) == 4
+    assert (np.clip(np.round(z["mx"]), 0, 4095) == xa.cpu().numpy()).all()
+    assert (np.clip(np.round(z["my"]), 0, 4095) == ya.cpu().numpy()).all()
+    trace = []
+    xb, yb, hb = optim.descend(D.x, D.y, D.src, D.dst, steps=7, step_size=4.0, extent=1 << 12,
+                               resume=f, trace=trace)
+    assert len(hb) == 3 and len(trace) == 3
+    assert torch.equal(trace[0][0], xa) and torch.equal(trace[0][1], ya)
+    for (xi, yi), h in zip(trace, hb):
+        c, _ = oracle.edge_crossing(xi.cpu().numpy(), yi.cpu().numpy(), L.src, L.dst)
+        assert h[1] == c

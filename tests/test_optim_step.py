@@ -1,5 +1,6 @@
 """The descent update of ``optim.descend`` on the CPU (pure torch; the loss
 and gradient themselves need the GPU)."""
+import pytest
 import torch
 
 from paper_2411_09809_amd import optim
@@ -24,3 +25,13 @@ def test_step_moves_the_largest_component_by_step_size():
     gy = torch.tensor([1.0, 0.0])
     optim.descent_step(mx, my, gx, gy, 4.0)
     assert mx.tolist() == [4.0, 9.0] and my.tolist() == [3.0, 5.0]
+
+
+def test_resume_from_a_file_of_another_size_is_refused(tmp_path):
+    import numpy as np
+    f = tmp_path / "ck.npz"
+    np.savez(f, mx=np.zeros(5, np.float32), my=np.zeros(5, np.float32), step=np.int64(3))
+    x = torch.zeros(7)
+    e = torch.zeros(0, dtype=torch.int32)
+    with pytest.raises(ValueError, match="5 nodes"):
+        optim.descend(x, x, e, e, steps=4, resume=str(f))
