@@ -51,11 +51,11 @@ __device__ __forceinline__ int add_mask_bits(int k, uint64_t plus, uint64_t minu
 template <int K, bool DIAG>
 __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                                               const int2 *__restrict__ rid,
-                                              int *__restrict__ colk, const double (&rX)[K],
+                                              int8_t *__restrict__ colk, const double (&rX)[K],
                                               const double (&rY)[K], const double (&rDX)[K],
                                               const double (&rDY)[K], const double (&rC)[K],
                                               const double (&rTH)[K], int (&kr)[K], int tid,
-                                              int64_t row0, int64_t col0, double ideal,
+                                              int diag_off, double ideal,
                                               double angc, uint32_t &n_proper,
                                               uint32_t &n_touch, double &acc) {
     const int wave = tid >> 6, lane = tid & 63;
@@ -75,7 +75,9 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             const double p12 = o1 * (o1 + cr);
             const double p34 = o3 * (o3 - cr);
             const double m = fmax(p12, p34);
-            const bool in_tri = !DIAG || (col0 + j > row0 + (int64_t)r * kBlock);
+            // a diagonal unit keeps column index > row index: with the tile's
+            // first row as origin, diag_off + j > r * 256 + tid
+            const bool in_tri = !DIAG || (diag_off + j > r * kBlock + tid);
             const bool closed = (m < 0.0) & in_tri;
             zr[r] = (m == 0.0) & in_tri;
             const double u = fabs(rTH[r] - cTH) - kHalfPi;
@@ -122,7 +124,7 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                           (int)__popcll(__builtin_amdgcn_ballot_w64(neg));
             }
         }
-        if (lane == 0) colk[wave * kChunk + j] = colsum;
+        if (lane == 0) colk[wave * kChunk + j] = (int8_t)colsum;   // |colsum| <= 64 K
     }
 }
 
@@ -135,7 +137,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     double ideal, int *__restrict__ kacc, CrossPartial *__restrict__ part) {
     __shared__ EdgeRec col[kChunk];
     __shared__ int2 rid[kBlock * K];
-    __shared__ int colk[(kBlock / 64) * kChunk];
+    // per-wave column sums of q: |sum| <= 64 K fits a byte, which keeps the
+    // block's LDS under 20 KB (8 blocks per CU)
+    __shared__ int8_t colk[(kBlock / 64) * kChunk];
     __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
     __shared__ double red_d[kBlock / 64];
     const int tid = threadIdx.x;
@@ -201,14 +205,20 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
             }
             rows_loaded = true;
         }
-        col[tid] = rec[c * kChunk + tid];
+        {
+            // the lane's staging address is rebuilt each unit, not held across the sweep
+            int lane_rec = tid;
+            __asm__ volatile("" : "+v"(lane_rec));
+            col[tid] = rec[c * kChunk + lane_rec];
+        }
         __syncthreads();
-        const int64_t row0 = I * R + tid, col0 = c * kChunk;
+        const int64_t col0 = c * kChunk;
+        const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
-            adjoint_chunk<K, true>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, row0, col0,
+            adjoint_chunk<K, true>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, diag_off,
                                    ideal, angc, n_p, n_t, acc);
         else
-            adjoint_chunk<K, false>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, row0, col0,
+            adjoint_chunk<K, false>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, diag_off,
                                     ideal, angc, n_p, n_t, acc);
         tot_p += n_p;
         tot_t += n_t;
@@ -310,7 +320,8 @@ int grid_for(int64_t n) {
     return (int)g;
 }
 
-constexpr int kAdjRows = 1, kAdjWaves = 7;
+constexpr int kAdjRows = 1, kAdjWaves = 8;
+static_assert(64 * kAdjRows <= 127, "per-wave column sums are stored as int8_t");
 int g_adj_list_grid = 0;
 
 #define RB_TRY(expr)                          \
