@@ -319,7 +319,7 @@ static rb_status occlusion_launch(const float *x, const float *y, int64_t n_node
     e = launch_occl_sweep(v, rec, a, grid, part, st);
     tl.done();
     if (e != hipSuccess) return hip_fail(e, "occlusion sweep launch");
-    e = launch_occl_finalize(part, grid, (unsigned long long *)out_count, st);
+    e = launch_occl_finalize(part, grid, (unsigned long long *)out_count, true, st);
     if (e != hipSuccess) return hip_fail(e, "occlusion finalize launch");
     return RB_OK;
 }
@@ -499,7 +499,7 @@ rb_status rb_node_occlusion_shard(const float *x, const float *y, int64_t n_node
         e = launch_occl_sweep(v, rec, a, grid, part, st);
         if (e != hipSuccess) return hip_fail(e, "occlusion sweep launch");
     }
-    e = launch_occl_finalize(part, grid, (unsigned long long *)out_count, st);
+    e = launch_occl_finalize(part, grid, (unsigned long long *)out_count, true, st);
     if (e != hipSuccess) return hip_fail(e, "occlusion finalize launch");
     return RB_OK;
 }

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void batch_occl_finalize_kernel(
         if (tid < s) sc[tid] += sc[tid + s];
         __syncthreads();
     }
-    if (tid == 0) out_count[L] = sc[0];
+    if (tid == 0) out_count[L] = sc[0] >> 1;       // the sweep's slots hold twice the count
 }
 
 // Algorithm 3 for one layout per block: mean, then the spread about it.

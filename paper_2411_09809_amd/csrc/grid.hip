@@ -604,7 +604,7 @@ hipError_t launch_occlusion_grid(const float *x, const float *y, int64_t n, doub
     hipLaunchKernelGGL(occl_grid_count_kernel, dim3(blocks), dim3(256), 0, st, keys, pos, n,
                        (long long)T, part);
     RB_TRY(hipGetLastError());
-    return launch_occl_finalize(part, blocks, out_count, st);
+    return launch_occl_finalize(part, blocks, out_count, false, st);
 }
 
 }  // namespace rb

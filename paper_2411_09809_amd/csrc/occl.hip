@@ -3,8 +3,9 @@
 //
 // Same decomposition as the edge sweep: a row tile of R = 256*K nodes held in
 // registers (K per thread) against chunks of W nodes staged in LDS, over the upper
-// triangle of each layout, one block per equal contiguous range of the unit
-// list of all layouts (many more blocks than the chip holds at once).  W is
+// triangle of each layout (row tiles against their own and later chunks), one
+// block per equal contiguous range of the unit list of all layouts (many more
+// blocks than the chip holds at once).  W is
 // 256, or 256/S for the variants that split chunks S ways: a layout of some
 // ten thousand nodes has only a few thousand 256-column units, a few per
 // block slot, and the last round of blocks would leave most of the chip idle.
@@ -27,11 +28,36 @@ __device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int64_t K
     return I * nC - KS * I * (I - 1) / 2;
 }
 
-template <int K, bool DIAG>
+// floor(U b / G), the first unit of block b, from a double-precision estimate
+// corrected in integers.  The 64-bit division the compiler emits otherwise is
+// a sequence of some hundred scalar instructions, run by every wave of every
+// block, and the scalar unit is shared by the whole CU.
+__device__ __forceinline__ int64_t first_unit(int64_t U, int64_t G, int64_t b) {
+    const int64_t p = U * b;
+    int64_t q = (int64_t)((double)U * (double)b * __builtin_amdgcn_rcp((double)G));
+    while (q > 0 && q * G > p) --q;
+    while ((q + 1) * G <= p) ++q;
+    return q;
+}
+
+// Row tile of local unit lu: the largest I with units_before(I) <= lu, from
+// the smaller root of units_before(I) = lu (a quadratic in I) corrected in
+// integers, in place of a binary search over the tiles.
+__device__ __forceinline__ int64_t tile_of_unit(int64_t lu, int64_t nI, int64_t nC, int64_t KS) {
+    const double B = (double)nC + 0.5 * (double)KS;
+    const double disc = fmax(B * B - 2.0 * (double)KS * (double)lu, 0.0);
+    int64_t I = (int64_t)((B - sqrt(disc)) * __builtin_amdgcn_rcp((double)KS));
+    I = I < 0 ? 0 : (I > nI - 1 ? nI - 1 : I);
+    while (I > 0 && units_before(I, nC, KS) > lu) --I;
+    while (I + 1 < nI && units_before(I + 1, nC, KS) <= lu) ++I;
+    return I;
+}
+
+// Ordered pairs (row, column) of a chunk that occlude, counted exactly.
+template <int K>
 __device__ __forceinline__ uint32_t occl_count(const NodeRec *__restrict__ col, int W,
                                                const double (&rX)[K], const double (&rY)[K],
-                                               const double (&rH)[K], int64_t row0,
-                                               int64_t col0) {
+                                               const double (&rH)[K]) {
     uint32_t n = 0;
     for (int j0 = 0; j0 < W; j0 += 4) {          // W is a multiple of 4
 #pragma unroll
@@ -41,13 +67,56 @@ __device__ __forceinline__ uint32_t occl_count(const NodeRec *__restrict__ col, 
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 const double g = fma(rX[r], cX, fma(rY[r], cY, cQ));
-                bool hit = g >= rH[r];
-                if (DIAG) hit = hit & (col0 + j > row0 + (int64_t)r * kBlock);
-                n += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+                n += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(g >= rH[r]));
             }
         }
     }
     return n;
+}
+
+// A chunk of the row tile's own diagonal square: every ordered pair, less
+// the self pairs of the rows that fall in this chunk.  Over the KS chunks of
+// the square this counts each occluding unordered pair of the tile twice: the
+// exact integer test is symmetric in the two nodes.  Masking the lower
+// triangle instead costs a 64-bit index compare, a select and scalar work per
+// pair.  A self pair evaluates to g = x^2 + y^2 + q = n/2 exactly (q = -n/2,
+// n = x^2 + y^2, all integers or halves below 2^53), so the pair the count
+// took is n >= 2h, decided here from the row's own registers.
+// dk: first row of the tile less first column of the chunk (both within the
+// tile's own range, so |dk| < R).
+template <int K>
+__device__ __forceinline__ uint32_t occl_square(const NodeRec *__restrict__ col, int W,
+                                                const double (&rX)[K], const double (&rY)[K],
+                                                const double (&rH)[K], int dk) {
+    uint32_t n = occl_count<K>(col, W, rX, rY, rH);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const int k = dk + (int)threadIdx.x + r * kBlock;
+        const bool self = k >= 0 && k < W && fma(rX[r], rX[r], rY[r] * rY[r]) >= 2.0 * rH[r];
+        n -= (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(self));
+    }
+    return n;
+}
+
+// A batch table entry read into scalar registers.  The kernel stores to
+// global memory, so the compiler cannot use a scalar load for the table and
+// would keep the entry in vector registers, live across the whole sweep of a
+// unit.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ SweepLayout table_entry(const SweepLayout *tab, int64_t L) {
+    const SweepLayout t = tab[L];
+    SweepLayout l;
+    l.unit_off = uniform64(t.unit_off);
+    l.rec_off = uniform64(t.rec_off);
+    l.n_row_tiles = uniform64(t.n_row_tiles);
+    l.n_chunks = uniform64(t.n_chunks);
+    l.col_shift = uniform64(t.col_shift);
+    return l;
 }
 
 // max of two doubles as one instruction: the compiler's fmax also quiets NaN
@@ -62,8 +131,7 @@ __device__ __forceinline__ double max2(double a, double b) {
 template <int K>
 __device__ __forceinline__ uint32_t occl_chunk(const NodeRec *__restrict__ col, int W,
                                                const double (&rX)[K], const double (&rY)[K],
-                                               const double (&rH)[K], int64_t row0,
-                                               int64_t col0) {
+                                               const double (&rH)[K]) {
     double gmax[K];
 #pragma unroll
     for (int r = 0; r < K; ++r) gmax[r] = -HUGE_VAL;
@@ -80,18 +148,29 @@ __device__ __forceinline__ uint32_t occl_chunk(const NodeRec *__restrict__ col, 
 #pragma unroll
     for (int r = 0; r < K; ++r) any |= gmax[r] >= rH[r];
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(any) == 0, 1)) return 0;
-    return occl_count<K, false>(col, W, rX, rY, rH, row0, col0);
+    return occl_count<K>(col, W, rX, rY, rH);
 }
 
+// Partial slots hold twice the count: off-diagonal chunks add 2n, the
+// diagonal squares their ordered pairs.  The finalize halves the total.
+//
+// A block starts at raised wave priority and drops it once its rows and first
+// column chunk are in: at equal priority the waves already sweeping take
+// nearly every issue slot, and a new block's start-up (unit position, loads,
+// barriers) stretched to about as long as its sweep.  Each unit's successor
+// chunk is fetched into registers while the unit is swept, except in the
+// batched 8-row form, whose register budget at 5 waves per SIMD leaves no
+// room for it (it would spill).
 template <int K, int WAVES, bool BATCH>
 __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
     const NodeRec *__restrict__ rec, SweepArgs a, OcclPartial *__restrict__ part) {
+    __builtin_amdgcn_s_setprio(3);
     __shared__ NodeRec col[kChunk];
     __shared__ unsigned long long red[kBlock / 64];
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t u_begin = a.unit_base + block_first_unit(a.n_units, G, b);
-    const int64_t u_end = a.unit_base + block_first_unit(a.n_units, G, b + 1);
+    const int64_t u_begin = a.unit_base + first_unit(a.n_units, G, b);
+    const int64_t u_end = a.unit_base + first_unit(a.n_units, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
 
     int64_t L = 0;
@@ -104,23 +183,23 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
         }
         L = lo;
     }
-    SweepLayout lay = BATCH ? a.table[L] : a.single;
+    SweepLayout lay = BATCH ? table_entry(a.table, L) : a.single;
     int W = kChunk >> lay.col_shift;               // columns per unit
     int64_t KS = (int64_t)K << lay.col_shift;      // chunks spanned by a row tile
     const int64_t lu = u_begin - lay.unit_off;
-    int64_t lo = 0, hi = lay.n_row_tiles - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (units_before(mid, lay.n_chunks, KS) <= lu) lo = mid;
-        else hi = mid - 1;
-    }
-    int64_t I = lo;
+    int64_t I = tile_of_unit(lu, lay.n_row_tiles, lay.n_chunks, KS);
     int64_t c = I * KS + (lu - units_before(I, lay.n_chunks, KS));
 
     double rX[K], rY[K], rH[K];
     bool rows_loaded = false;
     unsigned long long tot = 0;
     int64_t seg_units = 0;
+    constexpr bool PF = !(BATCH && K == 8);
+    double nX = 0.0, nY = 0.0, nQ = 0.0;           // this thread's record of the next chunk
+    if (PF && u_begin < u_end && tid < W) {
+        const NodeRec &v = rec[lay.rec_off + c * W + tid];
+        nX = v.x; nY = v.y; nQ = v.q;
+    }
 
     auto flush = [&](int64_t slot) {
         const int wave = tid >> 6, lane = tid & 63;
@@ -138,6 +217,10 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
     };
 
     for (int64_t u = u_begin; u < u_end; ++u) {
+        if (!PF && tid < W) {
+            const NodeRec &v = rec[lay.rec_off + c * W + tid];
+            nX = v.x; nY = v.y; nQ = v.q;
+        }
         if (!rows_loaded) {
 #pragma unroll
             for (int r = 0; r < K; ++r) {
@@ -147,29 +230,47 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
             rows_loaded = true;
         }
         __syncthreads();
-        if (tid < W) col[tid] = rec[lay.rec_off + c * W + tid];
+        if (tid < W) {
+            col[tid].x = nX;
+            col[tid].y = nY;
+            col[tid].q = nQ;
+        }
         __syncthreads();
-        const int64_t row0 = I * R + tid, col0 = c * W;
-        if (c < (I + 1) * KS) tot += occl_count<K, true>(col, W, rX, rY, rH, row0, col0);
-        else tot += occl_chunk<K>(col, W, rX, rY, rH, row0, col0);
-        ++seg_units;
+        __builtin_amdgcn_s_setprio(0);
+        const int Wu = W;
+        const bool diag = c < (I + 1) * KS;
+        const int dk = (int)(I * R - c * W);       // used only when diag: |dk| < R
+        // step to the next unit (possibly of the next layout) and fetch its chunk
+        bool layout_done = false;
         if (++c == lay.n_chunks) {
             ++I;
             c = I * KS;
             rows_loaded = false;
-            if (BATCH && I == lay.n_row_tiles) {
-                flush(b + L);
-                seg_units = 0;
-                ++L;
-                if (L < a.n_layouts) {
-                    lay = a.table[L];
-                    W = kChunk >> lay.col_shift;
-                    KS = (int64_t)K << lay.col_shift;
-                }
-                I = 0;
-                c = 0;
-            }
+            layout_done = BATCH && I == lay.n_row_tiles;
         }
+        const int64_t L_unit = L;
+        if (layout_done) {
+            ++L;
+            if (L < a.n_layouts) {
+                lay = table_entry(a.table, L);
+                W = kChunk >> lay.col_shift;
+                KS = (int64_t)K << lay.col_shift;
+            }
+            I = 0;
+            c = 0;
+        }
+        if (PF && u + 1 < u_end && tid < W) {
+            const NodeRec &v = rec[lay.rec_off + c * W + tid];
+            nX = v.x; nY = v.y; nQ = v.q;
+        }
+        if (diag) tot += occl_square<K>(col, Wu, rX, rY, rH, dk);
+        else tot += 2 * (unsigned long long)occl_chunk<K>(col, Wu, rX, rY, rH);
+        ++seg_units;
+        if (layout_done) {
+            flush(b + L_unit);
+            seg_units = 0;
+        }
+        __builtin_amdgcn_s_setprio(3);
     }
     if (seg_units > 0) flush(BATCH ? b + L : b);
 }
@@ -193,9 +294,10 @@ __global__ __launch_bounds__(256) void occl_fold_kernel(OcclPartial *__restrict_
     if (tid == 0) part[base].count = s[0];
 }
 
-// Sum of n slots part[0], part[stride], ...
+// Sum of n slots part[0], part[stride], ..., shifted right by `shift` (1
+// for the node sweep's slots, which hold twice the count)
 __global__ __launch_bounds__(256) void occl_finalize_kernel(const OcclPartial *__restrict__ part,
-                                                            int n, int stride,
+                                                            int n, int stride, int shift,
                                                             unsigned long long *out_count) {
     __shared__ unsigned long long s[256];
     const int tid = threadIdx.x;
@@ -207,7 +309,7 @@ __global__ __launch_bounds__(256) void occl_finalize_kernel(const OcclPartial *_
         if (tid < k) s[tid] += s[tid + k];
         __syncthreads();
     }
-    if (tid == 0) *out_count = s[0];
+    if (tid == 0) *out_count = s[0] >> shift;
 }
 
 // rows per thread, waves per SIMD, column split (log2): the split variants
@@ -215,7 +317,7 @@ __global__ __launch_bounds__(256) void occl_finalize_kernel(const OcclPartial *_
 // fill the chip with whole chunks
 constexpr SweepVariant kOccl[kOcclVariants] = {{8, 5, 0}, {2, 8, 0}, {4, 6, 0}, {4, 6, 2},
                                                {2, 8, 2}, {4, 6, 3}, {2, 8, 3}, {8, 5, 2},
-                                               {8, 5, 3}};
+                                               {8, 5, 3}, {4, 8, 0}, {4, 8, 2}, {4, 8, 3}};
 
 template <int V>
 struct OcclV {
@@ -253,6 +355,9 @@ hipError_t launch_occl_sweep(int v, const NodeRec *rec, const SweepArgs &a, int 
         RB_OCASE(6)
         RB_OCASE(7)
         RB_OCASE(8)
+        RB_OCASE(9)
+        RB_OCASE(10)
+        RB_OCASE(11)
         default: return hipErrorInvalidValue;
     }
 #undef RB_OCASE
@@ -260,7 +365,7 @@ hipError_t launch_occl_sweep(int v, const NodeRec *rec, const SweepArgs &a, int 
 }
 
 hipError_t launch_occl_finalize(OcclPartial *part, int n_part, unsigned long long *out_count,
-                                hipStream_t st) {
+                                bool doubled, hipStream_t st) {
     int n = n_part, stride = 1;
     if (n_part > kFoldSpan) {
         n = (n_part + kFoldSpan - 1) / kFoldSpan;
@@ -270,7 +375,7 @@ hipError_t launch_occl_finalize(OcclPartial *part, int n_part, unsigned long lon
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(occl_finalize_kernel, dim3(1), dim3(256), 0, st, part, n, stride,
-                       out_count);
+                       doubled ? 1 : 0, out_count);
     return hipGetLastError();
 }
 

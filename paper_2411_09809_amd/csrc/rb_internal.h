@@ -105,7 +105,7 @@ struct SweepVariant {
     int col_shift;
 };
 constexpr int kCrossVariants = 4;
-constexpr int kOcclVariants = 9;
+constexpr int kOcclVariants = 12;
 SweepVariant cross_variant(int v);
 SweepVariant occl_variant(int v);
 // The batched edge sweep offers every crossing variant but the 4-row one:
@@ -238,10 +238,12 @@ constexpr int kFoldSpan = 2048;
 hipError_t launch_cross_finalize(CrossPartial *part, int n_part, double ideal,
                                  unsigned long long *out_count, unsigned long long *out_proper,
                                  double *out_metric, double *out_dev_sum, hipStream_t st);
+// The node sweep's slots hold twice the count of their units (the diagonal
+// squares are counted as ordered pairs); its finalize takes doubled = true.
 hipError_t launch_occl_sweep(int variant, const NodeRec *rec, const SweepArgs &a, int grid,
                              OcclPartial *part, hipStream_t st);
 hipError_t launch_occl_finalize(OcclPartial *part, int n_part, unsigned long long *out_count,
-                                hipStream_t st);
+                                bool doubled, hipStream_t st);
 
 hipError_t launch_elv(const float *x, const float *y, const int32_t *src, const int32_t *dst,
                       int64_t n_nodes, int64_t n_edges, double *partial, Scalars *sc,

@@ -203,7 +203,7 @@ def test_every_sweep_variant_agrees(torch_mod, kind):
     rows, waves = C.c_int(), C.c_int()
     _lib.check(lib.rb_tune_query(kind, 0, n_items, C.byref(rows), C.byref(waves), None), "query")
     default = None
-    for v in range(9 if kind == 2 else 4):
+    for v in range(12 if kind == 2 else 4):
         _lib.check(lib.rb_tune_set(kind, 0, n_items, v), "rb_tune_set")
         say(f"[variant] kind {kind} variant {v}")
         if kind == 0:
@@ -245,6 +245,38 @@ def test_autotune_single_layout(torch_mod):
     for k in ("node_occlusion", "edge_crossing", "min_angle_n_used"):
         assert after[k] == before[k]
     assert after["crossing_angle"] == pytest.approx(before["crossing_angle"], rel=1e-12)
+
+
+@pytest.mark.parametrize("d", [0.0, 1.0, 6.0])
+def test_every_node_sweep_variant_on_ragged_sizes(torch_mod, d, tmp_path):
+    """Every node-sweep variant, single-layout and batched, on sizes around
+    its row tiles (256 K nodes) and column chunks (256, 64 or 32 nodes).  The
+    sweep counts a tile's own square as ordered pairs less its self pairs and
+    halves the total: that must hold with padding rows and columns, at
+    diameter 0 (no pair occludes, not even a node with itself), at 1 (only
+    coincident nodes) and at 6 on a crowded 40 x 40 canvas (Algorithm 1)."""
+    from paper_2411_09809_amd import _lib, metrics
+    from paper_2411_09809_amd.batch import Batch
+    lib = _lib.lib()
+    sizes = [1, 2, 3, 31, 255, 256, 257, 1023, 1025, 2049, 4100]
+    layouts = [gen.uniform_layout(n, 0, extent=40, diameter=d, seed=n) for n in sizes]
+    want = [oracle.node_occlusion(L.x, L.y, d) for L in layouts]
+    devs = [metrics.DeviceLayout.from_host(L) for L in layouts]
+    mean_v = max(1, sum(sizes) // len(sizes))
+    try:
+        for v in range(12):
+            say(f"[node variants] d={d} variant {v}")
+            for L, D, w in zip(layouts, devs, want):
+                _lib.check(lib.rb_tune_set(2, 0, L.n_nodes, v), "rb_tune_set")
+                assert metrics.node_occlusion(D.x, D.y, d) == w, (v, L.n_nodes)
+            _lib.check(lib.rb_tune_set(2, 1, mean_v, v), "rb_tune_set")
+            B = Batch(layouts)
+            B.evaluate()
+            assert list(B.results()["node_occlusion"]) == want, v
+    finally:
+        empty = tmp_path / "tune.txt"
+        empty.write_text("")
+        _lib.check(lib.rb_tune_load(str(empty).encode()), "rb_tune_load")   # built-in defaults
 
 
 @pytest.mark.parametrize("E", [769, 4095, 4096, 8192])
