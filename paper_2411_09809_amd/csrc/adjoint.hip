@@ -32,10 +32,6 @@ namespace {
 
 constexpr double kHalfPi = 1.5707963267948966192;
 
-__device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
-    return I * nC - (int64_t)K * I * (I - 1) / 2;
-}
-
 // k + [lane in plus] - [lane in minus]: the masks enter as the carry-in and
 // borrow-in of one add and one subtract
 // (in place, so lanes outside EXEC keep their value)
@@ -142,14 +138,17 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     __shared__ int8_t colk[(kBlock / 64) * kChunk];
     __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
     __shared__ double red_d[kBlock / 64];
+    // start-up at raised wave priority, dropped while a unit is swept (the
+    // waves already sweeping would otherwise take nearly every issue slot)
+    __builtin_amdgcn_s_setprio(3);
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
     // with a list, the first min(U, G) blocks take one equal range each, so
     // blocks with work are dispatched before the empty ones
     const int64_t U = LIST ? (int64_t)tile_off[n_tiles] : n_units;
     const int64_t n_items = std::min<int64_t>(U, G);
-    const int64_t u_begin = b < n_items ? block_first_unit(U, n_items, b) : 0;
-    const int64_t u_end = b < n_items ? block_first_unit(U, n_items, b + 1) : 0;
+    const int64_t u_begin = b < n_items ? first_unit(U, n_items, b) : 0;
+    const int64_t u_end = b < n_items ? first_unit(U, n_items, b + 1) : 0;
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
     if (LIST && u_begin == u_end) {            // more blocks than kept units
@@ -160,14 +159,18 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
         }
         return;
     }
-    int64_t lo = 0, hi = (LIST ? n_tiles : lay.n_row_tiles) - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        const int64_t first = LIST ? (int64_t)tile_off[mid] : units_before(mid, lay.n_chunks, K);
-        if (first <= u_begin) lo = mid;
-        else hi = mid - 1;
+    int64_t I;
+    if (LIST) {
+        int64_t lo = 0, hi = n_tiles - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if ((int64_t)tile_off[mid] <= u_begin) lo = mid;
+            else hi = mid - 1;
+        }
+        I = lo;
+    } else {
+        I = tile_of_unit(u_begin, lay.n_row_tiles, lay.n_chunks, K);
     }
-    int64_t I = lo;
     int64_t c = LIST ? 0 : I * K + (u_begin - units_before(I, lay.n_chunks, K));
     double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
     int kr[K];
@@ -212,6 +215,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
             col[tid] = rec[c * kChunk + lane_rec];
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
         const int64_t col0 = c * kChunk;
         const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
@@ -220,6 +224,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
         else
             adjoint_chunk<K, false>(col, rid, colk, rX, rY, rDX, rDY, rC, rTH, kr, tid, diag_off,
                                     ideal, angc, n_p, n_t, acc);
+        __builtin_amdgcn_s_setprio(3);
         tot_p += n_p;
         tot_t += n_t;
         n_p = 0;

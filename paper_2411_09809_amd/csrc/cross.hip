@@ -41,10 +41,6 @@ __device__ __forceinline__ uint32_t popc_ballot(bool p) {
     return (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
 }
 
-__device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int K) {
-    return I * nC - (int64_t)K * I * (I - 1) / 2;
-}
-
 template <int K, bool ANGLE, bool DIAG>
 __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
                                             const int2 *__restrict__ rid,
@@ -119,10 +115,15 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
     __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
     __shared__ double red_d[kBlock / 64];
 
+    // start-up (unit position, row and chunk loads) at raised wave priority,
+    // dropped while a unit is swept: at equal priority the waves already
+    // sweeping take nearly every issue slot and a new block's start-up
+    // stretches out
+    __builtin_amdgcn_s_setprio(3);
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t u_begin = a.unit_base + block_first_unit(a.n_units, G, b);
-    const int64_t u_end = a.unit_base + block_first_unit(a.n_units, G, b + 1);
+    const int64_t u_begin = a.unit_base + first_unit(a.n_units, G, b);
+    const int64_t u_end = a.unit_base + first_unit(a.n_units, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
 
@@ -136,16 +137,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
         }
         L = lo;
     }
-    SweepLayout lay = BATCH ? a.table[L] : a.single;
-    // row tile of the first unit: the largest I with units_before(I) <= local unit
+    SweepLayout lay = BATCH ? table_entry(a.table, L) : a.single;
     const int64_t lu = u_begin - lay.unit_off;
-    int64_t lo = 0, hi = lay.n_row_tiles - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (units_before(mid, lay.n_chunks, K) <= lu) lo = mid;
-        else hi = mid - 1;
-    }
-    int64_t I = lo;
+    int64_t I = tile_of_unit(lu, lay.n_row_tiles, lay.n_chunks, K);
     int64_t c = I * K + (lu - units_before(I, lay.n_chunks, K));
 
     double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
@@ -205,6 +199,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
             col[tid] = rec[lay.rec_off + c * kChunk + lane_rec];
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
         uint32_t n_p = 0, n_t = 0;
         const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
@@ -213,6 +208,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
         else
             sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
                                          ideal, angc, n_p, n_t, acc);
+        __builtin_amdgcn_s_setprio(3);
         tot_p += n_p;
         tot_t += n_t;
         ++seg_units;
@@ -224,7 +220,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
                 flush(b + L);
                 seg_units = 0;
                 ++L;
-                if (L < a.n_layouts) lay = a.table[L];
+                if (L < a.n_layouts) lay = table_entry(a.table, L);
                 I = 0;
                 c = 0;
             }
@@ -247,14 +243,15 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
     __shared__ double red_d[kBlock / 64];
 
+    __builtin_amdgcn_s_setprio(3);            // start-up at raised priority, as above
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
     // the first min(U, G) blocks take one equal range each, so blocks with
     // work are dispatched before the empty ones
     const int64_t U = tile_off[n_tiles];
     const int64_t n_items = std::min<int64_t>(U, G);
-    const int64_t u_begin = b < n_items ? block_first_unit(U, n_items, b) : 0;
-    const int64_t u_end = b < n_items ? block_first_unit(U, n_items, b + 1) : 0;
+    const int64_t u_begin = b < n_items ? first_unit(U, n_items, b) : 0;
+    const int64_t u_end = b < n_items ? first_unit(U, n_items, b + 1) : 0;
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
     if (u_begin == u_end) {                    // more blocks than kept units
@@ -297,8 +294,13 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
             rows_loaded = true;
         }
         const int64_t c = list[u];
-        col[tid] = rec[c * kChunk + tid];
+        {
+            int lane_rec = tid;                // rebuilt each unit, not held across the sweep
+            __asm__ volatile("" : "+v"(lane_rec));
+            col[tid] = rec[c * kChunk + lane_rec];
+        }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
         uint32_t n_p = 0, n_t = 0;
         const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
@@ -307,13 +309,16 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
         else
             sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
                                          ideal, angc, n_p, n_t, acc);
+        __builtin_amdgcn_s_setprio(3);
         tot_p += n_p;
         tot_t += n_t;
     }
     if (ANGLE) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     }
-    const int wave = tid >> 6, lane = tid & 63;
+    int t = tid;
+    __asm__ volatile("" : "+v"(t));
+    const int wave = t >> 6, lane = t & 63;
     __syncthreads();
     if (lane == 0) {
         red_p[wave] = tot_p;
@@ -471,6 +476,7 @@ hipError_t launch_cross_list(int v, const EdgeRec *rec, const int32_t *list,
 hipError_t launch_cross_sweep(int v, bool angle, const EdgeRec *rec, const SweepArgs &a,
                               int grid, double ideal, CrossPartial *part, hipStream_t st) {
     const bool batch = a.table != nullptr;
+    if (batch && !variant_offered(angle ? 1 : 0, true, v)) return hipErrorInvalidValue;
 #define RB_CASE(V)                                                                  \
     case V:                                                                         \
         if (angle) {                                                                \
@@ -481,14 +487,22 @@ hipError_t launch_cross_sweep(int v, bool angle, const EdgeRec *rec, const Sweep
             else launch_v<V, false, false>(rec, a, grid, ideal, part, st);          \
         }                                                                           \
         break;
+// the batched form of the excluded variant is never built
+#define RB_CASE_SINGLE(V)                                                           \
+    case V:                                                                         \
+        if (angle) launch_v<V, true, false>(rec, a, grid, ideal, part, st);         \
+        else launch_v<V, false, false>(rec, a, grid, ideal, part, st);              \
+        break;
+    static_assert(kBatchCrossExcluded == 3, "the switch below builds no batched variant 3");
     switch (v) {
         RB_CASE(0)
         RB_CASE(1)
         RB_CASE(2)
-        RB_CASE(3)
+        RB_CASE_SINGLE(3)
         default: return hipErrorInvalidValue;
     }
 #undef RB_CASE
+#undef RB_CASE_SINGLE
     return hipGetLastError();
 }
 

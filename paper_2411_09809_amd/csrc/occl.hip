@@ -23,36 +23,6 @@
 namespace rb {
 namespace {
 
-// units of the row tiles before tile I: tile i meets chunks i*KS .. nC-1
-__device__ __forceinline__ int64_t units_before(int64_t I, int64_t nC, int64_t KS) {
-    return I * nC - KS * I * (I - 1) / 2;
-}
-
-// floor(U b / G), the first unit of block b, from a double-precision estimate
-// corrected in integers.  The 64-bit division the compiler emits otherwise is
-// a sequence of some hundred scalar instructions, run by every wave of every
-// block, and the scalar unit is shared by the whole CU.
-__device__ __forceinline__ int64_t first_unit(int64_t U, int64_t G, int64_t b) {
-    const int64_t p = U * b;
-    int64_t q = (int64_t)((double)U * (double)b * __builtin_amdgcn_rcp((double)G));
-    while (q > 0 && q * G > p) --q;
-    while ((q + 1) * G <= p) ++q;
-    return q;
-}
-
-// Row tile of local unit lu: the largest I with units_before(I) <= lu, from
-// the smaller root of units_before(I) = lu (a quadratic in I) corrected in
-// integers, in place of a binary search over the tiles.
-__device__ __forceinline__ int64_t tile_of_unit(int64_t lu, int64_t nI, int64_t nC, int64_t KS) {
-    const double B = (double)nC + 0.5 * (double)KS;
-    const double disc = fmax(B * B - 2.0 * (double)KS * (double)lu, 0.0);
-    int64_t I = (int64_t)((B - sqrt(disc)) * __builtin_amdgcn_rcp((double)KS));
-    I = I < 0 ? 0 : (I > nI - 1 ? nI - 1 : I);
-    while (I > 0 && units_before(I, nC, KS) > lu) --I;
-    while (I + 1 < nI && units_before(I + 1, nC, KS) <= lu) ++I;
-    return I;
-}
-
 // Ordered pairs (row, column) of a chunk that occlude, counted exactly.
 template <int K>
 __device__ __forceinline__ uint32_t occl_count(const NodeRec *__restrict__ col, int W,
@@ -96,27 +66,6 @@ __device__ __forceinline__ uint32_t occl_square(const NodeRec *__restrict__ col,
         n -= (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(self));
     }
     return n;
-}
-
-// A batch table entry read into scalar registers.  The kernel stores to
-// global memory, so the compiler cannot use a scalar load for the table and
-// would keep the entry in vector registers, live across the whole sweep of a
-// unit.
-__device__ __forceinline__ int64_t uniform64(int64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ SweepLayout table_entry(const SweepLayout *tab, int64_t L) {
-    const SweepLayout t = tab[L];
-    SweepLayout l;
-    l.unit_off = uniform64(t.unit_off);
-    l.rec_off = uniform64(t.rec_off);
-    l.n_row_tiles = uniform64(t.n_row_tiles);
-    l.n_chunks = uniform64(t.n_chunks);
-    l.col_shift = uniform64(t.col_shift);
-    return l;
 }
 
 // max of two doubles as one instruction: the compiler's fmax also quiets NaN
