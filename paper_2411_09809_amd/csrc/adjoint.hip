@@ -61,27 +61,32 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
         const double cDX = col[j].dx, cDY = col[j].dy;
         const double cC = col[j].c, cTH = col[j].th;
         int colsum = 0;
-        bool zr[K];
+        uint64_t zm[K];
         uint64_t any_zero = 0;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const double o1 = fma(-rDY[r], cX, fma(rDX[r], cY, -rC[r]));
             const double o3 = fma(-cDY, rX[r], fma(cDX, rY[r], -cC));
             const double cr = fma(-rDY[r], cDX, rDX[r] * cDY);
-            const double p12 = o1 * (o1 + cr);
-            const double p34 = o3 * (o3 - cr);
-            const double m = fmax(p12, p34);
-            // a diagonal unit keeps column index > row index: with the tile's
-            // first row as origin, diag_off + j > r * 256 + tid
-            const bool in_tri = !DIAG || (diag_off + j > r * kBlock + tid);
-            const bool closed = (m < 0.0) & in_tri;
-            zr[r] = (m == 0.0) & in_tri;
+            // the signs of o1 (o1 + cr) and o3 (o3 - cr) as in the edge sweep:
+            // max(|2 o1 + cr|, |2 o3 - cr|) against |cr|, as lane masks
+            const double t = dev::max_abs(fma(2.0, o1, cr), fma(2.0, o3, -cr));
+            uint64_t lt = __builtin_amdgcn_ballot_w64(t < fabs(cr));
+            uint64_t le = __builtin_amdgcn_ballot_w64(t <= fabs(cr));
+            if (DIAG) {
+                // a diagonal unit keeps column index > row index: with the
+                // tile's first row as origin, diag_off + j > r * 256 + tid
+                const uint64_t tri = __builtin_amdgcn_ballot_w64(diag_off + j > r * kBlock + tid);
+                lt &= tri;
+                le &= tri;
+            }
+            zm[r] = le & ~lt;
             const double u = fabs(rTH[r] - cTH) - kHalfPi;
             const double v = angc + fabs(u);
             const double dot = fma(rDX[r], cDX, rDY[r] * cDY);
             const double s = (v * dot) * cr;
             // lane masks of the crossing pairs and of their q = +1 / -1
-            const uint64_t cmask = __builtin_amdgcn_ballot_w64(closed);
+            const uint64_t cmask = lt;
             const uint64_t pmask = __builtin_amdgcn_ballot_w64(s > 0.0) & cmask;
             const uint64_t nmask = __builtin_amdgcn_ballot_w64(s < 0.0) & cmask;
             colsum += (int)__popcll(pmask) - (int)__popcll(nmask);
@@ -89,7 +94,7 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             // forward terms of the same pair: the count and |ideal - a|
             n_proper += (uint32_t)__popcll(cmask);
             dev::add_abs_masked(acc, v, cmask);
-            any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
+            any_zero |= zm[r];
         }
         if (__builtin_expect(any_zero != 0, 0)) {
             // pairs with an end point on the other edge's line
@@ -100,7 +105,7 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             for (int r = 0; r < K; ++r) {
                 bool pos = false, neg = false, ok = false;
                 // incident pairs (the common case here) are settled by their ids
-                if (zr[r] && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
+                if (((zm[r] >> lane) & 1) && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
                     double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
                     __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
                     ok = dev::touching_apart(ex, ey, edx, edy, ec, fx, fy, fdx, fdy, fc);

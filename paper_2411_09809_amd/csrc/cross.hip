@@ -41,13 +41,24 @@ __device__ __forceinline__ uint32_t popc_ballot(bool p) {
     return (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p));
 }
 
+// threadIdx.x rebuilt from the wave's index (a scalar) and the lane id.  One
+// volatile asm block, so the compiler recomputes it where it is used instead
+// of holding it in a vector register across the sweep (the 4-row angle
+// kernels have none to spare).
+__device__ __forceinline__ int thread_index(int wave_s) {
+    int lane;
+    __asm__ volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0"
+                     : "=v"(lane));
+    return (wave_s << 6) + lane;
+}
+
 template <int K, bool ANGLE, bool DIAG>
 __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
                                             const int2 *__restrict__ rid,
                                             const double (&rX)[K], const double (&rY)[K],
                                             const double (&rDX)[K], const double (&rDY)[K],
                                             const double (&rC)[K], const double (&rTH)[K],
-                                            int tid, int diag_off, double ideal,
+                                            int wave_s, int diag_off, double ideal,
                                             double angc, uint32_t &n_proper, uint32_t &n_touch,
                                             double &acc) {
 #pragma unroll 4
@@ -58,28 +69,38 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
         const double cTH = ANGLE ? col[j].th : 0.0;
         // the K rows are independent straight-line work; one wave-uniform
         // branch per column takes every row's rare pairs
-        bool zr[K];
+        uint64_t zm[K];
         uint64_t any_zero = 0;
+        const int tid_d = DIAG ? thread_index(wave_s) : 0;   // per column, diagonal units only
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const double o1 = fma(-rDY[r], cX, fma(rDX[r], cY, -rC[r]));
             const double o3 = fma(-cDY, rX[r], fma(cDX, rY[r], -cC));
             const double cr = fma(-rDY[r], cDX, rDX[r] * cDY);
-            const double p12 = o1 * (o1 + cr);
-            const double p34 = o3 * (o3 - cr);
-            const double m = fmax(p12, p34);
-            // a diagonal unit keeps column index > row index: with the tile's
-            // first row as origin, diag_off + j > r * 256 + tid
-            const bool in_tri = !DIAG || (diag_off + j > r * kBlock + tid);
-            const bool prop = (m < 0.0) & in_tri;
-            zr[r] = (m == 0.0) & in_tri;
-            const uint64_t pmask = __builtin_amdgcn_ballot_w64(prop);
+            // o1 o2 = o1 (o1 + cr) has the sign of |2 o1 + cr| - |cr| (4 o1 o2 =
+            // (2 o1 + cr)^2 - cr^2), and o3 o4 = o3 (o3 - cr) that of
+            // |2 o3 - cr| - |cr|; both are negative iff the larger of
+            // |2 o1 + cr| and |2 o3 - cr| is below |cr|, and the larger
+            // product is zero iff it equals |cr|.  Exact on these integers; the
+            // two compares are lane masks (scalar results) used as they are.
+            const double t = dev::max_abs(fma(2.0, o1, cr), fma(2.0, o3, -cr));
+            uint64_t lt = __builtin_amdgcn_ballot_w64(t < fabs(cr));
+            uint64_t le = __builtin_amdgcn_ballot_w64(t <= fabs(cr));
+            if (DIAG) {
+                // a diagonal unit keeps column index > row index: with the
+                // tile's first row as origin, diag_off + j > r * 256 + tid
+                const uint64_t tri = __builtin_amdgcn_ballot_w64(diag_off + j > r * kBlock + tid_d);
+                lt &= tri;
+                le &= tri;
+            }
+            zm[r] = le & ~lt;                              // max of the two products == 0
+            const uint64_t pmask = lt;                     // both products < 0
             n_proper += (uint32_t)__popcll(pmask);
             if (ANGLE) {
                 const double u = fabs(rTH[r] - cTH) - kHalfPi;
                 dev::add_abs_masked(acc, angc + fabs(u), pmask);
             }
-            any_zero |= __builtin_amdgcn_ballot_w64(zr[r]);
+            any_zero |= zm[r];
         }
         if (__builtin_expect(any_zero != 0, 0)) {
             // most such pairs share an end id (the incident edges of a hub):
@@ -87,10 +108,11 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
             double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC, fth = cTH;
             __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc), "+v"(fth));
             const int2 fid = make_int2(col[j].s, col[j].t);
+            const int tid = thread_index(wave_s), lane = tid & 63;
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 bool ok = false;
-                if (zr[r] && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
+                if (((zm[r] >> lane) & 1) && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
                     double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
                     __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
                     ok = dev::touching_apart(ex, ey, edx, edy, ec, fx, fy, fdx, fdy, fc);
@@ -120,7 +142,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
     // sweeping take nearly every issue slot and a new block's start-up
     // stretches out
     __builtin_amdgcn_s_setprio(3);
-    const int tid = threadIdx.x;
+    const int wave_s = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int64_t G = gridDim.x, b = blockIdx.x;
     const int64_t u_begin = a.unit_base + first_unit(a.n_units, G, b);
     const int64_t u_end = a.unit_base + first_unit(a.n_units, G, b + 1);
@@ -152,19 +174,15 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
         if (ANGLE) {
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         }
-        // the reduction's LDS addresses are formed here, not held (or spilled)
-        // across the sweep
-        int t = tid;
-        __asm__ volatile("" : "+v"(t));
-        const int wave = t >> 6, lane = t & 63;
+        const int t = thread_index(wave_s);
         __syncthreads();
-        if (lane == 0) {
-            red_p[wave] = tot_p;
-            red_t[wave] = tot_t;
-            red_d[wave] = acc;
+        if ((t & 63) == 0) {
+            red_p[wave_s] = tot_p;
+            red_t[wave_s] = tot_t;
+            red_d[wave_s] = acc;
         }
         __syncthreads();
-        if (tid == 0) {
+        if (t == 0) {
             CrossPartial P;
             P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
             for (int w = 0; w < kBlock / 64; ++w) {
@@ -180,6 +198,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
     for (int64_t u = u_begin; u < u_end; ++u) {
         __syncthreads();                       // previous chunk and row ids consumed
         if (!rows_loaded) {
+            const int tid = thread_index(wave_s);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 const EdgeRec e = edge_row(rec + lay.rec_off, I * R + (int64_t)r * kBlock + tid,
@@ -191,22 +210,21 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
             rows_loaded = true;
         }
         {
-            // recompute the lane's address each unit: held across the whole
-            // loop it is one more 64-bit register pair, which the 3- and
-            // 4-row variants had to spill
-            int lane_rec = tid;
-            __asm__ volatile("" : "+v"(lane_rec));
-            col[tid] = rec[lay.rec_off + c * kChunk + lane_rec];
+            // the lane's index and staging address are rebuilt each unit: held
+            // across the loop they take registers the 3- and 4-row variants
+            // do not have
+            const int tid = thread_index(wave_s);
+            col[tid] = rec[lay.rec_off + c * kChunk + tid];
         }
         __syncthreads();
         __builtin_amdgcn_s_setprio(0);
         uint32_t n_p = 0, n_t = 0;
         const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
-            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
+            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, wave_s, diag_off,
                                         ideal, angc, n_p, n_t, acc);
         else
-            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
+            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, wave_s, diag_off,
                                          ideal, angc, n_p, n_t, acc);
         __builtin_amdgcn_s_setprio(3);
         tot_p += n_p;
@@ -244,7 +262,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     __shared__ double red_d[kBlock / 64];
 
     __builtin_amdgcn_s_setprio(3);            // start-up at raised priority, as above
-    const int tid = threadIdx.x;
+    const int wave_s = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int64_t G = gridDim.x, b = blockIdx.x;
     // the first min(U, G) blocks take one equal range each, so blocks with
     // work are dispatched before the empty ones
@@ -255,7 +273,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     constexpr int64_t R = (int64_t)kBlock * K;
     const double angc = ideal - kHalfPi;
     if (u_begin == u_end) {                    // more blocks than kept units
-        if (tid == 0) {
+        if (threadIdx.x == 0) {
             CrossPartial P;
             P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
             part[b] = P;
@@ -284,6 +302,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
         }
         __syncthreads();                       // previous chunk and row ids consumed
         if (!rows_loaded) {
+            const int tid = thread_index(wave_s);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 const EdgeRec e = edge_row(rec, I * R + (int64_t)r * kBlock + tid, n_rec);
@@ -295,19 +314,18 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
         }
         const int64_t c = list[u];
         {
-            int lane_rec = tid;                // rebuilt each unit, not held across the sweep
-            __asm__ volatile("" : "+v"(lane_rec));
-            col[tid] = rec[c * kChunk + lane_rec];
+            const int tid = thread_index(wave_s);   // rebuilt each unit, as above
+            col[tid] = rec[c * kChunk + tid];
         }
         __syncthreads();
         __builtin_amdgcn_s_setprio(0);
         uint32_t n_p = 0, n_t = 0;
         const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
-            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
+            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, wave_s, diag_off,
                                         ideal, angc, n_p, n_t, acc);
         else
-            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, tid, diag_off,
+            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, wave_s, diag_off,
                                          ideal, angc, n_p, n_t, acc);
         __builtin_amdgcn_s_setprio(3);
         tot_p += n_p;
@@ -316,17 +334,15 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     if (ANGLE) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     }
-    int t = tid;
-    __asm__ volatile("" : "+v"(t));
-    const int wave = t >> 6, lane = t & 63;
+    const int t = thread_index(wave_s);
     __syncthreads();
-    if (lane == 0) {
-        red_p[wave] = tot_p;
-        red_t[wave] = tot_t;
-        red_d[wave] = acc;
+    if ((t & 63) == 0) {
+        red_p[wave_s] = tot_p;
+        red_t[wave_s] = tot_t;
+        red_d[wave_s] = acc;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (t == 0) {
         CrossPartial P;
         P.proper = 0; P.touch = 0; P.dev = 0.0; P.pad = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) {

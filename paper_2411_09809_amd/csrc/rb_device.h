@@ -61,6 +61,14 @@ __device__ __forceinline__ void add_abs_masked(double &acc, double v, uint64_t m
             : "scc");
 }
 
+// max(|a|, |b|) as one instruction (absolute-value operands; the compiler's
+// fmax would also quiet NaN inputs, and no NaN reaches the sweeps)
+__device__ __forceinline__ double max_abs(double a, double b) {
+    double r;
+    __asm__("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // Pairs whose larger orientation product is zero.  Edges that share an end
 // id are never crossings (incident edges always have both products zero).
 __device__ __forceinline__ bool incident_ids(int2 a, int2 b) {
