@@ -38,21 +38,22 @@ sys.path.insert(0, ROOT)
 # (one FP64 FMA, FP32 or INT32 op per lane per clock; packed FP32 not used).
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # Algorithmic VALU lane-ops per edge pair of the crossing + crossing-angle
-# test: 2 FMA each for the orientations o1, o3 of one end of either edge
-# against the other's line, 2 for the cross product cr of the directions, 1
-# FMA each for 2 o1 + cr and 2 o3 - cr (the two orientation products o1 o2 and
-# o3 o4 have the signs of |2 o1 + cr| - |cr| and |2 o3 - cr| - |cr|), 1 max of
-# their absolute values, 2 compares against |cr| (both products < 0; the
-# larger one zero), and 4 for the angle term (difference of line angles,
-# fold, deviation, accumulate under the crossing mask).
-OPS_PER_EDGE_PAIR = 15
+# test, with both edges held as end-point sums S = P1 + P2 and doubled line
+# constants: 2 FMA each for t1 = 2 o1 + cross = dx_e S_f.y - dy_e S_f.x - 2 c_e
+# and t3 = 2 o3 - cross (o1, o3 the orientations of one end of either edge
+# against the other's line; the orientation products o1 o2 and o3 o4 have the
+# signs of |t1| - |cross| and |t3| - |cross|), 2 for the cross product of the
+# directions, 1 max of |t1| and |t3|, 2 compares against |cross| (both
+# products < 0; the larger one zero), and 4 for the angle term (difference of
+# line angles, fold, deviation, accumulate under the crossing mask).
+OPS_PER_EDGE_PAIR = 13
 # per node pair of the occlusion test: 2 FMA + 1 max (the exact count runs
 # only for the rare chunks that hold an occluding pair)
 OPS_PER_NODE_PAIR = 3
-# per edge pair of the fused forward + adjoint sweep: the 15 above, then the
+# per edge pair of the fused forward + adjoint sweep: the 13 above, then the
 # dot product of the directions (2), the sign product (v dot) cross (2), two
 # compares for q = +1 / -1 and the masked +-1 into the row's integer sum (2)
-OPS_PER_ADJOINT_PAIR = 23
+OPS_PER_ADJOINT_PAIR = 21
 # HBM bytes per launch of the crossing + angle sweep, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size, per
 # workload and (rows per thread, waves per SIMD).  Valid only for the kernel

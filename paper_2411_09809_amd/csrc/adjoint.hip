@@ -65,12 +65,13 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
         uint64_t any_zero = 0;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            const double o1 = fma(-rDY[r], cX, fma(rDX[r], cY, -rC[r]));
-            const double o3 = fma(-cDY, rX[r], fma(cDX, rY[r], -cC));
+            // rows and columns in sweep form, as in the edge sweep: the signs
+            // of o1 (o1 + cr) and o3 (o3 - cr) from max(|t1|, |t3|) against
+            // |cr|, with t1 = 2 o1 + cr and t3 = 2 o3 - cr, as lane masks
+            const double t1 = fma(rDX[r], cY, fma(-rDY[r], cX, -rC[r]));
+            const double t3 = fma(cDX, rY[r], fma(-cDY, rX[r], -cC));
             const double cr = fma(-rDY[r], cDX, rDX[r] * cDY);
-            // the signs of o1 (o1 + cr) and o3 (o3 - cr) as in the edge sweep:
-            // max(|2 o1 + cr|, |2 o3 - cr|) against |cr|, as lane masks
-            const double t = dev::max_abs(fma(2.0, o1, cr), fma(2.0, o3, -cr));
+            const double t = dev::max_abs(t1, t3);
             uint64_t lt = __builtin_amdgcn_ballot_w64(t < fabs(cr));
             uint64_t le = __builtin_amdgcn_ballot_w64(t <= fabs(cr));
             if (DIAG) {
@@ -100,6 +101,11 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             // pairs with an end point on the other edge's line
             double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC, fth = cTH;
             __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc), "+v"(fth));
+            // back from sweep form to start point and line constant (exact);
+            // after the opaque copy, so none of it is hoisted out of the loop
+            fx = 0.5 * (fx - fdx);
+            fy = 0.5 * (fy - fdy);
+            fc = 0.5 * fc;
             const int2 fid = make_int2(col[j].s, col[j].t);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
@@ -108,6 +114,9 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                 if (((zm[r] >> lane) & 1) && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
                     double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
                     __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
+                    ex = 0.5 * (ex - edx);
+                    ey = 0.5 * (ey - edy);
+                    ec = 0.5 * ec;
                     ok = dev::touching_apart(ex, ey, edx, edy, ec, fx, fy, fdx, fdy, fc);
                     if (ok) {
                         const double cr = fma(-edy, fdx, edx * fdy);
@@ -204,8 +213,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
         if (!rows_loaded) {
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = edge_row(rec, I * R + (int64_t)r * kBlock + tid,
-                                           lay.n_chunks * kChunk);
+                const EdgeRec e = sweep_form(edge_row(rec, I * R + (int64_t)r * kBlock + tid,
+                                                      lay.n_chunks * kChunk));
                 rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
                 rC[r] = e.c; rTH[r] = e.th;
                 rid[r * kBlock + tid] = make_int2(e.s, e.t);
@@ -217,7 +226,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
             // the lane's staging address is rebuilt each unit, not held across the sweep
             int lane_rec = tid;
             __asm__ volatile("" : "+v"(lane_rec));
-            col[tid] = rec[c * kChunk + lane_rec];
+            col[tid] = sweep_form(rec[c * kChunk + lane_rec]);
         }
         __syncthreads();
         __builtin_amdgcn_s_setprio(0);

@@ -24,6 +24,13 @@
 //   m == 0  some end point lies on the other line: the rare path decides
 //           (incident pairs are dropped, and when both products are zero the
 //           bounding boxes must meet).
+// The products are not formed.  Since 4 a b = (a + b)^2 - (a - b)^2, o1 o2 has
+// the sign of |2 o1 + cross| - |cross| and o3 o4 that of |2 o3 - cross| -
+// |cross|, and with the end-point sums S = P1 + P2 of each edge
+//   t1 = 2 o1 + cross = dx_e*S_f.y - dy_e*S_f.x - 2 c_e,
+//   t3 = 2 o3 - cross = dx_f*S_e.y - dy_f*S_e.x - 2 c_f,
+// two FMAs each.  So m < 0 iff max(|t1|, |t3|) < |cross|, and m == 0 iff that
+// maximum equals |cross|: 9 VALU operations per pair for the classification.
 // The crossing angle uses the per-edge line angles th in [0, pi):
 //   a = pi/2 - | |th_e - th_f| - pi/2 |,  dev = |ideal - a|
 // (a = 0 for parallel lines and zero-length edges).
@@ -74,16 +81,13 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
         const int tid_d = DIAG ? thread_index(wave_s) : 0;   // per column, diagonal units only
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            const double o1 = fma(-rDY[r], cX, fma(rDX[r], cY, -rC[r]));
-            const double o3 = fma(-cDY, rX[r], fma(cDX, rY[r], -cC));
+            // rows and columns are in sweep form (end-point sums, 2c): t1 =
+            // 2 o1 + cr and t3 = 2 o3 - cr directly; the two compares are
+            // lane masks (scalar results) used as they are
+            const double t1 = fma(rDX[r], cY, fma(-rDY[r], cX, -rC[r]));
+            const double t3 = fma(cDX, rY[r], fma(-cDY, rX[r], -cC));
             const double cr = fma(-rDY[r], cDX, rDX[r] * cDY);
-            // o1 o2 = o1 (o1 + cr) has the sign of |2 o1 + cr| - |cr| (4 o1 o2 =
-            // (2 o1 + cr)^2 - cr^2), and o3 o4 = o3 (o3 - cr) that of
-            // |2 o3 - cr| - |cr|; both are negative iff the larger of
-            // |2 o1 + cr| and |2 o3 - cr| is below |cr|, and the larger
-            // product is zero iff it equals |cr|.  Exact on these integers; the
-            // two compares are lane masks (scalar results) used as they are.
-            const double t = dev::max_abs(fma(2.0, o1, cr), fma(2.0, o3, -cr));
+            const double t = dev::max_abs(t1, t3);
             uint64_t lt = __builtin_amdgcn_ballot_w64(t < fabs(cr));
             uint64_t le = __builtin_amdgcn_ballot_w64(t <= fabs(cr));
             if (DIAG) {
@@ -107,6 +111,11 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
             // the id test comes first and the rest runs only for the others
             double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC, fth = cTH;
             __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc), "+v"(fth));
+            // back from sweep form to start point and line constant (exact);
+            // after the opaque copy, so none of it is hoisted out of the loop
+            fx = 0.5 * (fx - fdx);
+            fy = 0.5 * (fy - fdy);
+            fc = 0.5 * fc;
             const int2 fid = make_int2(col[j].s, col[j].t);
             const int tid = thread_index(wave_s), lane = tid & 63;
 #pragma unroll
@@ -115,6 +124,9 @@ __device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
                 if (((zm[r] >> lane) & 1) && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
                     double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
                     __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
+                    ex = 0.5 * (ex - edx);
+                    ey = 0.5 * (ey - edy);
+                    ec = 0.5 * ec;
                     ok = dev::touching_apart(ex, ey, edx, edy, ec, fx, fy, fdx, fdy, fc);
                     if (ANGLE && ok) {
                         // parallel lines or a zero-length edge: a = 0
@@ -201,8 +213,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
             const int tid = thread_index(wave_s);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = edge_row(rec + lay.rec_off, I * R + (int64_t)r * kBlock + tid,
-                                           lay.n_chunks * kChunk);
+                const EdgeRec e = sweep_form(edge_row(rec + lay.rec_off,
+                                                      I * R + (int64_t)r * kBlock + tid,
+                                                      lay.n_chunks * kChunk));
                 rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
                 rC[r] = e.c; rTH[r] = e.th;
                 rid[r * kBlock + tid] = make_int2(e.s, e.t);
@@ -214,7 +227,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
             // across the loop they take registers the 3- and 4-row variants
             // do not have
             const int tid = thread_index(wave_s);
-            col[tid] = rec[lay.rec_off + c * kChunk + tid];
+            col[tid] = sweep_form(rec[lay.rec_off + c * kChunk + tid]);
         }
         __syncthreads();
         __builtin_amdgcn_s_setprio(0);
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
             const int tid = thread_index(wave_s);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = edge_row(rec, I * R + (int64_t)r * kBlock + tid, n_rec);
+                const EdgeRec e = sweep_form(edge_row(rec, I * R + (int64_t)r * kBlock + tid, n_rec));
                 rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
                 rC[r] = e.c; rTH[r] = e.th;
                 rid[r * kBlock + tid] = make_int2(e.s, e.t);
@@ -315,7 +328,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
         const int64_t c = list[u];
         {
             const int tid = thread_index(wave_s);   // rebuilt each unit, as above
-            col[tid] = rec[c * kChunk + tid];
+            col[tid] = sweep_form(rec[c * kChunk + tid]);
         }
         __syncthreads();
         __builtin_amdgcn_s_setprio(0);

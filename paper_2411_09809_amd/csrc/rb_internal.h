@@ -35,6 +35,17 @@ __device__ __forceinline__ EdgeRec edge_row(const EdgeRec *__restrict__ seg, int
     return r;
 }
 
+// An edge record as the pair sweeps hold it (rows in registers, columns in
+// LDS): x and y become the end-point sums x1 + x2 = 2x + dx and y1 + y2, and c
+// becomes 2c; dx, dy, th and the ids stay.  Exact: integers below 2^44.  The
+// padding record keeps c != 0, so it never meets another edge's line.
+__device__ __forceinline__ EdgeRec sweep_form(EdgeRec e) {
+    e.x = fma(2.0, e.x, e.dx);
+    e.y = fma(2.0, e.y, e.dy);
+    e.c = 2.0 * e.c;
+    return e;
+}
+
 // Per-node record for the occlusion sweep.  With n = x^2 + y^2 and T the
 // largest integer below d^2, the test |p_u - p_v|^2 <= T is rewritten as
 //     x_u x_v + y_u y_v + q_v >= h_u,   q = -n/2,  h = (n - T)/2,
