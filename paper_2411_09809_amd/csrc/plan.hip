@@ -73,7 +73,8 @@ void load_locked(const char *path) {
 
 // the built-in default of a kind, batch flag and size class: the crossing
 // sweeps take 2 rows per thread, and the crossing + angle sweep of a single
-// layout 4 rows from 2^21 edges (1.3% faster at 3M edges); the pruned
+// layout 3 rows from 2^21 edges (0.7% faster than 2 rows and 1.4% than 4 at
+// 3M edges); the pruned
 // sweep takes the 1-row tiles (tightest boxes) below 2^17 edges and 2-row
 // tiles above.  The node sweep of a single layout splits its 256-column
 // chunks below 2^16 nodes, for units enough to fill the chip: 2 rows per
@@ -85,7 +86,7 @@ void load_locked(const char *path) {
 // nodes per layout.
 int default_variant(int k, int b, int c) {
     if (k == 3 && c >= 17) return 1;
-    if (k == 1 && !b && c >= 21) return 3;
+    if (k == 1 && !b && c >= 21) return 2;
     if (k == 2) {
         if (b) return c >= 19 ? 0 : 9;
         if (c <= 12) return 6;

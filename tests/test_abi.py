@@ -148,7 +148,7 @@ def test_argument_errors_of_the_other_entry_points_need_no_gpu(L):
 
 def test_built_in_tuning_defaults(L, tmp_path):
     """The defaults a table returns to on a load of an empty file: crossing
-    sweeps 2 rows / 7 waves, but 4 rows / 5 waves for the crossing + angle
+    sweeps 2 rows / 7 waves, but 3 rows / 5 waves for the crossing + angle
     sweep of a single layout from 2^21 edges; the node sweep of a single layout
     2 rows / 8 waves in chunks split 8 ways below 2^13 nodes, 4 rows / 8 waves
     split 8 ways below 2^14 and 4 ways below 2^15, 8 rows / 5 waves split 4
@@ -170,7 +170,7 @@ def test_built_in_tuning_defaults(L, tmp_path):
     for n in (2_000, 149_994, 3_000_000):
         assert q(0, n) == (2, 7) and q(1, n, batch=1) == (2, 7)
     assert q(1, 149_994) == (2, 7) and q(1, (1 << 21) - 1) == (2, 7)
-    assert q(1, 1 << 21) == (4, 5) and q(1, 3_000_000) == (4, 5)
+    assert q(1, 1 << 21) == (3, 5) and q(1, 3_000_000) == (3, 5)
     assert q(2, 1_000) == (2, 8, 8) and q(2, (1 << 13) - 1) == (2, 8, 8)
     assert q(2, 1 << 13) == (4, 8, 8) and q(2, 20_000) == (4, 8, 4)
     assert q(2, 50_000) == (8, 5, 4) and q(2, 100_000) == (4, 6, 1)
