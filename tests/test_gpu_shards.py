@@ -159,3 +159,34 @@ def test_powerlaw_small_metrics_match_oracle(powerlaw):
     ml, mu = metrics.edge_length_variation(D.x, D.y, D.src, D.dst)
     rml, rmu = oracle.edge_length_variation(L.x, L.y, L.src, L.dst)
     assert ml == pytest.approx(rml, rel=1e-9) and mu == pytest.approx(rmu, rel=1e-12)
+
+
+def test_powerlaw_whole_equals_the_stored_oracle(powerlaw):
+    """The full 1M-node / 3M-edge result against the oracle's, computed once
+    by tests/golden/make_golden.py in row slices (oracle only; the input
+    digest is checked): E_c, the proper crossings and N_c bit for bit,
+    E_ca, the deviation sum, M_a and M_l to 1e-5 relative (Algorithms 1-5)."""
+    import json
+    import os
+    from paper_2411_09809_amd import metrics
+    L, D = powerlaw
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workloads.json")) as fh:
+        want = json.load(fh)["powerlaw_V1000000_s0"]
+    assert want["digest"] == L.digest()
+    assert want["slices"] == {"crossing": 480, "occlusion": 40}
+    eca, cnt, dev = metrics.crossing_angle(D.x, D.y, D.src, D.dst, IDEAL)
+    c, p = metrics.edge_crossing(D.x, D.y, D.src, D.dst)
+    occ = metrics.node_occlusion(D.x, D.y, L.diameter)
+    say(f"[powerlaw] E_c={cnt} (oracle {want['edge_crossing']}) proper={p} "
+        f"(oracle {want['proper_crossing']}) N_c={occ} (oracle {want['node_occlusion']})")
+    assert cnt == c == want["edge_crossing"]
+    assert p == want["proper_crossing"]
+    assert occ == want["node_occlusion"]
+    assert metrics.node_occlusion_grid(D.x, D.y, L.diameter) == want["node_occlusion"]
+    assert eca == pytest.approx(want["crossing_angle"], rel=1e-5)
+    assert dev == pytest.approx(want["crossing_dev_sum"], rel=1e-5)
+    ma, sdv, used = metrics.min_angle(D.x, D.y, D.src, D.dst)
+    assert used == want["min_angle_n_used"]
+    assert ma == pytest.approx(want["min_angle"], rel=1e-5)
+    ml, mu = metrics.edge_length_variation(D.x, D.y, D.src, D.dst)
+    assert ml == pytest.approx(want["edge_length_variation"], rel=1e-5)
