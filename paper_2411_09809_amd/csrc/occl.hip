@@ -118,8 +118,11 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
     __shared__ unsigned long long red[kBlock / 64];
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t u_begin = a.unit_base + first_unit(a.n_units, G, b);
-    const int64_t u_end = a.unit_base + first_unit(a.n_units, G, b + 1);
+    // one unit per block (every layout below a few hundred thousand nodes):
+    // block b's range is [b, b + 1), with no estimate to correct
+    const bool one = a.n_units == G;
+    const int64_t u_begin = a.unit_base + (one ? b : first_unit(a.n_units, G, b));
+    const int64_t u_end = one ? u_begin + 1 : a.unit_base + first_unit(a.n_units, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
 
     int64_t L = 0;
@@ -136,7 +139,12 @@ __global__ __launch_bounds__(kBlock, WAVES) void occl_sweep_kernel(
     int W = kChunk >> lay.col_shift;               // columns per unit
     int64_t KS = (int64_t)K << lay.col_shift;      // chunks spanned by a row tile
     const int64_t lu = u_begin - lay.unit_off;
-    int64_t I = tile_of_unit(lu, lay.n_row_tiles, lay.n_chunks, KS);
+    // 32-bit operands when the launch's units all lie below 2^31 (a shard of a
+    // huge layout may start far above)
+    const bool small = one && !BATCH && a.unit_base + a.n_units <= INT32_MAX;
+    int64_t I = small
+                    ? tile_of_unit32((int)lu, (int)lay.n_row_tiles, (int)lay.n_chunks, (int)KS)
+                    : tile_of_unit(lu, lay.n_row_tiles, lay.n_chunks, KS);
     int64_t c = I * KS + (lu - units_before(I, lay.n_chunks, KS));
 
     double rX[K], rY[K], rH[K];

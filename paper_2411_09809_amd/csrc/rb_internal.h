@@ -415,6 +415,18 @@ __device__ __forceinline__ int64_t first_unit(int64_t U, int64_t G, int64_t b) {
     return q;
 }
 
+// tile_of_unit for operands below 2^31 (one unit per block: lu is a block
+// index), with 32-bit conversions in place of the 64-bit ones.
+__device__ __forceinline__ int64_t tile_of_unit32(int lu, int nI, int nC, int KS) {
+    const double B = (double)nC + 0.5 * (double)KS;
+    const double disc = fmax(B * B - 2.0 * (double)KS * (double)lu, 0.0);
+    int I = (int)((B - sqrt(disc)) * __builtin_amdgcn_rcp((double)KS));
+    I = I < 0 ? 0 : (I > nI - 1 ? nI - 1 : I);
+    while (I > 0 && units_before(I, nC, KS) > lu) --I;
+    while (I + 1 < nI && units_before(I + 1, nC, KS) <= lu) ++I;
+    return I;
+}
+
 // Row tile of local unit lu: the largest I < nI with units_before(I) <= lu,
 // from the smaller root of units_before(I) = lu (a quadratic in I) corrected
 // in integers, in place of a binary search over the tiles.
