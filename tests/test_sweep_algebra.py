@@ -1,0 +1,124 @@
+"""The crossing classification of the sweep kernels, checked against
+Algorithm 4's printed form in exact integer arithmetic (CPU only).
+
+The kernels never form the orientation products o1 o2 and o3 o4.  They hold
+each edge as its end-point sum S = P + Q, its direction D = Q - P and 2c
+(c = D x P), and compute
+
+    t1 = dx_e S_f.y - dy_e S_f.x - 2 c_e   (= 2 o1 + cross)
+    t3 = dx_f S_e.y - dy_f S_e.x - 2 c_f   (= 2 o3 - cross)
+    t  = max(|t1|, |t3|),  cross = dx_e dy_f - dy_e dx_f
+
+and classify a pair as crossing properly iff t < |cross| and as the rare case
+(the larger product zero) iff t == |cross|.  These tests pin that reading to
+max(o1 o2, o3 o4) < 0 and == 0, and check that every intermediate stays below
+2^53 at the coordinate limit 2^20, so the kernels' FP64 arithmetic is exact.
+"""
+import random
+
+import pytest
+
+LIM = 1 << 20
+
+
+def orient(px, py, dx, dy, qx, qy):
+    """Algorithm 4's CCW determinant of q against the line through p along d."""
+    return dx * (qy - py) - dy * (qx - px)
+
+
+def printed(e, f):
+    """max(o1 o2, o3 o4) as Algorithm 4 forms it."""
+    (ax, ay), (bx, by) = e
+    (cx, cy), (qx, qy) = f
+    o1 = orient(ax, ay, bx - ax, by - ay, cx, cy)
+    o2 = orient(ax, ay, bx - ax, by - ay, qx, qy)
+    o3 = orient(cx, cy, qx - cx, qy - cy, ax, ay)
+    o4 = orient(cx, cy, qx - cx, qy - cy, bx, by)
+    return max(o1 * o2, o3 * o4)
+
+
+def sweep_form(seg):
+    (px, py), (qx, qy) = seg
+    dx, dy = qx - px, qy - py
+    c = dx * py - dy * px
+    return px + qx, py + qy, dx, dy, 2 * c
+
+
+def kernel(e, f):
+    """The kernels' classification and the largest intermediate magnitude."""
+    sxe, sye, dxe, dye, c2e = sweep_form(e)
+    sxf, syf, dxf, dyf, c2f = sweep_form(f)
+    t1 = dxe * syf - dye * sxf - c2e
+    t3 = dxf * sye - dyf * sxe - c2f
+    cross = dxe * dyf - dye * dxf
+    t = max(abs(t1), abs(t3))
+    big = max(abs(v) for v in (sxe, sye, dxe, dye, c2e, sxf, syf, dxf, dyf, c2f,
+                               dxe * syf, dye * sxf, dxf * sye, dyf * sxe, t1, t3,
+                               dxe * dyf, dye * dxf, cross))
+    return (t < abs(cross)), (t == abs(cross)), big
+
+
+def classify(m):
+    return m < 0, m == 0
+
+
+def test_sign_identity_on_integers():
+    """o (o + c) and |2 o + c| - |c| have the same sign, zero included."""
+    rng = random.Random(1)
+    vals = [0, 1, -1, 2, -2, 3, (1 << 44) - 1, -(1 << 44)]
+    pairs = [(a, b) for a in vals for b in vals]
+    pairs += [(rng.randint(-(1 << 44), 1 << 44), rng.randint(-(1 << 44), 1 << 44))
+              for _ in range(20000)]
+    pairs += [(a, -2 * a) for a in vals] + [(a, -a) for a in vals]
+    for o, c in pairs:
+        p = o * (o + c)
+        q = abs(2 * o + c) - abs(c)
+        assert (p > 0) == (q > 0) and (p < 0) == (q < 0) and (p == 0) == (q == 0), (o, c)
+
+
+def _segments(rng, n, lim):
+    out = []
+    for _ in range(n):
+        out.append(((rng.randint(-lim, lim), rng.randint(-lim, lim)),
+                    (rng.randint(-lim, lim), rng.randint(-lim, lim))))
+    return out
+
+
+@pytest.mark.parametrize("lim", [4, 40, LIM])
+def test_kernel_form_equals_printed_form(lim):
+    """Random segment pairs, small canvases (many touching and collinear
+    pairs) and the full coordinate range: the same decision every time, and
+    every intermediate below 2^53."""
+    rng = random.Random(lim)
+    segs = _segments(rng, 400, lim)
+    biggest = 0
+    for i in range(0, len(segs), 2):
+        for j in range(len(segs)):
+            e, f = segs[i], segs[j]
+            crossing, rare, big = kernel(e, f)
+            assert (crossing, rare) == classify(printed(e, f)), (e, f)
+            biggest = max(biggest, big)
+    assert biggest < 1 << 53
+
+
+def test_constructed_cases():
+    """Shared end points, T-junctions, collinear overlaps and disjoint
+    collinear pieces, zero-length edges and parallel lines."""
+    cases = [
+        (((0, 0), (4, 4)), ((0, 4), (4, 0))),      # proper crossing
+        (((0, 0), (4, 0)), ((4, 0), (4, 4))),      # shared end point
+        (((0, 0), (4, 0)), ((2, 0), (2, 3))),      # T-junction
+        (((0, 0), (4, 0)), ((2, 0), (6, 0))),      # collinear overlap
+        (((0, 0), (1, 0)), ((2, 0), (3, 0))),      # collinear, disjoint
+        (((0, 0), (0, 0)), ((0, 0), (3, 3))),      # zero-length edge on the other
+        (((1, 1), (1, 1)), ((0, 0), (0, 3))),      # zero-length edge off the other
+        (((0, 0), (4, 0)), ((0, 1), (4, 1))),      # parallel lines
+        (((-LIM, -LIM), (LIM, LIM)), ((-LIM, LIM), (LIM, -LIM))),   # extreme corners
+        (((-LIM, 0), (LIM, 0)), ((LIM, -LIM), (LIM, LIM))),         # extreme T-junction
+    ]
+    want = [(True, False), (False, True), (False, True), (False, True), (False, True),
+            (False, True), (False, False), (False, False), (True, False), (False, True)]
+    for (e, f), w in zip(cases, want):
+        got = kernel(e, f)[:2]
+        assert got == classify(printed(e, f)) == w, (e, f, got)
+        assert kernel(f, e)[:2] == got, (e, f)
