@@ -55,7 +55,10 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                                               double angc, uint32_t &n_proper,
                                               uint32_t &n_touch, double &acc) {
     const int wave = tid >> 6, lane = tid & 63;
-#pragma unroll 2
+    // the column sums of four consecutive columns, one byte each (little
+    // endian, as colk's bytes lie), go to LDS as one 32-bit store
+    uint32_t packed = 0;
+#pragma unroll 4
     for (int j = 0; j < kChunk; ++j) {
         const double cX = col[j].x, cY = col[j].y;
         const double cDX = col[j].dx, cDY = col[j].dy;
@@ -134,7 +137,11 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
                           (int)__popcll(__builtin_amdgcn_ballot_w64(neg));
             }
         }
-        if (lane == 0) colk[wave * kChunk + j] = (int8_t)colsum;   // |colsum| <= 64 K
+        packed |= ((uint32_t)colsum & 0xffu) << (8 * (j & 3));     // |colsum| <= 64 K
+        if ((j & 3) == 3) {
+            if (lane == 0) __builtin_memcpy(&colk[wave * kChunk + j - 3], &packed, 4);
+            packed = 0;
+        }
     }
 }
 
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void adjoint_sweep_kernel(
     __shared__ int2 rid[kBlock * K];
     // per-wave column sums of q: |sum| <= 64 K fits a byte, which keeps the
     // block's LDS under 20 KB (8 blocks per CU)
-    __shared__ int8_t colk[(kBlock / 64) * kChunk];
+    __shared__ __align__(16) int8_t colk[(kBlock / 64) * kChunk];
     __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
     __shared__ double red_d[kBlock / 64];
     // start-up at raised wave priority, dropped while a unit is swept (the
