@@ -58,11 +58,19 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
     // the column sums of four consecutive columns, one byte each (little
     // endian, as colk's bytes lie), go to LDS as one 32-bit store
     uint32_t packed = 0;
-#pragma unroll 4
-    for (int j = 0; j < kChunk; ++j) {
-        const double cX = col[j].x, cY = col[j].y;
-        const double cDX = col[j].dx, cDY = col[j].dy;
-        const double cC = col[j].c, cTH = col[j].th;
+    // one LDS address per group of four columns, opaque so that the compiler
+    // neither rebuilds it per column (one instruction per pair at one row per
+    // thread) nor folds it away; the columns load at immediate offsets
+    typedef __attribute__((address_space(3))) const EdgeRec lds_rec;
+    for (int j0 = 0; j0 < kChunk; j0 += 4) {
+    lds_rec *grp = (lds_rec *)(col + j0);
+    __asm__ volatile("" : "+v"(grp));
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        const int j = j0 + jj;
+        const double cX = grp[jj].x, cY = grp[jj].y;
+        const double cDX = grp[jj].dx, cDY = grp[jj].dy;
+        const double cC = grp[jj].c, cTH = grp[jj].th;
         int colsum = 0;
         uint64_t zm[K];
         uint64_t any_zero = 0;
@@ -142,6 +150,7 @@ __device__ __forceinline__ void adjoint_chunk(const EdgeRec *__restrict__ col,
             if (lane == 0) __builtin_memcpy(&colk[wave * kChunk + j - 3], &packed, 4);
             packed = 0;
         }
+    }
     }
 }
 
