@@ -250,8 +250,35 @@ bool ws_layout(int64_t n_nodes, int64_t n_edges, WsLayout *L) {
     L->hash = take(sizeof(unsigned long long) * (size_t)h);
     L->kacc = take(sizeof(int32_t) * (size_t)L->n_edge_pad);
     L->fwd = take(sizeof(Fwd));
+    // hub order (rare-path pruning of large single-layout edge sweeps)
+    const int64_t hs = n_edges >= kHubSortMinEdges ? E : 0;
+    const int64_t n_hist = hs > 0 ? 256 * ((hs + kSortTile - 1) / kSortTile) : 0;
+    L->hub_deg = take(hs > 0 ? sizeof(uint32_t) * (size_t)V : 0);
+    L->hub_keys = take(sizeof(uint32_t) * (size_t)hs);
+    L->hub_vals = take(sizeof(int32_t) * (size_t)hs);
+    L->hub_keys2 = take(sizeof(uint32_t) * (size_t)hs);
+    L->hub_vals2 = take(sizeof(int32_t) * (size_t)hs);
+    L->hub_hist = take(sizeof(uint32_t) * (size_t)n_hist);
+    L->hub_hist_off = take(hs > 0 ? sizeof(uint32_t) * (size_t)(n_hist + 1) : 0);
+    L->hub_scan = take(hs > 0 ? sizeof(unsigned long long) * (size_t)((n_hist + 2047) / 2048 + 1)
+                              : 0);
     L->total = off;
     return true;
+}
+
+// The hub-sort buffers of a workspace, or NULL where it has none.
+static const HubSortBufs *hub_bufs(const WsLayout &L, char *w, int64_t n_edges,
+                                   HubSortBufs *B) {
+    if (n_edges < kHubSortMinEdges) return nullptr;
+    B->deg = (uint32_t *)(w + L.hub_deg);
+    B->keys = (uint32_t *)(w + L.hub_keys);
+    B->vals = (int32_t *)(w + L.hub_vals);
+    B->keys2 = (uint32_t *)(w + L.hub_keys2);
+    B->vals2 = (int32_t *)(w + L.hub_vals2);
+    B->hist = (uint32_t *)(w + L.hub_hist);
+    B->hist_off = (uint32_t *)(w + L.hub_hist_off);
+    B->scan_tile = (unsigned long long *)(w + L.hub_scan);
+    return B;
 }
 
 }  // namespace rb
@@ -329,7 +356,7 @@ static rb_status crossing_launch(const float *x, const float *y, int64_t n_nodes
                                  bool angle, double ideal, uint64_t *out_count,
                                  uint64_t *out_proper, double *out_metric, double *out_dev_sum,
                                  EdgeRec *rec, int64_t n_edge_pad, CrossPartial *part,
-                                 hipStream_t st);
+                                 const HubSortBufs *hub, hipStream_t st);
 
 static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes,
                                  const int32_t *src, const int32_t *dst, int64_t n_edges,
@@ -345,19 +372,23 @@ static rb_status crossing_common(const float *x, const float *y, int64_t n_nodes
                                    (hipStream_t)stream)))
         return s;
     char *w = (char *)ws;
+    HubSortBufs hb;
     return crossing_launch(x, y, n_nodes, src, dst, n_edges, angle, ideal, out_count, out_proper,
                            out_metric, out_dev_sum, (EdgeRec *)(w + L.edge_rec), L.n_edge_pad,
-                           (CrossPartial *)(w + L.partial), (hipStream_t)stream);
+                           (CrossPartial *)(w + L.partial), hub_bufs(L, w, n_edges, &hb),
+                           (hipStream_t)stream);
 }
 
-// Edge preparation, the all-pairs sweep and its finalize into caller-chosen
-// record (n_edge_pad entries) and partial-slot (kMaxPartials) buffers.
+// Edge preparation (in hub order when hub is not NULL), the all-pairs sweep
+// and its finalize into caller-chosen record (n_edge_pad entries) and
+// partial-slot (kMaxPartials) buffers.  The pairs and so the results do not
+// depend on the record order, apart from the rounding of the angle sums.
 static rb_status crossing_launch(const float *x, const float *y, int64_t n_nodes,
                                  const int32_t *src, const int32_t *dst, int64_t n_edges,
                                  bool angle, double ideal, uint64_t *out_count,
                                  uint64_t *out_proper, double *out_metric, double *out_dev_sum,
                                  EdgeRec *rec, int64_t n_edge_pad, CrossPartial *part,
-                                 hipStream_t st) {
+                                 const HubSortBufs *hub, hipStream_t st) {
     if (const int f = inject_fault("launch", "rb_edge_crossing / rb_crossing_angle")) return (rb_status)f;
     const int v = tuned_variant(angle ? 1 : 0, false, n_edges);
     const int rows = cross_variant(v).rows;
@@ -368,7 +399,11 @@ static rb_status crossing_launch(const float *x, const float *y, int64_t n_nodes
     a.n_units = sweep_units(n_edges, rows);
     a.unit_base = 0;
     const int grid = (int)std::min<int64_t>(a.n_units, cross_grid(v, angle));
-    hipError_t e = launch_edge_prep(x, y, src, dst, n_nodes, n_edges, n_edge_pad, rec, st);
+    hipError_t e = hipSuccess;
+    if (hub && (e = launch_hub_order(src, dst, n_nodes, n_edges, *hub, st)) != hipSuccess)
+        return hip_fail(e, "hub order launch");
+    e = launch_edge_prep_ordered(x, y, src, dst, n_nodes, n_edges, n_edge_pad,
+                                 hub ? hub->vals : nullptr, rec, st);
     if (e != hipSuccess) return hip_fail(e, "edge_prep launch");
     TimedLaunch tl(0, st);
     e = launch_cross_sweep(v, angle, rec, a, grid, ideal, part, st);
@@ -660,7 +695,7 @@ rb_status rb_crossing_angle_noalloc(const float *x, const float *y, int64_t n_no
     const int64_t pad = (int64_t)round_up((size_t)std::max<int64_t>(n_edges, 1), kRecPad);
     return crossing_launch(x, y, n_nodes, src, dst, n_edges, true, ideal_angle, out_count,
                            nullptr, out_metric, out_dev_sum, (EdgeRec *)w, pad,
-                           (CrossPartial *)(w + kNoAllocRecBytes), (hipStream_t)stream);
+                           (CrossPartial *)(w + kNoAllocRecBytes), nullptr, (hipStream_t)stream);
 }
 
 rb_status rb_min_angle(const float *x, const float *y, int64_t n_nodes, const int32_t *src,

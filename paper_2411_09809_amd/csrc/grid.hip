@@ -32,8 +32,7 @@
 namespace rb {
 namespace {
 
-constexpr int kSortTile = 2048;              // items per block and pass
-constexpr int kSortPer = kSortTile / 256;
+constexpr int kSortPer = kSortTile / 256;    // items per thread and pass
 
 __global__ __launch_bounds__(256) void sort_hist_kernel(const uint32_t *__restrict__ keys,
                                                         int64_t n, int shift,
@@ -289,6 +288,27 @@ __device__ __forceinline__ uint32_t hilbert14(uint32_t x, uint32_t y) {
 // classes by octave of their side (one long edge in a tile of short ones
 // would widen that tile's box), each class again in Hilbert order; edges
 // with bad ids after all others
+// key of edge e = its hub: the end point of larger degree, the smaller id
+// on a tie (0 for an edge with ids out of range, which the sweep skips)
+__global__ __launch_bounds__(256) void hub_key_kernel(const int32_t *__restrict__ src,
+                                                      const int32_t *__restrict__ dst,
+                                                      int64_t n_nodes, int64_t m,
+                                                      const uint32_t *__restrict__ deg,
+                                                      uint32_t *__restrict__ keys,
+                                                      int32_t *__restrict__ vals) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = src[e], t = dst[e];
+        uint32_t key = 0;
+        if (dev::valid_ids(s, t, n_nodes)) {
+            const uint32_t ds = deg[s], dt = deg[t];
+            key = (uint32_t)((ds > dt || (ds == dt && s <= t)) ? s : t);
+        }
+        keys[e] = key;
+        vals[e] = (int32_t)e;
+    }
+}
+
 __global__ __launch_bounds__(256) void edge_key_kernel(const float *__restrict__ x,
                                                        const float *__restrict__ y,
                                                        const int32_t *__restrict__ src,
@@ -500,6 +520,17 @@ hipError_t launch_radix_sort(uint32_t *keys, int32_t *vals, uint32_t *keys2, int
         std::swap(vi, vo);
     }
     return hipSuccess;
+}
+
+hipError_t launch_hub_order(const int32_t *src, const int32_t *dst, int64_t n_nodes,
+                            int64_t n_edges, const HubSortBufs &B, hipStream_t st) {
+    if (n_edges <= 0) return hipSuccess;
+    RB_TRY(launch_degrees(src, dst, n_nodes, n_edges, B.deg, st));
+    hipLaunchKernelGGL(hub_key_kernel, dim3(blocks_for(n_edges)), dim3(256), 0, st, src, dst,
+                       n_nodes, n_edges, B.deg, B.keys, B.vals);
+    RB_TRY(hipGetLastError());
+    return launch_radix_sort(B.keys, B.vals, B.keys2, B.vals2, n_edges, B.hist, B.hist_off,
+                             B.scan_tile, st);
 }
 
 hipError_t launch_grid_bounds(const float *x, const float *y, int64_t n, GridParams *gp,

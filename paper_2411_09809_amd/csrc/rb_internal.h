@@ -131,6 +131,8 @@ inline bool variant_offered(int kind, bool batch, int v) {
 struct WsLayout {
     size_t edge_rec, node_rec, partial, scalars;
     size_t deg, cursor, offs, angles, nbr, dv, big_list, hash, kacc, fwd;
+    // hub order of the edge records (empty below kHubSortMinEdges edges)
+    size_t hub_deg, hub_keys, hub_vals, hub_keys2, hub_vals2, hub_hist, hub_hist_off, hub_scan;
     size_t total;
     int64_t n_edge_pad, n_node_pad, hash_size;
 };
@@ -277,6 +279,9 @@ hipError_t launch_min_angle_grad(const float *x, const float *y, int64_t n_nodes
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_zero_scalars(Scalars *sc, hipStream_t st);
+// deg[v] = number of end points of valid edges at node v (deg holds max(n_nodes, 1) words)
+hipError_t launch_degrees(const int32_t *src, const int32_t *dst, int64_t n_nodes,
+                          int64_t n_edges, uint32_t *deg, hipStream_t st);
 // exclusive scan of deg[0..n) into offs[0..n] (tile: ceil(n/2048) scratch words)
 hipError_t launch_scan(const uint32_t *deg, int64_t n, unsigned long long *tile, uint32_t *offs,
                        hipStream_t st);
@@ -285,10 +290,33 @@ hipError_t launch_min_angle_nodes(const uint32_t *deg, const uint32_t *offs, dou
                                   int64_t n_nodes, double *dv, int32_t *big, Scalars *sc,
                                   hipStream_t st);
 
-// loss w_a (1 - E_ca) + w_l M_l + w_m (1 - M_a) and its gradient with respect to x, y
+// Stable LSD radix sort of (key, value) pairs, four 8-bit passes; the result
+// ends in keys, vals.  hist and hist_off hold 256 ceil(n / kSortTile) words
+// (hist_off one more), scan_tile ceil(that / 2048) + 1.
+constexpr int kSortTile = 2048;
 hipError_t launch_radix_sort(uint32_t *keys, int32_t *vals, uint32_t *keys2, int32_t *vals2,
                              int64_t n, uint32_t *hist, uint32_t *hist_off,
                              unsigned long long *scan_tile, hipStream_t st);
+
+// Hub order of the edge records.  An edge pair that shares an end id has
+// both orientation products zero, so the sweep's rare path runs for every
+// wave-column holding one.  In input order the incident pairs of a
+// power-law graph's hubs are spread over every wave-column (about one in 25
+// holds one); sorted by the end point of larger degree, a hub's edges are
+// consecutive records and its incident pairs fill a few tiles instead.  The
+// sort costs about a millisecond, so single-layout sweeps of at least
+// kHubSortMinEdges edges use it.
+constexpr int64_t kHubSortMinEdges = 1ll << 20;
+struct HubSortBufs {
+    uint32_t *deg, *keys, *keys2, *hist, *hist_off;
+    int32_t *vals, *vals2;
+    unsigned long long *scan_tile;
+};
+// vals[0..n_edges) = the edge ids ordered by (hub id, edge id), where the
+// hub of an edge is its end point of larger degree (the smaller id on a
+// tie); edges with ids out of range go first.
+hipError_t launch_hub_order(const int32_t *src, const int32_t *dst, int64_t n_nodes,
+                            int64_t n_edges, const HubSortBufs &B, hipStream_t st);
 hipError_t launch_grid_bounds(const float *x, const float *y, int64_t n, GridParams *gp,
                               int min_shift, int axis_bits, hipStream_t st);
 // Sweep over an explicit unit list: tile I meets chunks list[tile_off[I] ..
@@ -327,6 +355,7 @@ hipError_t launch_strip_crossing(const float *x, const float *y, const int32_t *
 hipError_t launch_occlusion_grid(const float *x, const float *y, int64_t n, double T,
                                  const GridWs &G, char *w, unsigned long long *out_count,
                                  hipStream_t st);
+// loss w_a (1 - E_ca) + w_l M_l + w_m (1 - M_a) and its gradient with respect to x, y
 hipError_t launch_loss_grad(const float *x, const float *y, int64_t n_nodes, const int32_t *src,
                             const int32_t *dst, int64_t n_edges, double ideal, double w_a,
                             double w_l, double w_m, double *out_loss, double *gx, double *gy,

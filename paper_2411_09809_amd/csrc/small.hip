@@ -743,6 +743,17 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
     return hipGetLastError();
 }
 
+hipError_t launch_degrees(const int32_t *src, const int32_t *dst, int64_t n_nodes,
+                          int64_t n_edges, uint32_t *deg, hipStream_t st) {
+    RB_TRY(launch_fill_u32(deg, n_nodes > 0 ? n_nodes : 1, 0u, st));
+    if (n_edges > 0) {
+        hipLaunchKernelGGL(degree_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, src, dst,
+                           n_nodes, n_edges, deg);
+        RB_LAUNCHED();
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_zero_scalars(Scalars *sc, hipStream_t st) {
     hipLaunchKernelGGL(zero_scalars_kernel, dim3(1), dim3(64), 0, st, sc);
     return hipGetLastError();
@@ -782,13 +793,8 @@ hipError_t launch_min_angle(const float *x, const float *y, int64_t n_nodes, con
 
     const int64_t V = n_nodes > 0 ? n_nodes : 1;
     RB_TRY(launch_zero_scalars(B.sc, st));
-    RB_TRY(launch_fill_u32(B.deg, V, 0u, st));
     RB_TRY(launch_fill_u32(B.cursor, V, 0u, st));
-    if (n_edges > 0) {
-        hipLaunchKernelGGL(degree_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, src, dst,
-                           n_nodes, n_edges, B.deg);
-        RB_LAUNCHED();
-    }
+    RB_TRY(launch_degrees(src, dst, n_nodes, n_edges, B.deg, st));
     RB_TRY(launch_scan(B.deg, V, tile, B.offs, st));
     if (n_edges > 0) {
         hipLaunchKernelGGL(fill_angles_kernel, dim3(grid_for(n_edges)), dim3(256), 0, st, x, y,

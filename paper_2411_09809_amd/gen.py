@@ -22,7 +22,8 @@ evaluation workloads:
                           hub-heavy Gaussian clusters in [0,2^20)^2.
 
 Hand-made layouts (convex K4, star, grid, K_n in convex position, two-row
-complete bipartite) are here too, for the closed-form checks.
+complete bipartite, hubs beside a hatch) are here too, for the closed-form
+checks.
 """
 from __future__ import annotations
 
@@ -428,6 +429,53 @@ def two_row_bipartite(m: int, n: int) -> Layout:
     y = np.concatenate([np.zeros(m), np.ones(n)])
     s, d = zip(*[(i, m + j) for i in range(m) for j in range(n)])
     return _finish(x, y, s, d, name=f"K{m},{n}_two_rows")
+
+
+def hatch_and_stars(n_lines: int, n_stars: int, q: int, r: int, seed: int = 0) -> Layout:
+    """Hubs next to a hatch, with node ids and edge order shuffled.
+
+    Hatch: n_lines horizontal segments (y = 2i + 1, x in [0, 2 n_lines]) and
+    n_lines vertical ones (x = 2j + 1, y in [0, 2 n_lines]); every
+    horizontal crosses every vertical at an interior point, at 90 degrees.
+    Star k, to the right of the hatch: a centre (cx, cy) joined to leaves
+    (cx - r, cy + t) and (cx + r, cy + t) for even t in [-2q, 2q], and a bar
+    y = cy + 1 over x in [cx - r - 1, cx + r + 1].  The bar crosses, at an
+    interior point of both, exactly the spokes with t >= 2 (2q per star, at
+    the angle atan(t / r)); the spokes share the centre, and nothing else
+    meets.  So there are n_lines^2 + 2 q n_stars crossings, and
+    4 n_lines + n_stars (4q + 3) nodes and 2 n_lines + n_stars (4q + 3)
+    edges, the centres of degree 4q + 2.
+    """
+    n = n_lines
+    xs, ys, es = [], [], []
+    m = 0
+
+    def seg(x0, y0, x1, y1):
+        nonlocal m
+        xs.extend((x0, x1)); ys.extend((y0, y1)); es.append((m, m + 1)); m += 2
+
+    for i in range(n):
+        seg(0, 2 * i + 1, 2 * n, 2 * i + 1)
+        seg(2 * i + 1, 0, 2 * i + 1, 2 * n)
+    cx = 2 * n + r + 8
+    for k in range(n_stars):
+        cy = 2 * q + 4 + k * (4 * q + 8)
+        c = m
+        xs.append(cx); ys.append(cy); m += 1
+        for t in range(-2 * q, 2 * q + 1, 2):
+            for side in (-r, r):
+                xs.append(cx + side); ys.append(cy + t); es.append((c, m)); m += 1
+        seg(cx - r - 1, cy + 1, cx + r + 1, cy + 1)
+    assert max(max(xs), max(ys)) < COORD_LIMIT
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(m)                 # node i gets id perm[i]
+    x = np.empty(m); y = np.empty(m)
+    x[perm] = xs; y[perm] = ys
+    e = perm[np.asarray(es, dtype=np.int64)]
+    e = e[rng.permutation(len(es))]
+    flip = rng.random(len(es)) < 0.5
+    s = np.where(flip, e[:, 1], e[:, 0]); d = np.where(flip, e[:, 0], e[:, 1])
+    return _finish(x, y, s, d, name=f"hatch{n}_stars{n_stars}x{4 * q + 2}_s{seed}")
 
 
 def square_lattice(k: int, spacing: int, diameter: float) -> Layout:

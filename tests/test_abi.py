@@ -43,6 +43,9 @@ def test_version_and_workspace(L):
     assert L.rb_workspace_size(0, 0) > 0
     assert L.rb_workspace_size(-1, 5) == 0
     assert L.rb_workspace_size(10, 1 << 31) == 0
+    # from 2^20 edges on, room for the hub sort: degrees, keys and values twice
+    below, at = L.rb_workspace_size(1000, (1 << 20) - 1), L.rb_workspace_size(1000, 1 << 20)
+    assert at - below >= 1000 * 4 + 16 * (1 << 20)
 
 
 def _err(L):

@@ -294,6 +294,28 @@ def test_two_row_bipartite(orc, m, n):
     assert c == p == math.comb(m, 2) * math.comb(n, 2)
 
 
+def hatch_and_stars_closed_form(n, n_stars, q, r, ideal):
+    """Crossings and deviation sum of gen.hatch_and_stars: n^2 right angles
+    in the hatch, and per star the bar against the spokes to (cx +- r, cy + t),
+    t = 2, 4, .., 2q, at the angle atan(t / r)."""
+    dev = n * n * (math.pi / 2 - ideal) / ideal
+    dev += n_stars * 2 * sum(abs(ideal - math.atan(t / r)) / ideal for t in range(2, 2 * q + 1, 2))
+    return n * n + 2 * q * n_stars, dev
+
+
+@pytest.mark.parametrize("n,n_stars,q,r,seed", [(12, 2, 5, 7, 1), (30, 3, 9, 20, 2),
+                                                (8, 1, 1, 3, 3), (5, 4, 12, 2, 4)])
+def test_hatch_and_stars(orc, n, n_stars, q, r, seed):
+    """Hubs of degree 4q + 2 beside a hatch, ids and edge order shuffled."""
+    L = gen.hatch_and_stars(n, n_stars, q, r, seed)
+    assert L.n_edges == 2 * n + n_stars * (4 * q + 3)
+    want_c, want_d = hatch_and_stars_closed_form(n, n_stars, q, r, IDEAL)
+    eca, cnt, dev = orc.crossing_angle(L.x, L.y, L.src, L.dst, IDEAL)
+    assert cnt == want_c and orc.edge_crossing(L.x, L.y, L.src, L.dst) == (want_c, want_c)
+    assert dev == pytest.approx(want_d, rel=1e-12)
+    assert eca == pytest.approx(1 - want_d / want_c, rel=1e-12)
+
+
 def test_star_and_grid_have_no_crossings(orc):
     for L in (gen.star(12), gen.grid(6, 7), gen.grid(1, 9)):
         assert orc.edge_crossing(L.x, L.y, L.src, L.dst) == (0, 0)
