@@ -47,9 +47,12 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # products < 0; the larger one zero), and 4 for the angle term (difference of
 # line angles, fold, deviation, accumulate under the crossing mask).
 OPS_PER_EDGE_PAIR = 13
-# per node pair of the occlusion test: 2 FMA + 1 max (the exact count runs
-# only for the rare chunks that hold an occluding pair)
-OPS_PER_NODE_PAIR = 3
+# per node pair of the occlusion sweep's filter: one v_sad_u16 (the cell
+# distance) and half a v_min3_u32 (two distances folded into the row's
+# running minimum); the exact count (2 FMA, a compare and its count) runs only
+# for the chunks where some row comes within the cell limit, and for the
+# diagonal squares
+OPS_PER_NODE_PAIR = 1.5
 # per edge pair of the fused forward + adjoint sweep: the 13 above, then the
 # dot product of the directions (2), the sign product (v dot) cross (2), two
 # compares for q = +1 / -1 and the masked +-1 into the row's integer sum (2)

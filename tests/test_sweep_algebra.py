@@ -14,6 +14,7 @@ and classify a pair as crossing properly iff t < |cross| and as the rare case
 max(o1 o2, o3 o4) < 0 and == 0, and check that every intermediate stays below
 2^53 at the coordinate limit 2^20, so the kernels' FP64 arithmetic is exact.
 """
+import math
 import random
 
 import pytest
@@ -122,3 +123,60 @@ def test_constructed_cases():
         got = kernel(e, f)[:2]
         assert got == classify(printed(e, f)) == w, (e, f, got)
         assert kernel(f, e)[:2] == got, (e, f)
+
+
+# ---------------------------------------------------------------- node sweep
+def cell(v):
+    """The node sweep's cell coordinate: floor((v + 2^20) / 32) in [0, 65535]."""
+    return min(max((v + LIM) >> 5, 0), 65535)
+
+
+def cell_limit(T):
+    """t of the node sweep's filter: isqrt(2 T) / 32 + 2 (None: no pair occludes)."""
+    return None if T < 0 else math.isqrt(2 * T) // 32 + 2
+
+
+def threshold(d):
+    """Largest integer below d^2 (the occlusion test is |p - q|^2 <= T)."""
+    return -1 if d <= 0 else math.ceil(d * d) - 1
+
+
+@pytest.mark.parametrize("d", [0.5, 1.0, 8.0, 16.0, 45.3, 64.0, 1000.0, 30000.0])
+def test_cell_filter_keeps_every_occluding_pair(d):
+    """Every pair with |p - q|^2 <= T has cell distance |dcx| + |dcy| <= t:
+    offsets on and near the boundary circle (the largest L1 for a given
+    distance is on the diagonals), at every alignment to the 32-unit cells,
+    including the clamped extremes of the coordinate range."""
+    T = threshold(d)
+    t = cell_limit(T)
+    rng = random.Random(int(d * 100))
+    r = math.isqrt(T)
+    offsets = set()
+    for dx in range(0, r + 1, max(1, r // 200)):
+        dy = math.isqrt(T - dx * dx)
+        offsets.update({(dx, dy), (dy, dx), (dx, max(dy - 1, 0))})
+    for dx, dy in offsets:
+        assert dx * dx + dy * dy <= T
+        for _ in range(12):
+            px = rng.choice([rng.randint(-LIM, LIM), -LIM, LIM - dx, rng.randint(-64, 64)])
+            py = rng.choice([rng.randint(-LIM, LIM), -LIM, LIM - dy, rng.randint(-64, 64)])
+            for sx, sy in ((1, 1), (1, -1), (-1, 1), (-1, -1)):
+                qx, qy = px + sx * dx, py + sy * dy
+                if not (-LIM <= qx <= LIM and -LIM <= qy <= LIM):
+                    continue
+                dist = abs(cell(px) - cell(qx)) + abs(cell(py) - cell(qy))
+                assert dist <= t, (d, px, py, qx, qy, dist, t)
+    # the benchmark diameters attain the bound: from the last point of a
+    # cell along the diagonal
+    if d in (8.0, 16.0, 64.0):
+        h = math.isqrt(T // 2)
+        p = -LIM + 31
+        assert abs(cell(p) - cell(p + h)) * 2 == t, (d, h, t)
+
+
+def test_cell_limit_special_cases():
+    assert cell_limit(threshold(0.0)) is None          # nothing occludes
+    assert cell_limit(threshold(0.5)) == 2             # T = 0: coincident nodes only
+    assert cell_limit(threshold(16.0)) == 2            # 2 T = 510: isqrt 22
+    assert cell_limit(threshold(64.0)) == 4            # 2 T = 8190: isqrt 90
+    assert cell(-LIM) == 0 and cell(LIM) == cell(LIM - 32) == 65535 and cell(LIM - 33) == 65534
