@@ -44,16 +44,18 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # against the other's line; the orientation products o1 o2 and o3 o4 have the
 # signs of |t1| - |cross| and |t3| - |cross|), 2 for the cross product of the
 # directions, 1 max of |t1| and |t3|, 2 compares against |cross| (both
-# products < 0; the larger one zero), and 4 for the angle term (difference of
-# line angles, fold, deviation, accumulate under the crossing mask).
-OPS_PER_EDGE_PAIR = 13
+# products < 0; the larger one zero), and 3 for the angle term on integer
+# line angles (v_sad_u32 each: |th_e - th_f|, its distance to pi/2, and the
+# deviation from the ideal angle added under the crossing mask).
+OPS_PER_EDGE_PAIR = 12
 # per node pair of the occlusion sweep's filter: one v_sad_u16 (the cell
 # distance) and half a v_min3_u32 (two distances folded into the row's
 # running minimum); the exact count (2 FMA, a compare and its count) runs only
 # for the chunks where some row comes within the cell limit, and for the
 # diagonal squares
 OPS_PER_NODE_PAIR = 1.5
-# per edge pair of the fused forward + adjoint sweep: the 13 above, then the
+# per edge pair of the fused forward + adjoint sweep: the same test with the
+# angle term on double line angles (13: four double operations for it), then the
 # dot product of the directions (2), the sign product (v dot) cross (2), two
 # compares for q = +1 / -1 and the masked +-1 into the row's integer sum (2)
 OPS_PER_ADJOINT_PAIR = 21

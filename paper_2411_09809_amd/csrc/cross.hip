@@ -33,7 +33,14 @@
 // maximum equals |cross|: 9 VALU operations per pair for the classification.
 // The crossing angle uses the per-edge line angles th in [0, pi):
 //   a = pi/2 - | |th_e - th_f| - pi/2 |,  dev = |ideal - a|
-// (a = 0 for parallel lines and zero-length edges).
+// (a = 0 for parallel lines and zero-length edges), on the angles held as
+// integers in units of pi / 2^26: |ideal - a| = | | |tq_e - tq_f| - 2^25 |
+// - beta | with beta = pi/2 - ideal, three v_sad_u32 (|x - y| + z), the last
+// adding into the lane's 32-bit sum under the crossing mask (4 double
+// operations before).  The sum is
+// folded into a double every 16 columns, before it can overflow.  Each
+// deviation is within 1.5 units (7.0e-8) of the same expression on the
+// double angles.
 #include "rb_device.h"
 #include "rb_internal.h"
 
@@ -59,92 +66,153 @@ __device__ __forceinline__ int thread_index(int wave_s) {
     return (wave_s << 6) + lane;
 }
 
+// An edge as the sweep holds it (rows in registers, columns in LDS): end-point
+// sums, direction and 2c (see sweep_form), the integer line angle and the end
+// ids.  c2 and tq share one 16-byte LDS read.
+struct __align__(16) SweepRec {
+    double sx, sy, dx, dy, c2;
+    uint32_t tq;
+    int32_t pad0;
+    int32_t s, t;
+    int32_t pad1, pad2;
+};
+static_assert(sizeof(SweepRec) == 64, "sweep record is 64 bytes");
+
+__device__ __forceinline__ SweepRec sweep_rec(const EdgeRec &r) {
+    const EdgeRec e = sweep_form(r);
+    SweepRec w;
+    w.sx = e.x; w.sy = e.y; w.dx = e.dx; w.dy = e.dy; w.c2 = e.c;
+    w.tq = e.tq; w.pad0 = 0;
+    w.s = e.s; w.t = e.t;
+    w.pad1 = 0; w.pad2 = 0;
+    return w;
+}
+
+// |x - y| on unsigned 32-bit integers, as one v_sad_u32 (the compiler has
+// no builtin for it and emits min, max and a subtraction); y may be uniform
+__device__ __forceinline__ uint32_t absdiff(uint32_t x, uint32_t y) {
+    uint32_t r;
+    __asm__("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+__device__ __forceinline__ uint32_t absdiff_s(uint32_t x, uint32_t y_uniform) {
+    uint32_t r;
+    __asm__("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(x), "s"(y_uniform));
+    return r;
+}
+
+// acc += |v - beta| in the lanes of `mask` only (through EXEC, as in
+// add_abs_masked)
+__device__ __forceinline__ void add_dev_masked(uint32_t &acc, uint32_t v, uint32_t beta,
+                                               uint64_t mask) {
+    uint64_t saved;
+    __asm__("s_and_saveexec_b64 %1, %2\n\t"
+            "v_sad_u32 %0, %3, %4, %0\n\t"
+            "s_mov_b64 exec, %1"
+            : "+v"(acc), "=&s"(saved)
+            : "s"(mask), "v"(v), "s"(beta)
+            : "scc");
+}
+
 template <int K, bool ANGLE, bool DIAG>
-__device__ __forceinline__ void sweep_chunk(const EdgeRec *__restrict__ col,
+__device__ __forceinline__ void sweep_chunk(const SweepRec *__restrict__ col,
                                             const int2 *__restrict__ rid,
                                             const double (&rX)[K], const double (&rY)[K],
                                             const double (&rDX)[K], const double (&rDY)[K],
-                                            const double (&rC)[K], const double (&rTH)[K],
-                                            int wave_s, int diag_off, double ideal,
-                                            double angc, uint32_t &n_proper, uint32_t &n_touch,
+                                            const double (&rC)[K], const uint32_t (&rTQ)[K],
+                                            int wave_s, int diag_off, uint32_t beta,
+                                            uint32_t &n_proper, uint32_t &n_touch,
                                             double &acc) {
+    const uint32_t ideal_q = kHalfPiQ - beta;          // the deviation of a = 0
+    // 16 columns add at most K * 16 deviations of at most 2^25 units: below
+    // 2^32 for K <= 4
+    static_assert(K <= 4, "the 32-bit angle sum is folded every 16 columns");
+    for (int j0 = 0; j0 < kChunk; j0 += 16) {
+        uint32_t accq = 0;
 #pragma unroll 4
-    for (int j = 0; j < kChunk; ++j) {
-        const double cX = col[j].x, cY = col[j].y;
-        const double cDX = col[j].dx, cDY = col[j].dy;
-        const double cC = col[j].c;
-        const double cTH = ANGLE ? col[j].th : 0.0;
-        // the K rows are independent straight-line work; one wave-uniform
-        // branch per column takes every row's rare pairs
-        uint64_t zm[K];
-        uint64_t any_zero = 0;
-        const int tid_d = DIAG ? thread_index(wave_s) : 0;   // per column, diagonal units only
-#pragma unroll
-        for (int r = 0; r < K; ++r) {
-            // rows and columns are in sweep form (end-point sums, 2c): t1 =
-            // 2 o1 + cr and t3 = 2 o3 - cr directly; the two compares are
-            // lane masks (scalar results) used as they are
-            const double t1 = fma(rDX[r], cY, fma(-rDY[r], cX, -rC[r]));
-            const double t3 = fma(cDX, rY[r], fma(-cDY, rX[r], -cC));
-            const double cr = fma(-rDY[r], cDX, rDX[r] * cDY);
-            const double t = dev::max_abs(t1, t3);
-            uint64_t lt = __builtin_amdgcn_ballot_w64(t < fabs(cr));
-            uint64_t le = __builtin_amdgcn_ballot_w64(t <= fabs(cr));
-            if (DIAG) {
-                // a diagonal unit keeps column index > row index: with the
-                // tile's first row as origin, diag_off + j > r * 256 + tid
-                const uint64_t tri = __builtin_amdgcn_ballot_w64(diag_off + j > r * kBlock + tid_d);
-                lt &= tri;
-                le &= tri;
-            }
-            zm[r] = le & ~lt;                              // max of the two products == 0
-            const uint64_t pmask = lt;                     // both products < 0
-            n_proper += (uint32_t)__popcll(pmask);
-            if (ANGLE) {
-                const double u = fabs(rTH[r] - cTH) - kHalfPi;
-                dev::add_abs_masked(acc, angc + fabs(u), pmask);
-            }
-            any_zero |= zm[r];
-        }
-        if (__builtin_expect(any_zero != 0, 0)) {
-            // most such pairs share an end id (the incident edges of a hub):
-            // the id test comes first and the rest runs only for the others
-            double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC, fth = cTH;
-            __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc), "+v"(fth));
-            // back from sweep form to start point and line constant (exact);
-            // after the opaque copy, so none of it is hoisted out of the loop
-            fx = 0.5 * (fx - fdx);
-            fy = 0.5 * (fy - fdy);
-            fc = 0.5 * fc;
-            const int2 fid = make_int2(col[j].s, col[j].t);
-            const int tid = thread_index(wave_s), lane = tid & 63;
+        for (int j = j0; j < j0 + 16; ++j) {
+            const double cX = col[j].sx, cY = col[j].sy;
+            const double cDX = col[j].dx, cDY = col[j].dy;
+            // c2 and tq as one 16-byte read (tq in the low word of the second half)
+            const double2 ct = *reinterpret_cast<const double2 *>(&col[j].c2);
+            const double cC = ct.x;
+            const uint32_t cTQ = ANGLE ? (uint32_t)__double_as_longlong(ct.y) : 0u;
+            // the K rows are independent straight-line work; one wave-uniform
+            // branch per column takes every row's rare pairs
+            uint64_t zm[K];
+            uint64_t any_zero = 0;
+            const int tid_d = DIAG ? thread_index(wave_s) : 0;   // per column, diagonal units only
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                bool ok = false;
-                if (((zm[r] >> lane) & 1) && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
-                    double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
-                    __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
-                    ex = 0.5 * (ex - edx);
-                    ey = 0.5 * (ey - edy);
-                    ec = 0.5 * ec;
-                    ok = dev::touching_apart(ex, ey, edx, edy, ec, fx, fy, fdx, fdy, fc);
-                    if (ANGLE && ok) {
-                        // parallel lines or a zero-length edge: a = 0
-                        const double crs = fma(-edy, fdx, edx * fdy);
-                        const double u = fabs(rTH[r] - fth) - kHalfPi;
-                        acc += (crs == 0.0) ? ideal : fabs(angc + fabs(u));
-                    }
+                // rows and columns are in sweep form (end-point sums, 2c): t1 =
+                // 2 o1 + cr and t3 = 2 o3 - cr directly; the two compares are
+                // lane masks (scalar results) used as they are
+                const double t1 = fma(rDX[r], cY, fma(-rDY[r], cX, -rC[r]));
+                const double t3 = fma(cDX, rY[r], fma(-cDY, rX[r], -cC));
+                const double cr = fma(-rDY[r], cDX, rDX[r] * cDY);
+                const double t = dev::max_abs(t1, t3);
+                uint64_t lt = __builtin_amdgcn_ballot_w64(t < fabs(cr));
+                uint64_t le = __builtin_amdgcn_ballot_w64(t <= fabs(cr));
+                if (DIAG) {
+                    // a diagonal unit keeps column index > row index: with the
+                    // tile's first row as origin, diag_off + j > r * 256 + tid
+                    const uint64_t tri =
+                        __builtin_amdgcn_ballot_w64(diag_off + j > r * kBlock + tid_d);
+                    lt &= tri;
+                    le &= tri;
                 }
-                n_touch += popc_ballot(ok);
+                zm[r] = le & ~lt;                              // max of the two products == 0
+                const uint64_t pmask = lt;                     // both products < 0
+                n_proper += (uint32_t)__popcll(pmask);
+                if (ANGLE) {
+                    // pi/2 - a = ||tq_e - tq_f| - 2^25|, then += |pi/2 - a - beta|
+                    const uint32_t e = absdiff_s(absdiff(rTQ[r], cTQ), kHalfPiQ);
+                    add_dev_masked(accq, e, beta, pmask);
+                }
+                any_zero |= zm[r];
+            }
+            if (__builtin_expect(any_zero != 0, 0)) {
+                // most such pairs share an end id (the incident edges of a hub):
+                // the id test comes first and the rest runs only for the others
+                double fx = cX, fy = cY, fdx = cDX, fdy = cDY, fc = cC;
+                uint32_t ftq = cTQ;
+                __asm__ volatile("" : "+v"(fx), "+v"(fy), "+v"(fdx), "+v"(fdy), "+v"(fc), "+v"(ftq));
+                // back from sweep form to start point and line constant (exact);
+                // after the opaque copy, so none of it is hoisted out of the loop
+                fx = 0.5 * (fx - fdx);
+                fy = 0.5 * (fy - fdy);
+                fc = 0.5 * fc;
+                const int2 fid = make_int2(col[j].s, col[j].t);
+                const int tid = thread_index(wave_s), lane = tid & 63;
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    bool ok = false;
+                    if (((zm[r] >> lane) & 1) && !dev::incident_ids(rid[r * kBlock + tid], fid)) {
+                        double ex = rX[r], ey = rY[r], edx = rDX[r], edy = rDY[r], ec = rC[r];
+                        __asm__ volatile("" : "+v"(ex), "+v"(ey), "+v"(edx), "+v"(edy), "+v"(ec));
+                        ex = 0.5 * (ex - edx);
+                        ey = 0.5 * (ey - edy);
+                        ec = 0.5 * ec;
+                        ok = dev::touching_apart(ex, ey, edx, edy, ec, fx, fy, fdx, fdy, fc);
+                        if (ANGLE && ok) {
+                            // parallel lines or a zero-length edge: a = 0
+                            const double crs = fma(-edy, fdx, edx * fdy);
+                            const uint32_t e = absdiff_s(absdiff(rTQ[r], ftq), kHalfPiQ);
+                            accq += (crs == 0.0) ? ideal_q : absdiff_s(e, beta);
+                        }
+                    }
+                    n_touch += popc_ballot(ok);
+                }
             }
         }
+        if (ANGLE) acc = fma((double)accq, kAngleUnit, acc);
     }
 }
 
 template <int K, int WAVES, bool ANGLE, bool BATCH>
 __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
     const EdgeRec *__restrict__ rec, SweepArgs a, double ideal, CrossPartial *__restrict__ part) {
-    __shared__ EdgeRec col[kChunk];
+    __shared__ SweepRec col[kChunk];
     __shared__ int2 rid[kBlock * K];
     __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
     __shared__ double red_d[kBlock / 64];
@@ -159,7 +227,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
     const int64_t u_begin = a.unit_base + first_unit(a.n_units, G, b);
     const int64_t u_end = a.unit_base + first_unit(a.n_units, G, b + 1);
     constexpr int64_t R = (int64_t)kBlock * K;
-    const double angc = ideal - kHalfPi;
+    // pi/2 - ideal in angle units (a scalar)
+    const uint32_t beta = __builtin_amdgcn_readfirstlane(quantize_angle(kHalfPi - ideal));
 
     int64_t L = 0;
     if (BATCH) {
@@ -176,7 +245,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
     int64_t I = tile_of_unit(lu, lay.n_row_tiles, lay.n_chunks, K);
     int64_t c = I * K + (lu - units_before(I, lay.n_chunks, K));
 
-    double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
+    double rX[K], rY[K], rDX[K], rDY[K], rC[K];
+    uint32_t rTQ[K];
     bool rows_loaded = false;
     unsigned long long tot_p = 0, tot_t = 0;
     double acc = 0.0;
@@ -213,11 +283,11 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
             const int tid = thread_index(wave_s);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = sweep_form(edge_row(rec + lay.rec_off,
+                const SweepRec e = sweep_rec(edge_row(rec + lay.rec_off,
                                                       I * R + (int64_t)r * kBlock + tid,
                                                       lay.n_chunks * kChunk));
-                rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
-                rC[r] = e.c; rTH[r] = e.th;
+                rX[r] = e.sx; rY[r] = e.sy; rDX[r] = e.dx; rDY[r] = e.dy;
+                rC[r] = e.c2; rTQ[r] = e.tq;
                 rid[r * kBlock + tid] = make_int2(e.s, e.t);
             }
             rows_loaded = true;
@@ -227,18 +297,18 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_sweep_kernel(
             // across the loop they take registers the 3- and 4-row variants
             // do not have
             const int tid = thread_index(wave_s);
-            col[tid] = sweep_form(rec[lay.rec_off + c * kChunk + tid]);
+            col[tid] = sweep_rec(rec[lay.rec_off + c * kChunk + tid]);
         }
         __syncthreads();
         __builtin_amdgcn_s_setprio(0);
         uint32_t n_p = 0, n_t = 0;
         const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
-            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, wave_s, diag_off,
-                                        ideal, angc, n_p, n_t, acc);
+            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTQ, wave_s, diag_off,
+                                        beta, n_p, n_t, acc);
         else
-            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, wave_s, diag_off,
-                                         ideal, angc, n_p, n_t, acc);
+            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTQ, wave_s, diag_off,
+                                         beta, n_p, n_t, acc);
         __builtin_amdgcn_s_setprio(3);
         tot_p += n_p;
         tot_t += n_t;
@@ -269,7 +339,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     const EdgeRec *__restrict__ rec, const int32_t *__restrict__ list,
     const uint32_t *__restrict__ tile_off, int64_t n_tiles, int64_t n_rec, double ideal,
     CrossPartial *__restrict__ part) {
-    __shared__ EdgeRec col[kChunk];
+    __shared__ SweepRec col[kChunk];
     __shared__ int2 rid[kBlock * K];
     __shared__ unsigned long long red_p[kBlock / 64], red_t[kBlock / 64];
     __shared__ double red_d[kBlock / 64];
@@ -284,7 +354,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     const int64_t u_begin = b < n_items ? first_unit(U, n_items, b) : 0;
     const int64_t u_end = b < n_items ? first_unit(U, n_items, b + 1) : 0;
     constexpr int64_t R = (int64_t)kBlock * K;
-    const double angc = ideal - kHalfPi;
+    // pi/2 - ideal in angle units (a scalar)
+    const uint32_t beta = __builtin_amdgcn_readfirstlane(quantize_angle(kHalfPi - ideal));
     if (u_begin == u_end) {                    // more blocks than kept units
         if (threadIdx.x == 0) {
             CrossPartial P;
@@ -303,7 +374,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
     }
     int64_t I = lo;
 
-    double rX[K], rY[K], rDX[K], rDY[K], rC[K], rTH[K];
+    double rX[K], rY[K], rDX[K], rDY[K], rC[K];
+    uint32_t rTQ[K];
     bool rows_loaded = false;
     unsigned long long tot_p = 0, tot_t = 0;
     double acc = 0.0;
@@ -318,9 +390,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
             const int tid = thread_index(wave_s);
 #pragma unroll
             for (int r = 0; r < K; ++r) {
-                const EdgeRec e = sweep_form(edge_row(rec, I * R + (int64_t)r * kBlock + tid, n_rec));
-                rX[r] = e.x; rY[r] = e.y; rDX[r] = e.dx; rDY[r] = e.dy;
-                rC[r] = e.c; rTH[r] = e.th;
+                const SweepRec e = sweep_rec(edge_row(rec, I * R + (int64_t)r * kBlock + tid, n_rec));
+                rX[r] = e.sx; rY[r] = e.sy; rDX[r] = e.dx; rDY[r] = e.dy;
+                rC[r] = e.c2; rTQ[r] = e.tq;
                 rid[r * kBlock + tid] = make_int2(e.s, e.t);
             }
             rows_loaded = true;
@@ -328,18 +400,18 @@ __global__ __launch_bounds__(kBlock, WAVES) void cross_list_kernel(
         const int64_t c = list[u];
         {
             const int tid = thread_index(wave_s);   // rebuilt each unit, as above
-            col[tid] = sweep_form(rec[c * kChunk + tid]);
+            col[tid] = sweep_rec(rec[c * kChunk + tid]);
         }
         __syncthreads();
         __builtin_amdgcn_s_setprio(0);
         uint32_t n_p = 0, n_t = 0;
         const int diag_off = (int)(c - I * K) * kChunk;   // used for c < (I + 1) K only
         if (c < (I + 1) * K)
-            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTH, wave_s, diag_off,
-                                        ideal, angc, n_p, n_t, acc);
+            sweep_chunk<K, ANGLE, true>(col, rid, rX, rY, rDX, rDY, rC, rTQ, wave_s, diag_off,
+                                        beta, n_p, n_t, acc);
         else
-            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTH, wave_s, diag_off,
-                                         ideal, angc, n_p, n_t, acc);
+            sweep_chunk<K, ANGLE, false>(col, rid, rX, rY, rDX, rDY, rC, rTQ, wave_s, diag_off,
+                                         beta, n_p, n_t, acc);
         __builtin_amdgcn_s_setprio(3);
         tot_p += n_p;
         tot_t += n_t;

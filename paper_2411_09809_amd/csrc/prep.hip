@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void edge_prep_kernel(const float *__restrict_
             r.x = 0.0; r.y = 0.0; r.dx = 0.0; r.dy = 0.0; r.c = -1.0; r.th = 0.0;
             r.s = -1; r.t = -1;
         }
-        r.pad0 = 0;
+        r.tq = quantize_angle(r.th);
         r.pad1 = 0;
         rec[e] = r;
     }

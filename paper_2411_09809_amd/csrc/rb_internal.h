@@ -16,14 +16,29 @@ namespace rb {
 // coordinates |.| <= 2^20 every field but th is an integer below 2^43 in
 // magnitude, hence exact in double, and so is every orientation value the
 // sweep derives from them (Algorithm 4's CCW).
+// tq is the line angle as an integer (see quantize_angle).
 struct __align__(16) EdgeRec {
     double x, y;
     double dx, dy;
     double c, th;
     int32_t s, t;
-    int32_t pad0, pad1;
+    uint32_t tq;
+    int32_t pad1;
 };
 static_assert(sizeof(EdgeRec) == 64, "edge record is 64 bytes");
+
+// The crossing sweeps' angle term runs on line angles held as integers in
+// units of u = pi / 2^26 (so pi/2 is exactly 2^25 u): tq = rint(th / u) in
+// [0, 2^26].  With a = pi/2 - ||tq_e - tq_f| - 2^25| and beta = pi/2 -
+// ideal in the same units, each crossing's deviation |ideal - a| is three
+// v_sad_u32 operations (|x - y| + z) in exact integer arithmetic.  Against
+// the same expression on the double angles, a is off by at most u (both
+// roundings) and beta by u/2, so each deviation by at most 1.5 u = 7.0e-8.
+constexpr uint32_t kHalfPiQ = 1u << 25;
+constexpr double kAngleUnit = 3.14159265358979323846 / 67108864.0;
+__host__ __device__ inline uint32_t quantize_angle(double th) {
+    return (uint32_t)rint(th * (67108864.0 / 3.14159265358979323846));
+}
 
 // Record i of a layout segment of n records, or a padding edge at and past
 // its end: a row tile (256 * rows records) need not divide the segment.
@@ -31,7 +46,7 @@ __device__ __forceinline__ EdgeRec edge_row(const EdgeRec *__restrict__ seg, int
     if (i < n) return seg[i];
     EdgeRec r;
     r.x = 0.0; r.y = 0.0; r.dx = 0.0; r.dy = 0.0; r.c = -1.0; r.th = 0.0;
-    r.s = -1; r.t = -1; r.pad0 = 0; r.pad1 = 0;
+    r.s = -1; r.t = -1; r.tq = 0; r.pad1 = 0;
     return r;
 }
 

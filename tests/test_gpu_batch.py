@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 from paper_2411_09809_amd import gen
+from _angle_tol import approx_dev, approx_eca
 
 pytestmark = pytest.mark.gpu
 IDEAL = gen.IDEAL_ANGLE
@@ -299,7 +300,7 @@ def test_every_variant_at_record_segment_ends(torch_mod, E, tmp_path):
             p = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, IDEAL)
             for got in (r, p):
                 assert got[1] == want[0][1]
-                assert got[0] == pytest.approx(want[0][0], rel=1e-9, abs=1e-12)
+                assert got[0] == approx_eca(want[0][0], IDEAL)
             if v == 3:          # the 4-row sweep is not offered for batches
                 assert lib.rb_tune_set(1, 1, E, v) == _lib.RB_EINVAL
                 continue
@@ -309,7 +310,7 @@ def test_every_variant_at_record_segment_ends(torch_mod, E, tmp_path):
             R = B.results()
             for i in range(3):
                 assert R["edge_crossing"][i] == want[i][1], (v, i)
-                assert R["crossing_angle"][i] == pytest.approx(want[i][0], rel=1e-9, abs=1e-12)
+                assert R["crossing_angle"][i] == approx_eca(want[i][0], IDEAL)
     finally:
         empty = tmp_path / "tune.txt"
         empty.write_text("")

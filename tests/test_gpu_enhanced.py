@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from paper_2411_09809_amd import gen
+from _angle_tol import approx_dev
 
 pytestmark = pytest.mark.gpu
 IDEAL = gen.IDEAL_ANGLE
@@ -64,7 +65,8 @@ def test_single_strip_is_exact(torch_mod):
     eca, cnt, dev, _ = metrics.enhanced_crossing(D.x, D.y, D.src, D.dst, 1 << 19)
     ex = metrics.crossing_angle(D.x, D.y, D.src, D.dst)
     assert cnt == ex[1]
-    assert dev == pytest.approx(ex[2], rel=1e-9)
+    # the strip kernel works on double line angles, the sweep on integer ones
+    assert dev == approx_dev(ex[2], cnt, gen.IDEAL_ANGLE)
 
 
 def test_clustered_and_workspace_growth(torch_mod):

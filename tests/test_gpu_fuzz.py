@@ -4,7 +4,8 @@ and grid paths and the overlapped evaluation against the oracle.
 Coordinates come from small grids, so collinear, touching, coincident and
 zero-length configurations are frequent; ids are distinct pairs without
 self-loops (the layout preconditions).  Counts must match bit for bit,
-floating metrics within 1e-9 relative (the bar is 1e-5).  The examples are
+floating metrics within 1e-9 relative (the bar is 1e-5), the crossing angle
+within the bound of its integer line angles (see _angle_tol).  The examples are
 derandomised, so every run checks the same layouts.
 """
 import sys
@@ -17,6 +18,7 @@ from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E
 
 import oracle  # noqa: E402
 from paper_2411_09809_amd import gen  # noqa: E402
+from _angle_tol import approx_dev, approx_eca  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 IDEAL = gen.IDEAL_ANGLE
@@ -67,11 +69,12 @@ def test_tiny_layouts_match_the_oracle(torch_mod, L):
     assert (c, p) == (want["edge_crossing"], want["proper_crossing"]), (L.x, L.y, L.src, L.dst)
     eca, cnt, dev = metrics.crossing_angle(D.x, D.y, D.src, D.dst, IDEAL)
     assert cnt == want["edge_crossing"]
-    assert close(eca, want["crossing_angle"]) and close(dev, want["crossing_dev_sum"])
+    assert eca == approx_eca(want["crossing_angle"], IDEAL)
+    assert dev == approx_dev(want["crossing_dev_sum"], cnt, IDEAL)
     assert metrics.node_occlusion(D.x, D.y, L.diameter) == want["node_occlusion"]
     assert metrics.node_occlusion_grid(D.x, D.y, L.diameter) == want["node_occlusion"]
     pr = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst, IDEAL)
-    assert pr[1] == want["edge_crossing"] and close(pr[0], want["crossing_angle"])
+    assert pr[1] == want["edge_crossing"] and pr[0] == approx_eca(want["crossing_angle"], IDEAL)
     ma, sdv, used = metrics.min_angle(D.x, D.y, D.src, D.dst)
     assert used == want["min_angle_n_used"] and close(ma, want["min_angle"])
     ml, mu = metrics.edge_length_variation(D.x, D.y, D.src, D.dst)
@@ -79,7 +82,8 @@ def test_tiny_layouts_match_the_oracle(torch_mod, L):
     got = metrics.evaluate(D)
     for k in ("node_occlusion", "edge_crossing", "min_angle_n_used"):
         assert got[k] == want[k]
-    for k in ("crossing_angle", "min_angle", "edge_length_variation"):
+    assert got["crossing_angle"] == approx_eca(want["crossing_angle"], IDEAL)
+    for k in ("min_angle", "edge_length_variation"):
         assert close(got[k], want[k])
 
 

@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 from paper_2411_09809_amd import gen
+from _angle_tol import approx_dev, approx_eca
 
 pytestmark = pytest.mark.gpu
 
@@ -195,7 +196,7 @@ def test_pruned_hand_cases(torch_mod):
         eca, cnt, dev = oracle.crossing_angle(L.x, L.y, L.src, L.dst, gen.IDEAL_ANGLE)
         p = metrics.crossing_angle_pruned(D.x, D.y, D.src, D.dst)
         assert p[1] == cnt, name
-        assert p[0] == pytest.approx(eca, rel=1e-9, abs=1e-12), name
+        assert p[0] == approx_eca(eca, gen.IDEAL_ANGLE), name
 
 
 @pytest.mark.parametrize("V,E,extent,seed", [(300, 700, 64, 1), (2000, 5000, 4096, 2),
@@ -209,7 +210,7 @@ def test_pruned_uniform_vs_oracle(torch_mod, V, E, extent, seed):
     brute, pruned = _both(metrics, D)
     assert brute[1] == cnt
     _same(brute, pruned)
-    assert pruned[2] == pytest.approx(dev, rel=1e-9, abs=1e-12)
+    assert pruned[2] == approx_dev(dev, cnt, gen.IDEAL_ANGLE)
 
 
 def test_pruned_local_edges(torch_mod):

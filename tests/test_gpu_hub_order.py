@@ -4,14 +4,15 @@ order.  The record order changes no pair, so both orders must give the
 closed-form result of gen.hatch_and_stars: hubs of degree 65,538 beside a
 hatch of 2^18 x 2^18 right-angle crossings, node ids and edge order shuffled.
 
-Counts exact; deviation sums within 1e-9 relative of the closed form (FP64,
-summation order).
+Counts exact; the crossing angle within the bound of the sweeps' integer
+line angles (see _angle_tol), and within 1e-9 between the two orders.
 """
 import sys
 
 import pytest
 
 from paper_2411_09809_amd import gen
+from _angle_tol import approx_dev, approx_eca
 from test_oracle_pins import hatch_and_stars_closed_form
 
 pytestmark = pytest.mark.gpu
@@ -43,8 +44,8 @@ def test_hatch_and_stars_at_the_hub_sort_threshold(metrics, q, seed):
     eca, cnt, dev = metrics.crossing_angle(D.x, D.y, D.src, D.dst, IDEAL)
     say(f"[hub] whole: count {cnt} dev {dev!r}")
     assert cnt == want_c
-    assert dev == pytest.approx(want_d, rel=1e-9)
-    assert eca == pytest.approx(1 - want_d / want_c, rel=1e-9)
+    assert dev == approx_dev(want_d, want_c, IDEAL)
+    assert eca == approx_eca(1 - want_d / want_c, IDEAL)
     c, p = metrics.edge_crossing(D.x, D.y, D.src, D.dst)
     say(f"[hub] count only: {c} proper {p}")
     assert c == p == want_c

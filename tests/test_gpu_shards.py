@@ -19,6 +19,7 @@ import pytest
 
 import oracle
 from paper_2411_09809_amd import gen
+from _angle_tol import approx_dev, approx_eca
 
 pytestmark = pytest.mark.gpu
 IDEAL = gen.IDEAL_ANGLE
@@ -72,7 +73,7 @@ def test_shards_match_oracle_rows(torch_mod):
         say(f"[shard-oracle] edges [{r0}, {r1})")
         rc, rdev = oracle.crossing_angle_rows(L.x, L.y, L.src, L.dst, IDEAL, r0, r1)
         assert c == rc
-        assert dev == pytest.approx(rdev, rel=1e-9)
+        assert dev == approx_dev(rdev, c, IDEAL)
         o, q0, q1 = metrics.node_occlusion_shard(D.x, D.y, 10.0, k, 3)
         assert o == oracle.node_occlusion_rows(L.x, L.y, 10.0, q0, q1)
 
@@ -107,7 +108,7 @@ def test_powerlaw_shards_match_oracle_rows(powerlaw):
         assert r1 > r0
         rc, rdev = oracle.crossing_angle_rows(L.x, L.y, L.src, L.dst, IDEAL, r0, r1)
         assert c == rc
-        assert dev == pytest.approx(rdev, rel=1e-9)
+        assert dev == approx_dev(rdev, c, IDEAL)
         o, q0, q1 = metrics.node_occlusion_shard(D.x, D.y, L.diameter, k, n)
         say(f"[powerlaw] occlusion shard {k}/{n}: nodes [{q0}, {q1}) count {o}")
         assert o == oracle.node_occlusion_rows(L.x, L.y, L.diameter, q0, q1)
