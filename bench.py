@@ -65,8 +65,8 @@ OPS_PER_ADJOINT_PAIR = 21
 # source they were measured on (first 16 hex digits of its sha256); None
 # otherwise.
 MEASURED_TRAFFIC = {
-    "powerlaw": {"source_sha": "7e414b5688de5684",
-                 "bytes": {(3, 5): 176680643.5625 * 1024 * 1.9998 + 4096 * 1024}},
+    "powerlaw": {"source_sha": "c593525979badbcf",
+                 "bytes": {(3, 5): 176845458.6875 * 1024 * 1.9998 + 4096 * 1024}},
 }
 
 
