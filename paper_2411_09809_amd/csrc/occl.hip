@@ -25,10 +25,11 @@
 // distance of a pair and one v_min3_u32 folds two of them into the row's
 // running minimum: 1.5 operations per pair against 3 for the exact test
 // (two fused multiply-adds and one max of g), and no per-pair scalar work
-// (the CU's single scalar unit would otherwise bound the sweep).  On the
-// benchmark layouts the condition holds for 3 to 17 times as many pairs as
-// actually occlude; each such pair sends its wave through the exact count of
-// one chunk.
+// (the CU's single scalar unit would otherwise bound the sweep).  The
+// condition holds for 3 times as many pairs as occlude on the 50,000-node
+// layout (diameter 64), 17 times on the 1,000,000-node one (diameter 16) and
+// about 100 times on small layouts with a diameter far below the 32-unit
+// cell; each such pair sends its wave through the exact count of one chunk.
 #include "rb_internal.h"
 
 namespace rb {
