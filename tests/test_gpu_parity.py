@@ -184,6 +184,22 @@ def test_occlusion_diameters(rb, d):
     assert rb.node_occlusion(D.x, D.y, d) == oracle.node_occlusion(L.x, L.y, d)
 
 
+@pytest.mark.parametrize("ideal", [math.pi / 2, math.radians(45), math.radians(1), 1e-3])
+def test_ideal_angles(rb, ideal):
+    """E_ca at other ideal angles: pi/2 - ideal in the sweep's angle units
+    from 0 to nearly 2^25, on a spread and a crowded layout."""
+    for L in (gen.uniform_layout(2000, 5000, extent=4096, seed=31),
+              gen.uniform_layout(400, 900, extent=40, seed=32)):
+        D = dev(L)
+        eca, cnt, devsum = rb.crossing_angle(D.x, D.y, D.src, D.dst, ideal)
+        want = oracle.crossing_angle(L.x, L.y, L.src, L.dst, ideal)
+        assert cnt == want[1]
+        assert eca == approx_eca(want[0], ideal)
+        assert devsum == approx_dev(want[2], cnt, ideal)
+        p = rb.crossing_angle_pruned(D.x, D.y, D.src, D.dst, ideal)
+        assert p[1] == cnt and p[0] == pytest.approx(eca, rel=1e-12, abs=1e-15)
+
+
 def test_high_degree_min_angle(rb):
     """Stars of every min-angle path: per-thread (deg <= 16), LDS sort
     (<= 2048) and in-place global sort (larger)."""

@@ -180,3 +180,58 @@ def test_cell_limit_special_cases():
     assert cell_limit(threshold(16.0)) == 2            # 2 T = 510: isqrt 22
     assert cell_limit(threshold(64.0)) == 4            # 2 T = 8190: isqrt 90
     assert cell(-LIM) == 0 and cell(LIM) == cell(LIM - 32) == 65535 and cell(LIM - 33) == 65534
+
+
+# ------------------------------------------------------- integer line angles
+ANGLE_UNIT = math.pi / 2 ** 26          # pi/2 is exactly 2^25 units
+HALF_PI_Q = 1 << 25
+
+
+def quantize(th):
+    """The edge preparation's rint(th / u) (round half to even, as rint)."""
+    return round(th * (2 ** 26 / math.pi))
+
+
+def deviation_double(th_e, th_f, ideal):
+    """|ideal - a| with a = pi/2 - ||th_e - th_f| - pi/2| (the acute angle)."""
+    a = math.pi / 2 - abs(abs(th_e - th_f) - math.pi / 2)
+    return abs(ideal - a)
+
+
+def deviation_integer(tq_e, tq_f, beta_q):
+    """The sweep's three v_sad_u32: ||tq_e - tq_f| - 2^25| then |. - beta|."""
+    e = abs(abs(tq_e - tq_f) - HALF_PI_Q)
+    return abs(e - beta_q)
+
+
+@pytest.mark.parametrize("ideal", [math.radians(70), math.pi / 2, math.radians(45),
+                                   math.radians(1), 1e-3])
+def test_integer_angle_deviation_within_one_and_a_half_units(ideal):
+    """Each crossing's deviation on the integer angles is within 1.5 units of
+    the double expression, stays in [0, 2^25], and 4 rows x 16 columns of
+    them cannot overflow the lanes' 32-bit sums."""
+    rng = random.Random(int(ideal * 1e6))
+    beta_q = quantize(math.pi / 2 - ideal)
+    worst = 0.0
+    cases = [(rng.uniform(0, math.pi), rng.uniform(0, math.pi)) for _ in range(20000)]
+    cases += [(0.0, math.pi / 2), (0.0, 0.0), (math.pi - 1e-12, 0.0), (1.0, 1.0 + ideal),
+              (0.3, 0.3 + math.pi / 2 - ideal), (2.0, 2.0 - ideal)]
+    for th_e, th_f in cases:
+        q = deviation_integer(quantize(th_e), quantize(th_f), beta_q)
+        assert 0 <= q <= HALF_PI_Q
+        err = abs(q * ANGLE_UNIT - deviation_double(th_e, th_f, ideal))
+        worst = max(worst, err)
+    assert worst <= 1.5 * ANGLE_UNIT + 1e-15
+    assert 4 * 16 * HALF_PI_Q < 2 ** 32
+
+
+def test_integer_deviation_invariant_under_a_quarter_turn():
+    """A 90-degree rotation adds pi/2 to every line angle (mod pi), which is
+    2^25 units: adding 2^25 (mod 2^26) to both angles of a pair leaves its
+    integer deviation unchanged."""
+    rng = random.Random(5)
+    for _ in range(5000):
+        a, b = rng.randrange(0, 2 ** 26), rng.randrange(0, 2 ** 26)
+        ra, rb = (a + HALF_PI_Q) % 2 ** 26, (b + HALF_PI_Q) % 2 ** 26
+        for beta_q in (0, 123456, HALF_PI_Q // 3):
+            assert deviation_integer(a, b, beta_q) == deviation_integer(ra, rb, beta_q)
