@@ -8,7 +8,8 @@ rb_node_occlusion_shard) and the 1M-node / 3M-edge power-law layout.
 * at 1M nodes / 3M edges, where the full O(|E|^2) oracle is out of reach:
   the first and last shard of 4096 against the oracle's row slices, the
   whole result against a 90-degree rotation of the layout (exact integer
-  transform; counts are invariant) and against a different sweep variant,
+  transform; counts are invariant), against the single shard (input record
+  order; the whole call sweeps in hub order) and a different sweep variant,
   and minimum angle and edge length variation against the oracle.
 Tolerance for deviation sums: 1e-9 relative (FP64, different summation order).
 """
@@ -128,6 +129,11 @@ def test_powerlaw_whole_invariants(powerlaw, torch_mod):
     eca_r, cnt_r, dev_r = metrics.crossing_angle(xr, yr, D.src, D.dst, IDEAL)
     assert cnt_r == cnt and dev_r == pytest.approx(dev, rel=1e-9)
     assert metrics.node_occlusion(xr, yr, L.diameter) == occ
+    # one shard of one sweeps the records in input order, the whole call in
+    # hub order (3M edges): the same pairs, so the same count and angle terms
+    c1, dev1, r0, r1 = metrics.crossing_angle_shard(D.x, D.y, D.src, D.dst, 0, 1, IDEAL)
+    say(f"[powerlaw] input order: E_c={c1} rows [{r0}, {r1})")
+    assert (c1, r0, r1) == (cnt, 0, L.n_edges) and dev1 == pytest.approx(dev, rel=1e-9)
     # a different sweep variant (other rows per thread, other tiles)
     import ctypes as C
     import os
