@@ -65,7 +65,7 @@ OPS_PER_ADJOINT_PAIR = 21
 # source they were measured on (first 16 hex digits of its sha256); None
 # otherwise.
 MEASURED_TRAFFIC = {
-    "powerlaw": {"source_sha": "c593525979badbcf",
+    "powerlaw": {"source_sha": "610bdfe6fa1ec413",
                  "bytes": {(3, 5): 176845458.6875 * 1024 * 1.9998 + 4096 * 1024}},
 }
 

@@ -36,11 +36,10 @@
 // (a = 0 for parallel lines and zero-length edges), on the angles held as
 // integers in units of pi / 2^26: |ideal - a| = | | |tq_e - tq_f| - 2^25 |
 // - beta | with beta = pi/2 - ideal, three v_sad_u32 (|x - y| + z), the last
-// adding into the lane's 32-bit sum under the crossing mask (4 double
-// operations before).  The sum is
-// folded into a double every 16 columns, before it can overflow.  Each
-// deviation is within 1.5 units (7.0e-8) of the same expression on the
-// double angles.
+// adding into the lane's 32-bit sum under the crossing mask, where the
+// double form takes four operations.  The sum is folded into a double every
+// 16 columns, before it can overflow.  Each deviation is within 1.5 units
+// (7.0e-8) of the same expression on the double angles.
 #include "rb_device.h"
 #include "rb_internal.h"
 
@@ -89,7 +88,8 @@ __device__ __forceinline__ SweepRec sweep_rec(const EdgeRec &r) {
 }
 
 // |x - y| on unsigned 32-bit integers, as one v_sad_u32 (the compiler has
-// no builtin for it and emits min, max and a subtraction); y may be uniform
+// no builtin for it and emits min, max and a subtraction); absdiff_s takes
+// a uniform y from a scalar register
 __device__ __forceinline__ uint32_t absdiff(uint32_t x, uint32_t y) {
     uint32_t r;
     __asm__("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(x), "v"(y));
