@@ -338,7 +338,7 @@ static rb_status occlusion_launch(const float *x, const float *y, int64_t n_node
     a.n_layouts = 1;
     a.n_units = sweep_units(n_nodes, rows, shift);
     a.unit_base = 0;
-    const int grid = (int)std::min<int64_t>(a.n_units, occl_grid(v));
+    const int grid = occl_grid(v, a.n_units, n_nodes);
     hipError_t e = launch_node_prep(x, y, n_nodes, n_node_pad, occlusion_threshold(diameter),
                                     rec, st);
     if (e != hipSuccess) return hip_fail(e, "node_prep launch");
@@ -526,7 +526,7 @@ rb_status rb_node_occlusion_shard(const float *x, const float *y, int64_t n_node
     a.n_layouts = 1;
     a.n_units = ue - ub;
     a.unit_base = ub;
-    const int grid = (int)std::min<int64_t>(a.n_units, occl_grid(v));
+    const int grid = occl_grid(v, a.n_units, n_nodes);
     hipError_t e = launch_node_prep(x, y, n_nodes, L.n_node_pad, occlusion_threshold(diameter),
                                     rec, st);
     if (e != hipSuccess) return hip_fail(e, "node_prep launch");
@@ -921,7 +921,8 @@ rb_status rb_autotune(const float *x, const float *y, int64_t n_nodes, const int
             a.n_layouts = 1;
             a.n_units = sweep_units(n, sv.rows, sv.col_shift);
             a.unit_base = 0;
-            const int grid = (int)std::min<int64_t>(a.n_units, occl ? occl_grid(v) : cross_grid(v, angle));
+            const int grid = occl ? occl_grid(v, a.n_units, n)
+                                  : (int)std::min<int64_t>(a.n_units, cross_grid(v, angle));
             float ms = 0.f;
             if (occl)
                 e = timed([&] { return launch_occl_sweep(v, nrec, a, grid, (OcclPartial *)(w + L.partial), st); }, &ms);

@@ -490,7 +490,7 @@ hipError_t upload(rb_batch *b, void *ws, hipStream_t st) {
     b->cross_units = cu;
     b->occl_units = ou;
     b->cross_grid_n = (int)std::min<int64_t>(cu, cross_grid(b->cross_var, true));
-    b->occl_grid_n = (int)std::min<int64_t>(ou, occl_grid(b->occl_var));
+    b->occl_grid_n = (int)std::min<int64_t>(ou, kMaxPartials);   // one unit per block
     b->uploaded = ws;
     ++b->plan_gen;
     return hipSuccess;

@@ -345,7 +345,11 @@ void launch_v(const NodeRec *rec, const SweepArgs &a, int grid, OcclPartial *par
 
 SweepVariant occl_variant(int v) { return kOccl[v]; }
 
-int occl_grid(int) { return kMaxPartials; }
+int occl_grid(int v, int64_t n_units, int64_t n_nodes) {
+    int64_t g = std::min<int64_t>(n_units, kMaxPartials);
+    if (kOccl[v].col_shift > 0 && n_nodes >= kTwoUnitNodes) g = (g + 1) / 2;
+    return (int)g;
+}
 
 hipError_t launch_occl_sweep(int v, const NodeRec *rec, const SweepArgs &a, int grid,
                              OcclPartial *part, hipStream_t st) {

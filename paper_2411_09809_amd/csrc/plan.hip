@@ -77,10 +77,10 @@ void load_locked(const char *path) {
 // 3M edges); the pruned
 // sweep takes the 1-row tiles (tightest boxes) below 2^17 edges and 2-row
 // tiles above.  The node sweep of a single layout splits its 256-column
-// chunks below 2^15 nodes, for units enough to fill the chip: 2 rows per
+// chunks below 2^16 nodes, for units enough to fill the chip: 2 rows per
 // thread and 32 columns below 2^13 nodes, 4 rows at 8 waves per SIMD and 32
-// columns below 2^14, the same with 64 columns below 2^15, and whole chunks
-// at 4 rows and 8 waves from there.  A batch has units enough in any case
+// columns below 2^14, the same with 64 columns below 2^16 (two units per
+// block from 2^15), and whole chunks at 4 rows and 8 waves from there.  A batch has units enough in any case
 // and keeps 4-row tiles at 8 waves up to a mean of 2^19 nodes per layout.
 int default_variant(int k, int b, int c) {
     if (k == 3 && c >= 17) return 1;
@@ -89,7 +89,7 @@ int default_variant(int k, int b, int c) {
         if (b) return c >= 19 ? 0 : 9;
         if (c <= 12) return 6;
         if (c == 13) return 11;
-        if (c == 14) return 10;
+        if (c == 14 || c == 15) return 10;
         return 9;
     }
     return kDefault[k];

@@ -242,7 +242,14 @@ int64_t sweep_units(int64_t n_items, int rows, int col_shift = 0);
 // Largest grid (blocks) of a sweep variant; a launch uses min(units, this),
 // one equal contiguous range of the unit list per block.
 int cross_grid(int variant, bool angle);
-int occl_grid(int variant);
+// Grid of a single layout's node sweep over n_units units: one unit per
+// block (up to the partial slots), but two consecutive units per block for
+// the split-chunk variants from kTwoUnitNodes nodes, where the units far
+// outnumber the chip's block slots: the block's start-up (position, row
+// loads) then serves two units, and the second unit's chunk is fetched while
+// the first is swept.
+constexpr int64_t kTwoUnitNodes = 1ll << 15;
+int occl_grid(int variant, int64_t n_units, int64_t n_nodes);
 
 // ------------------------------------------------------------------ launches
 // Every launcher enqueues on `st` and returns the launch status.

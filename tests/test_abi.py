@@ -154,7 +154,7 @@ def test_built_in_tuning_defaults(L, tmp_path):
     sweeps 2 rows / 7 waves, but 3 rows / 5 waves for the crossing + angle
     sweep of a single layout from 2^21 edges; the node sweep of a single layout
     2 rows / 8 waves in chunks split 8 ways below 2^13 nodes, 4 rows / 8 waves
-    split 8 ways below 2^14 and 4 ways below 2^15, 4 rows / 8 waves in whole
+    split 8 ways below 2^14 and 4 ways below 2^16, 4 rows / 8 waves in whole
     chunks from there (a batch: 4 rows / 8 waves, whole chunks, below a mean
     of 2^19 nodes); the pruned sweep 1-row tiles below 2^17 edges and 2-row
     tiles from there."""
@@ -175,8 +175,9 @@ def test_built_in_tuning_defaults(L, tmp_path):
     assert q(1, 1 << 21) == (3, 5) and q(1, 3_000_000) == (3, 5)
     assert q(2, 1_000) == (2, 8, 8) and q(2, (1 << 13) - 1) == (2, 8, 8)
     assert q(2, 1 << 13) == (4, 8, 8) and q(2, 20_000) == (4, 8, 4)
-    assert q(2, (1 << 15) - 1) == (4, 8, 4) and q(2, 1 << 15) == (4, 8, 1)
-    assert q(2, 50_000) == (4, 8, 1) and q(2, 1_000_000) == (4, 8, 1)
+    assert q(2, (1 << 15) - 1) == (4, 8, 4) and q(2, 50_000) == (4, 8, 4)
+    assert q(2, (1 << 16) - 1) == (4, 8, 4) and q(2, 1 << 16) == (4, 8, 1)
+    assert q(2, 1_000_000) == (4, 8, 1)
     assert q(2, 50_000, batch=1) == (4, 8, 1) and q(2, 1 << 19, batch=1) == (8, 5, 1)
     assert q(3, (1 << 17) - 1) == (1, 8) and q(3, 1 << 17) == (2, 7)
 

@@ -255,11 +255,13 @@ def test_every_node_sweep_variant_on_ragged_sizes(torch_mod, d, tmp_path):
     sweep counts a tile's own square as ordered pairs less its self pairs and
     halves the total: that must hold with padding rows and columns, at
     diameter 0 (no pair occludes, not even a node with itself), at 1 (only
-    coincident nodes) and at 6 on a crowded 40 x 40 canvas (Algorithm 1)."""
+    coincident nodes) and at 6 on a crowded 40 x 40 canvas (Algorithm 1).
+    From 2^15 nodes the split variants of a single layout take two units per
+    block (32768 and 40961 nodes)."""
     from paper_2411_09809_amd import _lib, metrics
     from paper_2411_09809_amd.batch import Batch
     lib = _lib.lib()
-    sizes = [1, 2, 3, 31, 255, 256, 257, 1023, 1025, 2049, 4100]
+    sizes = [1, 2, 3, 31, 255, 256, 257, 1023, 1025, 2049, 4100, 32768, 40961]
     layouts = [gen.uniform_layout(n, 0, extent=40, diameter=d, seed=n) for n in sizes]
     want = [oracle.node_occlusion(L.x, L.y, d) for L in layouts]
     devs = [metrics.DeviceLayout.from_host(L) for L in layouts]

@@ -65,6 +65,23 @@ def test_shards_sum_to_whole(torch_mod, n_shards):
         assert all(p[3] > p[2] for p in parts)
 
 
+@pytest.mark.parametrize("n_shards", [1, 3, 64])
+def test_node_shards_with_two_units_per_block(torch_mod, n_shards):
+    """At 40,000 nodes the default node sweep splits chunks 4 ways and takes
+    two units per block: shards still cover every row once, sum to the whole
+    and match the oracle's row slices."""
+    from paper_2411_09809_amd import metrics
+    L = gen.uniform_layout(40000, 0, extent=1 << 12, diameter=9.0, seed=23)
+    D = metrics.DeviceLayout.from_host(L)
+    occ = metrics.node_occlusion(D.x, D.y, 9.0)
+    assert occ == oracle.node_occlusion(L.x, L.y, 9.0)
+    parts = [metrics.node_occlusion_shard(D.x, D.y, 9.0, k, n_shards) for k in range(n_shards)]
+    _check_cover([(p[1], p[2]) for p in parts], L.n_nodes)
+    assert sum(p[0] for p in parts) == occ
+    for o, q0, q1 in parts[:2] + parts[-1:]:
+        assert o == oracle.node_occlusion_rows(L.x, L.y, 9.0, q0, q1)
+
+
 def test_shards_match_oracle_rows(torch_mod):
     from paper_2411_09809_amd import metrics
     L = gen.uniform_layout(6000, 15000, extent=1 << 11, seed=22)
