@@ -151,7 +151,7 @@ rb_status rb_crossing_angle_noalloc(const float *x, const float *y, int64_t n_no
  * rb_node_occlusion_grid: N_c as rb_node_occlusion, by the grid method of
  *   Section 3.2.1 (cells of side >= d; each node meets the nodes of its own
  *   and four neighbour cells).  Work is O(|V| log |V| + candidate pairs).
- *   Below 2^15 nodes it runs the all-pairs sweep of rb_node_occlusion
+ *   Below 2^16 nodes it runs the all-pairs sweep of rb_node_occlusion
  *   instead (the grid's sort and count passes cost more there); the count
  *   is the same either way.
  * rb_crossing_angle_pruned: E_ca, E_c and the deviation sum as

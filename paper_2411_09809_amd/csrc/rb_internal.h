@@ -172,9 +172,9 @@ struct GridWs {
 // largest edge count of the pruned edge sweep (its unit list is indexed in 32 bits)
 constexpr int64_t kMaxPrunedEdges = 1ll << 24;
 // below this many nodes the grid occlusion call runs the all-pairs sweep: its
-// sort and count passes cost about 0.1 ms whatever the size, more than the
-// sweep of 2^15 nodes
-constexpr int64_t kGridMinNodes = 1ll << 15;
+// sort and count passes cost 0.13-0.14 ms up to about 65,000 nodes, where
+// the sweep costs as much (50,000 nodes: 0.09 ms)
+constexpr int64_t kGridMinNodes = 1ll << 16;
 bool grid_ws_layout(int64_t n_nodes, int64_t n_edges, GridWs *G);
 
 // Small device scalars used between kernels of one call.

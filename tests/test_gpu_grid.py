@@ -4,7 +4,7 @@ rb_node_occlusion_grid must return the brute-force N_c bit for bit: on
 closed-form lattices, coincident nodes, the full range of diameters (zero,
 sub-unit, exact integer thresholds, larger than the layout), crowded and
 negative-coordinate layouts, and the full-size workloads up to the
-1,000,000-node power-law layout.  Below 2^15 nodes the call runs the
+1,000,000-node power-law layout.  Below 2^16 nodes the call runs the
 all-pairs sweep; the small cases are also run with a lattice of far filler
 nodes added (same count), which takes them through the grid kernels.
 """
@@ -38,23 +38,21 @@ def dev_xy(torch, x, y):
     return t(x), t(y)
 
 
-GRID_MIN_NODES = 1 << 15      # below this the grid call runs the all-pairs sweep
-FILL_SIDE = 182               # 182^2 >= 2^15 filler nodes
+GRID_MIN_NODES = 1 << 16      # below this the grid call runs the all-pairs sweep
 
 
 def with_fillers(xs, ys, d):
-    """The layout plus a lattice of 182^2 filler nodes beside it, spaced at
-    least d apart and at least d from every node: the same occlusion count,
-    and enough nodes for the grid call to take the grid route.  None when
-    the lattice does not fit in [-2^20, 2^20]."""
+    """The layout plus a lattice of at least 2^16 filler nodes beside it,
+    spaced at least d apart and at least d from every node: the same
+    occlusion count, and enough nodes for the grid call to take the grid
+    route.  The lattice runs up from y = -2^20 (up to 1024 rows, fewer for a
+    wide spacing) and as many columns as that needs.  None when it does not
+    fit in [-2^20, 2^20]."""
     xs, ys = np.asarray(xs, dtype=np.int64), np.asarray(ys, dtype=np.int64)
     s = max(1, int(np.ceil(d)))
-    span = (FILL_SIDE - 1) * s
-    lo_y = int(ys.min()) if ys.size else 0
-    if lo_y + span > 1 << 20:
-        lo_y = (1 << 20) - span
-    if lo_y < -(1 << 20):
-        return None
+    rows = min(1024, (1 << 21) // s + 1)
+    cols = -(-GRID_MIN_NODES // rows)
+    span = (cols - 1) * s
     hi_x = int(xs.max()) if xs.size else 0
     lo_x = int(xs.min()) if xs.size else 0
     if hi_x + s + span <= 1 << 20:
@@ -63,12 +61,12 @@ def with_fillers(xs, ys, d):
         x0 = lo_x - s - span
     else:
         return None
-    gx, gy = np.meshgrid(np.arange(FILL_SIDE) * s + x0, np.arange(FILL_SIDE) * s + lo_y)
+    gx, gy = np.meshgrid(np.arange(cols) * s + x0, np.arange(rows) * s - (1 << 20))
     return (np.concatenate([xs, gx.ravel()]), np.concatenate([ys, gy.ravel()]))
 
 
 def grid_count(torch, xs, ys, d):
-    """rb_node_occlusion_grid on the layout (below 2^15 nodes: the sweep
+    """rb_node_occlusion_grid on the layout (below 2^16 nodes: the sweep
     route) and, where the fillers fit, on the layout with fillers (the grid
     route); both must agree."""
     from paper_2411_09809_amd import metrics
